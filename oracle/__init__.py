@@ -1,0 +1,215 @@
+"""CPU oracle for the GP-WENO FD-Prim scheme.
+
+TEST INFRASTRUCTURE ONLY. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import or run anything in this package;
+the product library never does, and the two share no code.
+
+Pieces:
+  * :mod:`oracle.tables` -- pre-simulation GP tables in 60-digit arithmetic (mpmath);
+  * ``gpweno_oracle.c``  -- the scheme in plain float64 C (built into ``liboracle.so``);
+  * this module          -- ctypes loader and a small ``OracleSolver`` wrapper.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+from .tables import gp_tables  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gpweno_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-std=c11"]
+
+
+def build(force: bool = True) -> str:
+    """Compile ``liboracle.so`` next to its source with gcc."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Cfg(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int),
+        ("n", ctypes.c_int * 3),
+        ("dx", ctypes.c_double * 3),
+        ("R", ctypes.c_int),
+        ("gamma", ctypes.c_double),
+        ("positivity_fallback", ctypes.c_int),
+        ("wp", ctypes.c_double * 48),
+        ("wm", ctypes.c_double * 48),
+        ("gp", ctypes.c_double * 12),
+        ("gm", ctypes.c_double * 12),
+        ("P", ctypes.c_double * 48),
+    ]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        L.oracle_cfg_size.restype = ctypes.c_size_t
+        assert L.oracle_cfg_size() == ctypes.sizeof(Cfg), "oracle_cfg layout mismatch"
+        L.oracle_rhs.restype = ctypes.c_long
+        L.oracle_rhs.argtypes = [ctypes.POINTER(Cfg), _dp, _dp]
+        L.oracle_max_speed.restype = ctypes.c_double
+        L.oracle_max_speed.argtypes = [ctypes.POINTER(Cfg), _dp]
+        L.oracle_dt.restype = ctypes.c_double
+        L.oracle_dt.argtypes = [ctypes.POINTER(Cfg), _dp, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.oracle_step_dt.restype = ctypes.c_long
+        L.oracle_step_dt.argtypes = [ctypes.POINTER(Cfg), _dp, ctypes.c_double]
+        L.oracle_run.restype = ctypes.c_long
+        L.oracle_run.argtypes = [ctypes.POINTER(Cfg), _dp, ctypes.c_double, ctypes.c_double, ctypes.c_long,
+                                 _dp, ctypes.POINTER(ctypes.c_long)]
+        L.oracle_run_fixed.restype = ctypes.c_long
+        L.oracle_run_fixed.argtypes = [ctypes.POINTER(Cfg), _dp, ctypes.c_double, ctypes.c_long]
+        L.oracle_gp_weno.restype = None
+        L.oracle_gp_weno.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_hllc.restype = None
+        L.oracle_hllc.argtypes = [_dp, _dp, ctypes.c_double, _dp]
+        L.oracle_flux_hat.restype = ctypes.c_double
+        L.oracle_flux_hat.argtypes = [_dp]
+        L.oracle_char_vectors.restype = None
+        L.oracle_char_vectors.argtypes = [_dp, ctypes.c_double, _dp, _dp]
+        L.oracle_rk3_combine.restype = None
+        L.oracle_rk3_combine.argtypes = [ctypes.c_int, ctypes.c_size_t, _dp, _dp, _dp, ctypes.c_double, _dp]
+        L.oracle_cons_to_prim.restype = None
+        L.oracle_cons_to_prim.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_dp)
+
+
+# ----------------------------------------------------------------------------
+# Thin wrappers over the per-step building blocks (used by the pin tests).
+# ----------------------------------------------------------------------------
+def gp_weno(f, tab):
+    """GP-WENO interpolation of one variable; ``f`` has 2R+1 entries.
+    Returns (q+, q-, beta, omega+, omega-)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    R = (len(f) - 1) // 2
+    qp = ctypes.c_double()
+    qm = ctypes.c_double()
+    beta = np.zeros(4)
+    omp = np.zeros(4)
+    omm = np.zeros(4)
+    arrs = [np.ascontiguousarray(tab[k], dtype=np.float64) for k in ("w+", "w-", "gamma+", "gamma-", "P")]
+    lib().oracle_gp_weno(R, _ptr(f), *[_ptr(a) for a in arrs], ctypes.byref(qp), ctypes.byref(qm),
+                         _ptr(beta), _ptr(omp), _ptr(omm))
+    return qp.value, qm.value, beta[: R + 1], omp[: R + 1], omm[: R + 1]
+
+
+def hllc(qL, qR, gamma):
+    """HLLC flux in the rotated frame; q = (rho, u_n, u_t1, u_t2, p)."""
+    qL = np.ascontiguousarray(qL, dtype=np.float64)
+    qR = np.ascontiguousarray(qR, dtype=np.float64)
+    F = np.zeros(5)
+    lib().oracle_hllc(_ptr(qL), _ptr(qR), gamma, _ptr(F))
+    return F
+
+
+def flux_hat(F5):
+    F5 = np.ascontiguousarray(F5, dtype=np.float64)
+    return lib().oracle_flux_hat(_ptr(F5))
+
+
+def char_vectors(q, gamma):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    L = np.zeros((5, 5))
+    Rm = np.zeros((5, 5))
+    lib().oracle_char_vectors(_ptr(q), gamma, _ptr(L), _ptr(Rm))
+    return L, Rm  # rows l_k, and Rm[k] = r_k
+
+
+def rk3_combine(stage, Un, Uin, L, dt):
+    Un, Uin, L = (np.ascontiguousarray(a, dtype=np.float64) for a in (Un, Uin, L))
+    out = np.empty_like(Un)
+    lib().oracle_rk3_combine(stage, Un.size, _ptr(Un), _ptr(Uin), _ptr(L), dt, _ptr(out))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# Whole-scheme driver.
+# ----------------------------------------------------------------------------
+class OracleSolver:
+    """FP64 CPU reference solver. ``ell`` and ``sigma`` are physical lengths."""
+
+    def __init__(self, grid, R, ell, sigma, gamma=1.4, cfl=0.4, positivity_fallback=False):
+        self.grid = grid
+        self.R = R
+        self.cfl = cfl
+        c = Cfg()
+        c.ndim = grid.ndim
+        for d in range(3):
+            c.n[d] = grid.n[d] if d < grid.ndim else 1
+            c.dx[d] = grid.dx[d] if d < grid.ndim else 1.0
+        c.R = R
+        c.gamma = gamma
+        c.positivity_fallback = 1 if positivity_fallback else 0
+        self.tables = []
+        for d in range(grid.ndim):
+            t = gp_tables(R, ell / grid.dx[d], sigma / grid.dx[d])
+            self.tables.append(t)
+            for m in range(4):
+                c.gp[4 * d + m] = t["gamma+"][m]
+                c.gm[4 * d + m] = t["gamma-"][m]
+                for j in range(4):
+                    c.wp[16 * d + 4 * m + j] = t["w+"][m, j]
+                    c.wm[16 * d + 4 * m + j] = t["w-"][m, j]
+                    c.P[16 * d + 4 * m + j] = t["P"][m, j]
+        self.cfg = c
+        self.fallbacks = 0
+
+    def _check(self, U):
+        assert U.dtype == np.float64 and U.flags["C_CONTIGUOUS"]
+        assert U.size == self.grid.nv * self.grid.ncells
+
+    def rhs(self, U):
+        self._check(U)
+        L = np.empty_like(U)
+        self.fallbacks += lib().oracle_rhs(ctypes.byref(self.cfg), _ptr(U), _ptr(L))
+        return L
+
+    def max_speed(self, U):
+        self._check(U)
+        return lib().oracle_max_speed(ctypes.byref(self.cfg), _ptr(U))
+
+    def dt(self, U, t, t_final):
+        return lib().oracle_dt(ctypes.byref(self.cfg), _ptr(U), self.cfl, t, t_final)
+
+    def step(self, U, dt):
+        """One SSP-RK3 step of size dt, in place."""
+        self._check(U)
+        self.fallbacks += lib().oracle_step_dt(ctypes.byref(self.cfg), _ptr(U), dt)
+        return U
+
+    def run(self, U, t_final, max_steps=-1, t0=0.0):
+        """CFL-limited run to t_final (in place). Returns (t, nsteps)."""
+        self._check(U)
+        t = ctypes.c_double(t0)
+        n = ctypes.c_long(0)
+        self.fallbacks += lib().oracle_run(ctypes.byref(self.cfg), _ptr(U), self.cfl, t_final, max_steps,
+                                           ctypes.byref(t), ctypes.byref(n))
+        return t.value, n.value
+
+    def run_fixed(self, U, dt, nsteps):
+        self._check(U)
+        self.fallbacks += lib().oracle_run_fixed(ctypes.byref(self.cfg), _ptr(U), dt, nsteps)
+        return U
