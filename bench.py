@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Benchmark of the GP-WENO FD-Prim hot path on one MI355X.
+
+A step is one SSP-RK3 step (CFL time step, three stages, each stage one fused
+sweep per direction) of the whole grid. Default workload: the 2D isentropic
+vortex, 512 x 512 periodic cells on [-5,5]^2, vortex strength 5, gamma = 1.4,
+GP-R2 with ell = 12 dx, sigma = 3 dx, CFL 0.4, one period t = 10.
+
+Reported (one JSON line):
+  value       cell-updates/s per RK stage of the float32-sweep path (float64 state)
+  fp64        the same for the all-float64 path
+  accuracy    relative L1 of both paths against the float64 CPU oracle after the
+              oracle's sample steps, and density L1 against the exact solution
+              after full solves to t = 10
+  latency     p50/p99 time-to-solution of full solves (upload, run to t = 10, download)
+  roofline    the dominant sweep kernel, timed with HIP events on its stream
+  cpu_baseline the CPU oracle timed on a bounded sample of the same workload
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import inputs  # noqa: E402
+
+METRIC = "cell-updates/sec per RK stage (FP32 vs FP64 at stated L1 err); p50/p99 solve latency"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X published vector peaks
+KERNEL_SRC = os.path.join(ROOT, "paper_1808_04960_amd", "csrc", "gpweno_kernels.hip")
+
+
+def flops_per_cell_sweep(ndim: int, R: int) -> int:
+    """Algorithmic flops of one cell in one direction's sweep (FMA = 2, divide and
+    square root = 1), counted from the per-cell formulas:
+      cons->prim 3*ndim+3, eigen quantities 8, projection 6n (n = 2R+1),
+      GP-WENO per field (R+1)^2 (2R+3) + 2(R+1)(2R+1) + 11(R+1) + 2,
+      back-projection 14, HLLC 53 + 9(ndim-1) + 3 nv, correction and difference 16 nv."""
+    nv = 2 + ndim
+    n = 2 * R + 1
+    weno = (R + 1) ** 2 * (2 * R + 3) + 2 * (R + 1) * (2 * R + 1) + 11 * (R + 1) + 2
+    hllc = 53 + 9 * (ndim - 1) + 3 * nv
+    return (3 * ndim + 3) + 8 + 6 * n + nv * weno + 14 + hllc + 16 * nv
+
+
+WORKLOADS = {
+    "vortex2d": dict(desc="2D isentropic vortex, 512x512 periodic on [-5,5]^2, strength 5, gamma 1.4, "
+                          "GP-R2 (ell=12dx, sigma=3dx), SSP-RK3 CFL 0.4, t=10",
+                     make=lambda: inputs.isentropic_vortex_2d(512), R=2, t_final=10.0),
+    "sine1d": dict(desc="1D sine density wave, N=128 periodic on [0,1], GP-R2, CFL 0.4, t=1",
+                   make=lambda: inputs.sine_wave_1d(128), R=2, t_final=1.0),
+    "kh2d": dict(desc="2D Kelvin-Helmholtz, 2048x1024 periodic on [0,2]x[0,1], GP-R3, CFL 0.4",
+                 make=lambda: inputs.kelvin_helmholtz_2d(2048, 1024), R=3, t_final=None),
+    "wave3d": dict(desc="3D density wave, 256^3 periodic on [0,1]^3, GP-R2, CFL 0.4",
+                   make=lambda: inputs.density_wave_3d(256), R=2, t_final=None),
+    "vortex3d": dict(desc="3D isentropic vortex (w=0), 256^3 periodic on [-5,5]^3, GP-R2, CFL 0.4",
+                     make=lambda: inputs.isentropic_vortex_3d(256), R=2, t_final=None),
+}
+
+
+def traffic_from_profiles(kernel_name):
+    """HBM bytes per launch of the kernel from a committed rocprofv3 counter summary,
+    valid only while the kernel source is unchanged (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.txt")
+    if not os.path.exists(path):
+        return None
+    with open(KERNEL_SRC, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+    entries = {}
+    with open(path) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            parts = line.split()
+            if len(parts) >= 4:
+                entries[(parts[0], parts[1])] = float(parts[2]) + float(parts[3])
+    return entries.get((kernel_name, sha))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="vortex2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--solves", type=int, default=5, help="full solves for latency and exact-solution error")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle sample budget")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the design of one is "
+              "described in DESIGN.md); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1808_04960_amd as gw
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    W = WORKLOADS[args.workload]
+    grid, U0 = W["make"]()
+    R = W["R"]
+    dx = grid.dx[0]
+    ncell = grid.ncells
+    t_final = W["t_final"]
+    t_run = 1e9  # timing runs never reach their end time
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    solvers = {}
+    timing = {}
+    for prec in ("fp32", "fp64"):
+        s = gw.Solver(grid, R, 12 * dx, 3 * dx, precision=prec, U0=U0)
+        solvers[prec] = s
+        s.run(t_run, max_steps=args.warmup)
+        s.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n, _ = s.run(t_run, max_steps=args.steps)
+        s.synchronize()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        assert n == args.steps
+        timing[prec] = el
+        log(f"{prec}: {args.steps} steps in {el * 1e3:.2f} ms -> {ncell * 3 * args.steps / el:.4e} cell-updates/s")
+
+    # dominant kernel: one direction's sweep, timed with HIP events on the solver's stream
+    kern = {}
+    for prec in ("fp32", "fp64"):
+        s = solvers[prec]
+        s.set_state(U0)
+        L = torch.empty_like(s.state)
+        for d in range(grid.ndim):
+            for _ in range(3):
+                s.rhs_dir_device(d, s.state, L)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s.stream)
+            for _ in range(args.kernel_reps):
+                s.rhs_dir_device(d, s.state, L)
+            e1.record(s.stream)
+            e1.synchronize()
+            kern[(prec, d)] = e0.elapsed_time(e1) / args.kernel_reps * 1e-3
+            log(f"{prec} sweep dir {d}: {kern[(prec, d)] * 1e6:.1f} us per launch")
+
+    if args.copy_probe:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nbytes} bytes read + {nbytes} bytes written per launch")
+
+    # accuracy and latency: full solves
+    acc = {}
+    lat = []
+    if t_final is not None:
+        rho_exact = U0[0]
+        for prec in ("fp32", "fp64"):
+            s = solvers[prec]
+            reps = args.solves if prec == "fp32" else 1
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s.set_state(U0)
+                n, t = s.run(t_final)
+                Ug = s.get_state()
+                el = time.perf_counter() - t0
+                if prec == "fp32":
+                    lat.append(el)
+            acc[f"{prec}_density_l1_vs_exact"] = float(np.mean(np.abs(Ug[0] - rho_exact)))
+            acc[f"{prec}_steps_to_t_final"] = int(n)
+            log(f"{prec}: solve to t={t:.3f} in {n} steps, density L1 vs exact "
+                f"{acc[f'{prec}_density_l1_vs_exact']:.3e}")
+
+    # CPU oracle: bounded sample of the same workload, then parity of both GPU paths
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        o = oracle.OracleSolver(grid, R, 12 * dx, 3 * dx)
+        Uo = U0.copy()
+        t0 = time.perf_counter()
+        steps = 0
+        t_o = 0.0
+        while True:
+            t_o, n1 = o.run(Uo, t_run, max_steps=1, t0=t_o)
+            steps += n1
+            el = time.perf_counter() - t0
+            if el >= args.cpu_seconds or el * (steps + 1) / steps > 30.0:
+                break
+        cpu = {"value": ncell * 3 * steps / el, "unit": "cell-updates/s", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": f"first {steps} SSP-RK3 steps of the same workload from t=0 ({el:.1f} s, float64)"}
+        log(f"oracle: {steps} steps in {el:.1f} s on {oracle.threads()} threads")
+        for prec in ("fp32", "fp64"):
+            s = solvers[prec]
+            s.set_state(U0)
+            s.run(t_run, max_steps=steps)
+            Ug = s.get_state()
+            acc[f"{prec}_rel_l1_vs_oracle"] = float(np.abs(Ug - Uo).sum() / np.abs(Uo).sum())
+        acc["oracle_steps_compared"] = steps
+
+    cu32 = ncell * 3 * args.steps / timing["fp32"]
+    cu64 = ncell * 3 * args.steps / timing["fp64"]
+    dom_dir = max(range(grid.ndim), key=lambda d: kern[("fp32", d)])
+    t_k = kern[("fp32", dom_dir)]
+    fl = flops_per_cell_sweep(grid.ndim, R) * ncell
+    achieved = fl / t_k / 1e12
+    name = f"sweep_kernel<{grid.ndim},{dom_dir},{R},float>"
+    traffic = traffic_from_profiles(name)
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS["fp32"], "traffic": traffic, "kernel": name,
+            "avg_launch_us": t_k * 1e6, "flops_per_launch": fl,
+            "fp64": {"kernel": f"sweep_kernel<{grid.ndim},{dom_dir},{R},double>",
+                     "avg_launch_us": kern[("fp64", dom_dir)] * 1e6,
+                     "achieved": fl / kern[("fp64", dom_dir)] / 1e12, "peak": PEAK_TFLOPS["fp64"],
+                     "frac": fl / kern[("fp64", dom_dir)] / 1e12 / PEAK_TFLOPS["fp64"]}}
+    out = {
+        "metric": METRIC,
+        "value": cu32,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": timing["fp32"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": W["desc"], "grid": list(grid.n[: grid.ndim]), "R": R,
+                   "arithmetic": "float32 sweep, float64 state/dt/RK/sums"},
+        "fp64": {"value": cu64, "ms_per_step": timing["fp64"] / args.steps * 1e3, "dtype": "f64"},
+        "accuracy": acc,
+        "latency": ({"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                     "solves": len(lat), "what": "upload + run to t_final + download, fp32 path"} if lat else None),
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

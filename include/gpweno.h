@@ -1,0 +1,176 @@
+/*
+ * gpweno.h -- C ABI of libgpweno: the GP-WENO finite-difference (FD-Prim)
+ * scheme for the compressible Euler equations on static uniform periodic grids,
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Method (Reyes, Lee, Graziani, Tzeferacos, "A variable high-order
+ * shock-capturing finite difference method with GP-WENO"):
+ *   - point values of the conserved variables U = (rho, rho u[, rho v[, rho w]], E)
+ *     (Sec. 2, Eq. (euler)) are advanced by the conservative difference of
+ *     numerical fluxes, Eq. (disc_fd);
+ *   - Riemann states at the faces x_{i+-1/2} are interpolated per direction by
+ *     GP-WENO on characteristic variables (Sec. 3.2-3.3, Sec. 4 step 2, Sec. 7);
+ *   - face fluxes come from an HLLC Riemann solver (Eq. (riemann_prob)) and are
+ *     corrected to high order with alpha = -1/24, beta = 3/640
+ *     (Eqs. (numFlux_cor), (FD-ders));
+ *   - time integration is third-order SSP (TVD) Runge-Kutta.
+ *
+ * Conventions shared by every entry point
+ *   - Status: every function returns an int, GPWENO_OK (0) on success or a
+ *     negative gpweno_status. Nothing is printed, nothing exits; the text of the
+ *     last failure is available from gpweno_last_error().
+ *   - Units: ell and sigma are physical lengths (pass 12*dx and 3*dx for the
+ *     paper's usual ell/dx = 12, sigma/dx = 3, Sec. 3.4). gamma is the ratio of
+ *     specific heats (not the paper's linear weights).
+ *   - State layout: float64, structure of arrays [nv][nz][ny][nx], x fastest,
+ *     nv = 2 + ndim, conserved variables in the order (rho, rho u, rho v, rho w, E)
+ *     restricted to the grid's dimension. Values are point values at cell centres
+ *     x_i = lo + (i + 1/2) dx.
+ *   - Ownership: the caller allocates and owns the device state and the device
+ *     workspace (any allocator, e.g. PyTorch); the library never frees them.
+ *     A context owns only its small control block and host-side tables.
+ *   - Streams: work is enqueued on the context's stream (gpweno_options.stream,
+ *     a hipStream_t; NULL means the default stream). Calls documented as
+ *     blocking synchronise that stream; the others return after enqueueing.
+ *   - Threads: a context is used by one host thread at a time.
+ */
+#ifndef GPWENO_H
+#define GPWENO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GPWENO_OK = 0,
+    GPWENO_EINVAL = -1,    /* invalid argument */
+    GPWENO_ENOMEM = -2,    /* allocation failed */
+    GPWENO_EHIP = -3,      /* a HIP runtime call failed */
+    GPWENO_ENONPHYS = -4,  /* a non-physical state (rho <= 0, p <= 0 or NaN) was produced */
+    GPWENO_ESTATE = -5     /* call not valid in the context's current state (e.g. not bound) */
+} gpweno_status;
+
+typedef enum {
+    GPWENO_FP64 = 0,       /* all arithmetic in float64 */
+    GPWENO_FP32 = 1        /* sweep arithmetic in float32; state, flux differences,
+                              RK combination, dt and conservation sums in float64 */
+} gpweno_precision;
+
+/* Uniform periodic grid. Axes beyond ndim are ignored. */
+typedef struct {
+    int ndim;              /* 1, 2 or 3 */
+    int n[3];              /* cells per axis */
+    double lo[3];          /* domain lower corner */
+    double hi[3];          /* domain upper corner */
+} gpweno_grid;
+
+typedef struct {
+    int precision;         /* gpweno_precision */
+    double cfl;            /* CFL number of the time-step rule (default 0.4) */
+    double fixed_dt;       /* > 0: use this time step instead of the CFL rule */
+    int positivity_fallback; /* 1: a Riemann state with rho <= 0 or p <= 0 is replaced
+                                by the cell-centre state (default 0) */
+    void *stream;          /* hipStream_t, NULL = default stream */
+} gpweno_options;
+
+typedef struct gpweno_ctx gpweno_ctx;
+
+/* Pre-simulation step (Sec. 4 step 1): builds the GP weights w_m at x_{i+-1/2}
+ * (Eqs. (kmat), (kstar), (q-intrp)), the linear weights gamma_m as the
+ * least-squares solution of Eq. (gamm-system) with M of Eq. (M-mat), and the
+ * eigen-projections P_i = v_i / sqrt(lambda_i) of K_m(sigma) (Eq. (beta-eigen)),
+ * in binary128 and rounded to float64, for every direction.
+ * grid: host pointer, copied. R: stencil radius, 1..3. ell, sigma: physical
+ * length scales, sigma > dx on every axis (Sec. 3.4: sigma <= dx is unstable).
+ * gamma: ratio of specific heats, > 1. Every axis needs n >= 2. On success *out
+ * receives a context with default options; the device in use is the current
+ * HIP device. Errors: EINVAL for invalid arguments, ENOMEM/EHIP on allocation.
+ * Host-side work plus one small device allocation (the control block). */
+int gpweno_init(const gpweno_grid *grid, int R, double ell, double sigma, double gamma,
+                gpweno_ctx **out);
+
+/* Options (host pointer, copied). Changing the precision or positivity flag
+ * drops any captured graph. Errors: EINVAL. */
+int gpweno_set_options(gpweno_ctx *ctx, const gpweno_options *opt);
+int gpweno_get_options(const gpweno_ctx *ctx, gpweno_options *opt);
+
+/* Number of float64 values in the state: nv * ncells. */
+size_t gpweno_state_count(const gpweno_ctx *ctx);
+
+/* Bytes of device workspace gpweno_bind needs (two RK stage states, the
+ * direction accumulator and reduction partials), 256-byte aligned. */
+size_t gpweno_workspace_bytes(const gpweno_ctx *ctx);
+
+/* Binds the caller's device state (float64, layout above, gpweno_state_count
+ * values) and workspace (gpweno_workspace_bytes bytes, 256-byte aligned). Both
+ * stay owned by the caller and must outlive the binding. Resets t and the step
+ * count to 0, and enqueues the CFL speed reduction of the current state (so the
+ * state must hold valid data before the first step; call gpweno_set_time after
+ * changing it). Errors: EINVAL for NULL or misaligned pointers. */
+int gpweno_bind(gpweno_ctx *ctx, double *d_state, void *d_workspace);
+
+/* Sets the simulation time and step count, and recomputes the CFL speed of the
+ * bound state (enqueued). Use after the caller rewrote the state. ESTATE if
+ * not bound. */
+int gpweno_set_time(gpweno_ctx *ctx, double t, long nsteps);
+
+/* One SSP-RK3 step (enqueued, asynchronous): dt = cfl / max_i sum_d (|u_d|+c)/dx_d
+ * from the state at the start of the step (or fixed_dt), clipped so that t does
+ * not pass t_final; no-op when t >= t_final. The state is updated in place.
+ * ESTATE if not bound. Failures inside the step are reported by the next
+ * blocking call (gpweno_get_time / gpweno_run) as ENONPHYS. */
+int gpweno_step(gpweno_ctx *ctx, double t_final);
+
+/* Advances until t >= t_final or max_steps more steps were taken (max_steps < 0:
+ * no limit). Blocking. Steps are replayed from captured HIP graphs. On return
+ * *nsteps_out (nullable) holds the steps taken by this call and *t_out (nullable)
+ * the time reached. Returns ENONPHYS if a stage produced rho <= 0, p <= 0 or a
+ * NaN (the state then holds the failing stage's output). */
+int gpweno_run(gpweno_ctx *ctx, double t_final, long max_steps, long *nsteps_out, double *t_out);
+
+/* Blocking: current time, the last step's dt, and the total step count
+ * (each nullable). Returns ENONPHYS if a non-physical state was detected. */
+int gpweno_get_time(gpweno_ctx *ctx, double *t, double *dt, long *nsteps);
+
+/* One evaluation of the right-hand side of Eq. (disc_fd) for an arbitrary device
+ * state d_U (same layout as the bound state), written to d_L (same size):
+ * L = -sum_d (fhat_{i+1/2} - fhat_{i-1/2}) / dx_d. Enqueued. Needs no bound
+ * state or workspace; d_U and d_L must not overlap. Errors: EINVAL. */
+int gpweno_rhs(gpweno_ctx *ctx, const double *d_U, double *d_L);
+
+/* One direction's term of the right-hand side of Eq. (disc_fd):
+ * -(fhat_{i+1/2} - fhat_{i-1/2}) / dx_dir for every cell, from the device state
+ * d_U, written to d_L (accumulate = 0) or added to d_L (accumulate = 1). This is
+ * exactly one launch of the direction's sweep kernel. dir < ndim. Enqueued.
+ * d_U and d_L must not overlap. Errors: EINVAL. */
+int gpweno_rhs_dir(gpweno_ctx *ctx, int dir, const double *d_U, double *d_L, int accumulate);
+
+/* Blocking: float64 sums over all cells of each conserved field of the bound
+ * state, written to host out[nv], by a deterministic device reduction. */
+int gpweno_conserved_sums(gpweno_ctx *ctx, double *out);
+
+/* Host-only (no device needed): the pre-simulation tables of gpweno_init for
+ * stencil radius R and length scales in units of dx (ell_over_dx, sigma_over_dx).
+ * Outputs are host arrays, row-major, padded to 4: w_plus[4][4], w_minus[4][4]
+ * (sub-stencil m = 0..R, node j = 0..R; sub-stencil m holds nodes m-R..m
+ * relative to the centre cell), gam_plus[4], gam_minus[4], P[4][4] (row i is
+ * v_i / sqrt(lambda_i)); any output may be NULL. Errors: EINVAL. */
+int gpweno_compute_tables(int R, double ell_over_dx, double sigma_over_dx,
+                          double *w_plus, double *w_minus, double *gam_plus,
+                          double *gam_minus, double *P);
+
+/* Text of the last failure on this context (ctx may be NULL for failures of
+ * gpweno_init and of calls given a NULL context). Never NULL. */
+const char *gpweno_last_error(const gpweno_ctx *ctx);
+
+/* Releases the context's own resources (not the caller's buffers). Synchronises
+ * the context's stream first. NULL is ignored. */
+void gpweno_destroy(gpweno_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPWENO_H */

@@ -86,10 +86,16 @@ def lib():
         L.oracle_char_vectors.argtypes = [_dp, ctypes.c_double, _dp, _dp]
         L.oracle_rk3_combine.restype = None
         L.oracle_rk3_combine.argtypes = [ctypes.c_int, ctypes.c_size_t, _dp, _dp, _dp, ctypes.c_double, _dp]
+        L.oracle_threads.restype = ctypes.c_int
         L.oracle_cons_to_prim.restype = None
         L.oracle_cons_to_prim.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp]
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads used by the oracle's pencil loops."""
+    return lib().oracle_threads()
 
 
 def _ptr(a: np.ndarray):

@@ -37,6 +37,9 @@
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fast-math).
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -469,6 +472,15 @@ long oracle_run_fixed(const oracle_cfg *c, double *U, double dt, long nsteps) {
     long fb = 0;
     for (long s = 0; s < nsteps; ++s) fb += oracle_step_dt(c, U, dt);
     return fb;
+}
+
+/* Number of OpenMP threads the oracle's parallel loops use. */
+int oracle_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Size of oracle_cfg, so the loader can check its mirror of the struct. */

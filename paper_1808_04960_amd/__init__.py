@@ -1,0 +1,237 @@
+"""Python binding of libgpweno (GP-WENO FD-Prim for the Euler equations on MI355X).
+
+Argument marshalling only: every step of the scheme runs in the HIP kernels of
+``libgpweno.so`` behind the C ABI declared in ``include/gpweno.h``. PyTorch is
+used for device memory and streams. There is no CPU fallback: if the library is
+not built, or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgpweno.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "gpweno.h")
+
+OK, EINVAL, ENOMEM, EHIP, ENONPHYS, ESTATE = 0, -1, -2, -3, -4, -5
+FP64, FP32 = 0, 1
+_STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", ENONPHYS: "ENONPHYS", ESTATE: "ESTATE"}
+
+
+class GpwenoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class NonPhysicalState(GpwenoError):
+    pass
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
+                ("hi", ctypes.c_double * 3)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("cfl", ctypes.c_double), ("fixed_dt", ctypes.c_double),
+                ("positivity_fallback", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    """Loads libgpweno.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise GpwenoError(ESTATE, f"{LIB_PATH} is not built; run `python -m paper_1808_04960_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        L.gpweno_init.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.POINTER(vp)]
+        L.gpweno_set_options.argtypes = [vp, ctypes.POINTER(_Options)]
+        L.gpweno_get_options.argtypes = [vp, ctypes.POINTER(_Options)]
+        L.gpweno_state_count.argtypes = [vp]
+        L.gpweno_state_count.restype = ctypes.c_size_t
+        L.gpweno_workspace_bytes.argtypes = [vp]
+        L.gpweno_workspace_bytes.restype = ctypes.c_size_t
+        L.gpweno_bind.argtypes = [vp, vp, vp]
+        L.gpweno_set_time.argtypes = [vp, ctypes.c_double, ctypes.c_long]
+        L.gpweno_step.argtypes = [vp, ctypes.c_double]
+        L.gpweno_run.argtypes = [vp, ctypes.c_double, ctypes.c_long, ctypes.POINTER(ctypes.c_long), _dp]
+        L.gpweno_get_time.argtypes = [vp, _dp, _dp, ctypes.POINTER(ctypes.c_long)]
+        L.gpweno_rhs.argtypes = [vp, vp, vp]
+        L.gpweno_rhs_dir.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int]
+        L.gpweno_conserved_sums.argtypes = [vp, _dp]
+        L.gpweno_compute_tables.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp, _dp]
+        L.gpweno_last_error.argtypes = [vp]
+        L.gpweno_last_error.restype = ctypes.c_char_p
+        L.gpweno_destroy.argtypes = [vp]
+        L.gpweno_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def declared_symbols():
+    """Names of the functions declared in include/gpweno.h."""
+    with open(HEADER_PATH) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"\b(gpweno_[a-z_0-9]+)\s*\(", text)))
+
+
+def _check(code, ctx=None):
+    if code != OK:
+        msg = lib().gpweno_last_error(ctx).decode()
+        if code == ENONPHYS:
+            raise NonPhysicalState(code, msg)
+        raise GpwenoError(code, msg)
+
+
+def compute_tables(R, ell_over_dx, sigma_over_dx):
+    """Host-only pre-simulation tables (binary128 arithmetic rounded to float64)."""
+    wp, wm, P = np.zeros((4, 4)), np.zeros((4, 4)), np.zeros((4, 4))
+    gp, gm = np.zeros(4), np.zeros(4)
+    ptr = lambda a: a.ctypes.data_as(_dp)  # noqa: E731
+    _check(lib().gpweno_compute_tables(R, ell_over_dx, sigma_over_dx, ptr(wp), ptr(wm), ptr(gp), ptr(gm), ptr(P)))
+    return {"w+": wp, "w-": wm, "gamma+": gp, "gamma-": gm, "P": P}
+
+
+def make_grid(grid):
+    """Any object with ndim, n, lo, hi (per axis) -> C grid struct."""
+    g = _Grid()
+    g.ndim = grid.ndim
+    for d in range(3):
+        g.n[d] = int(grid.n[d]) if d < grid.ndim else 1
+        g.lo[d] = float(grid.lo[d]) if d < grid.ndim else 0.0
+        g.hi[d] = float(grid.hi[d]) if d < grid.ndim else 1.0
+    return g
+
+
+class Solver:
+    """One GP-WENO problem resident on the GPU.
+
+    ``ell`` and ``sigma`` are physical lengths; ``precision`` is "fp64" or
+    "fp32" (float32 sweep arithmetic, float64 state). The state lives in a
+    float64 torch tensor of shape ``(nv, *grid.shape)`` owned by this object.
+    """
+
+    def __init__(self, grid, R, ell, sigma, gamma=1.4, precision="fp64", cfl=0.4, fixed_dt=0.0,
+                 positivity_fallback=False, U0=None, device=None, stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise GpwenoError(EHIP, "no GPU available (there is no CPU fallback)")
+        self._torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.grid = grid
+        self.R = R
+        self.nv = 2 + grid.ndim
+        self.shape = (self.nv,) + tuple(reversed([grid.n[d] for d in range(grid.ndim)]))
+        self._ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+            g = make_grid(grid)
+            _check(lib().gpweno_init(ctypes.byref(g), R, ell, sigma, gamma, ctypes.byref(self._ctx)))
+            count = lib().gpweno_state_count(self._ctx)
+            assert count == int(np.prod(self.shape))
+            self.state = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+            self.workspace = torch.empty(lib().gpweno_workspace_bytes(self._ctx), dtype=torch.uint8,
+                                         device=self.device)
+        self._bound = False
+        self.set_options(precision, cfl, fixed_dt, positivity_fallback)
+        if U0 is not None:
+            self.set_state(U0)
+
+    # -- configuration -------------------------------------------------------
+    def set_options(self, precision="fp64", cfl=0.4, fixed_dt=0.0, positivity_fallback=False):
+        o = _Options()
+        o.precision = {"fp64": FP64, "fp32": FP32}[precision]
+        o.cfl = cfl
+        o.fixed_dt = fixed_dt
+        o.positivity_fallback = 1 if positivity_fallback else 0
+        o.stream = self.stream.cuda_stream
+        self.precision = precision
+        _check(lib().gpweno_set_options(self._ctx, ctypes.byref(o)), self._ctx)
+
+    # -- state ---------------------------------------------------------------
+    def set_state(self, U, t=0.0, nsteps=0):
+        """Copies U (numpy or torch, float64, shape (nv, *grid.shape)) into the device state."""
+        torch = self._torch
+        src = torch.as_tensor(np.ascontiguousarray(U) if isinstance(U, np.ndarray) else U, dtype=torch.float64)
+        if tuple(src.shape) != self.shape:
+            raise GpwenoError(EINVAL, f"state shape {tuple(src.shape)} != {self.shape}")
+        torch.cuda.current_stream(self.device).synchronize()
+        with torch.cuda.stream(self.stream):
+            self.state.copy_(src)
+        if not self._bound:
+            _check(lib().gpweno_bind(self._ctx, ctypes.c_void_p(self.state.data_ptr()),
+                                     ctypes.c_void_p(self.workspace.data_ptr())), self._ctx)
+            self._bound = True
+        _check(lib().gpweno_set_time(self._ctx, t, nsteps), self._ctx)
+
+    def get_state(self):
+        """Blocking copy of the state to a numpy array."""
+        with self._torch.cuda.stream(self.stream):
+            host = self.state.to("cpu", non_blocking=False)
+        self.stream.synchronize()
+        return host.numpy()
+
+    # -- time stepping ---------------------------------------------------------
+    def step(self, t_final):
+        _check(lib().gpweno_step(self._ctx, t_final), self._ctx)
+
+    def run(self, t_final, max_steps=-1):
+        """Blocking: advance to t_final (or max_steps more steps). Returns (nsteps, t)."""
+        n = ctypes.c_long()
+        t = ctypes.c_double()
+        _check(lib().gpweno_run(self._ctx, t_final, max_steps, ctypes.byref(n), ctypes.byref(t)), self._ctx)
+        return n.value, t.value
+
+    def time(self):
+        t, dt = ctypes.c_double(), ctypes.c_double()
+        n = ctypes.c_long()
+        _check(lib().gpweno_get_time(self._ctx, ctypes.byref(t), ctypes.byref(dt), ctypes.byref(n)), self._ctx)
+        return t.value, dt.value, n.value
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    # -- diagnostics -----------------------------------------------------------
+    def rhs(self, U):
+        """Right-hand side of the semi-discrete scheme for an arbitrary state (numpy in, numpy out)."""
+        torch = self._torch
+        src = torch.as_tensor(np.ascontiguousarray(U), dtype=torch.float64).to(self.device)
+        out = torch.empty_like(src)
+        torch.cuda.current_stream(self.device).synchronize()
+        _check(lib().gpweno_rhs(self._ctx, ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(out.data_ptr())),
+               self._ctx)
+        self.stream.synchronize()
+        return out.cpu().numpy()
+
+    def rhs_dir_device(self, dir, U_dev, L_dev, accumulate=False):
+        """Enqueue one direction's sweep on device tensors (no synchronisation)."""
+        _check(lib().gpweno_rhs_dir(self._ctx, dir, ctypes.c_void_p(U_dev.data_ptr()),
+                                    ctypes.c_void_p(L_dev.data_ptr()), 1 if accumulate else 0), self._ctx)
+
+    def conserved_sums(self):
+        out = np.zeros(8)
+        _check(lib().gpweno_conserved_sums(self._ctx, out.ctypes.data_as(_dp)), self._ctx)
+        return out[: self.nv]
+
+    def close(self):
+        if self._ctx:
+            lib().gpweno_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

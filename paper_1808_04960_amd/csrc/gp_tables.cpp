@@ -1,0 +1,200 @@
+// Pre-simulation GP tables in binary128 (Sec. 4 step 1 of the paper).
+//
+//   (b) squared-exponential covariance K on the 2R+1 stencil and K_m on each
+//       R+1 sub-stencil (Eq. (kmat)), prediction vectors k_* (Eq. (kstar)),
+//       GP weights w^T = k_*^T K^{-1} (Sec. 3.2, Eq. (q-intrp));
+//   (c) linear weights gamma: least-squares solution of M gamma = w_*
+//       (Sec. 3.3, Eqs. (gamm-system), (M-mat));
+//   (d) eigensystem of K_m built with sigma (Sec. 3.4); rows P_i = v_i/sqrt(lambda_i)
+//       (Eq. (beta-eigen)).
+//
+// K is badly conditioned at the usual ell = 12 dx (about 1e5, 6e9, 8e13 for
+// R = 1, 2, 3, and far worse for larger ell/dx), so a float64 solve loses up to
+// four digits of w for R = 3. Everything here runs in IEEE binary128 (113-bit
+// significand) and is rounded to float64 once at the end.
+//
+// Coordinates are in units of dx: stencil nodes at the integers -R..R, the
+// prediction point at x_* = +1/2 (w_plus) or -1/2 (w_minus).
+// Built with g++ (binary128 arithmetic and expq/sqrtq from libquadmath).
+#include <quadmath.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "gp_tables.h"
+
+namespace {
+
+typedef __float128 q128;
+
+constexpr int NMAX = 7;  // 2R+1 for R <= 3
+
+q128 se_kernel(q128 a, q128 b, q128 ell) {
+    q128 d = a - b;
+    return expq(-(d * d) / (2 * ell * ell));
+}
+
+// Solve A x = b for symmetric positive definite A (n <= NMAX) by Cholesky.
+bool cholesky_solve(int n, const q128 A[NMAX][NMAX], const q128 *b, q128 *x) {
+    q128 L[NMAX][NMAX] = {};
+    for (int j = 0; j < n; ++j) {
+        q128 s = A[j][j];
+        for (int k = 0; k < j; ++k) s -= L[j][k] * L[j][k];
+        if (!(s > 0)) return false;
+        L[j][j] = sqrtq(s);
+        for (int i = j + 1; i < n; ++i) {
+            q128 t = A[i][j];
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t / L[j][j];
+        }
+    }
+    q128 y[NMAX];
+    for (int i = 0; i < n; ++i) {
+        q128 t = b[i];
+        for (int k = 0; k < i; ++k) t -= L[i][k] * y[k];
+        y[i] = t / L[i][i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        q128 t = y[i];
+        for (int k = i + 1; k < n; ++k) t -= L[k][i] * x[k];
+        x[i] = t / L[i][i];
+    }
+    return true;
+}
+
+// Least squares min ||A x - b|| for A (m x n, m >= n, full column rank) by
+// Householder QR.
+bool householder_lsq(int m, int n, q128 A[NMAX][NMAX], q128 *b, q128 *x) {
+    for (int k = 0; k < n; ++k) {
+        q128 norm = 0;
+        for (int i = k; i < m; ++i) norm += A[i][k] * A[i][k];
+        norm = sqrtq(norm);
+        if (norm == 0) return false;
+        q128 alpha = (A[k][k] > 0) ? -norm : norm;
+        q128 v[NMAX] = {};
+        for (int i = k; i < m; ++i) v[i] = A[i][k];
+        v[k] -= alpha;
+        q128 vv = 0;
+        for (int i = k; i < m; ++i) vv += v[i] * v[i];
+        if (vv == 0) continue;
+        for (int j = k; j < n; ++j) {
+            q128 s = 0;
+            for (int i = k; i < m; ++i) s += v[i] * A[i][j];
+            s = 2 * s / vv;
+            for (int i = k; i < m; ++i) A[i][j] -= s * v[i];
+        }
+        q128 s = 0;
+        for (int i = k; i < m; ++i) s += v[i] * b[i];
+        s = 2 * s / vv;
+        for (int i = k; i < m; ++i) b[i] -= s * v[i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        q128 t = b[i];
+        for (int j = i + 1; j < n; ++j) t -= A[i][j] * x[j];
+        if (A[i][i] == 0) return false;
+        x[i] = t / A[i][i];
+    }
+    return true;
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (n <= 4).
+// On return A's diagonal holds the eigenvalues and V's columns the eigenvectors.
+void jacobi_eigen(int n, q128 A[4][4], q128 V[4][4]) {
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) V[i][j] = (i == j) ? 1 : 0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        q128 off = 0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += A[p][q] * A[p][q];
+        if (off < (q128)1e-60 * (q128)1e-6) break;
+        for (int p = 0; p < n; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                if (A[p][q] == 0) continue;
+                q128 theta = (A[q][q] - A[p][p]) / (2 * A[p][q]);
+                q128 t = (theta >= 0 ? 1 : -1) / (fabsq(theta) + sqrtq(theta * theta + 1));
+                q128 c = 1 / sqrtq(t * t + 1);
+                q128 s = t * c;
+                for (int k = 0; k < n; ++k) {  // A <- A J (columns p, q)
+                    q128 akp = A[k][p], akq = A[k][q];
+                    A[k][p] = c * akp - s * akq;
+                    A[k][q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {  // A <- J^T A (rows p, q)
+                    q128 apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = c * apk - s * aqk;
+                    A[q][k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    q128 vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = c * vkp - s * vkq;
+                    V[k][q] = s * vkp + c * vkq;
+                }
+            }
+        }
+    }
+}
+
+// GP weights and linear weights for one prediction point x_*.
+bool weights_for_point(int R, q128 ell, q128 xstar, q128 w[4][4], q128 gam[4]) {
+    const int n = 2 * R + 1;
+    q128 nodes[NMAX];
+    for (int j = 0; j < n; ++j) nodes[j] = (q128)(j - R);
+    // full stencil: K w_* = k_*
+    q128 K[NMAX][NMAX], ks[NMAX], wstar[NMAX];
+    for (int i = 0; i < n; ++i) {
+        ks[i] = se_kernel(xstar, nodes[i], ell);
+        for (int j = 0; j < n; ++j) K[i][j] = se_kernel(nodes[i], nodes[j], ell);
+    }
+    if (!cholesky_solve(n, K, ks, wstar)) return false;
+    // sub-stencils m = 0..R over nodes m-R .. m
+    for (int m = 0; m <= R; ++m) {
+        q128 Km[NMAX][NMAX], km[NMAX], wm[NMAX];
+        for (int i = 0; i <= R; ++i) {
+            km[i] = ks[m + i];
+            for (int j = 0; j <= R; ++j) Km[i][j] = K[m + i][m + j];
+        }
+        if (!cholesky_solve(R + 1, Km, km, wm)) return false;
+        for (int j = 0; j <= R; ++j) w[m][j] = wm[j];
+    }
+    // M gamma = w_*, column m holds w_m in rows m..m+R
+    q128 M[NMAX][NMAX] = {};
+    for (int m = 0; m <= R; ++m)
+        for (int j = 0; j <= R; ++j) M[m + j][m] = w[m][j];
+    q128 rhs[NMAX], g[NMAX];
+    for (int i = 0; i < n; ++i) rhs[i] = wstar[i];
+    if (!householder_lsq(n, R + 1, M, rhs, g)) return false;
+    for (int m = 0; m <= R; ++m) gam[m] = g[m];
+    return true;
+}
+
+}  // namespace
+
+int gpw_build_tables(int R, double ell_over_dx, double sigma_over_dx, GpTablesF64 *out) {
+    if (R < 1 || R > 3 || !(ell_over_dx > 0) || !(sigma_over_dx > 0) || !out) return -1;
+    std::memset(out, 0, sizeof(*out));
+    q128 ell = (q128)ell_over_dx;
+    q128 sig = (q128)sigma_over_dx;
+    q128 wp[4][4] = {}, wm[4][4] = {}, gp[4] = {}, gm[4] = {};
+    if (!weights_for_point(R, ell, (q128)0.5, wp, gp)) return -2;
+    if (!weights_for_point(R, ell, (q128)-0.5, wm, gm)) return -2;
+    // eigensystem of K_m(sigma) on nodes 0..R (identical for every sub-stencil)
+    q128 A[4][4] = {}, V[4][4] = {};
+    for (int i = 0; i <= R; ++i)
+        for (int j = 0; j <= R; ++j) A[i][j] = se_kernel((q128)i, (q128)j, sig);
+    jacobi_eigen(R + 1, A, V);
+    for (int i = 0; i <= R; ++i) {
+        q128 lam = A[i][i];
+        if (!(lam > 0)) return -3;
+        q128 inv = 1 / sqrtq(lam);
+        for (int j = 0; j <= R; ++j) out->P[i][j] = (double)(V[j][i] * inv);
+    }
+    for (int m = 0; m <= R; ++m) {
+        out->gam_plus[m] = (double)gp[m];
+        out->gam_minus[m] = (double)gm[m];
+        for (int j = 0; j <= R; ++j) {
+            out->w_plus[m][j] = (double)wp[m][j];
+            out->w_minus[m][j] = (double)wm[m][j];
+        }
+    }
+    return 0;
+}

@@ -1,0 +1,67 @@
+// Device-side data shared by the kernels and the host API of libgpweno.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gpw {
+
+// Control block in device memory. Written by the time-step kernel and read by
+// the sweeps, so a captured sequence of steps needs no host involvement.
+struct Ctl {
+    double t;               // time reached after the step in flight
+    double dt;              // time step of the step in flight
+    double t_final;         // stop time of the current run
+    double cfl;             // CFL number
+    double fixed_dt;        // > 0: fixed time step
+    unsigned long long speed_bits;  // max_i sum_d (|u_d|+c)/dx_d of the current state,
+                                    // bit image of a non-negative double (atomic max)
+    long long nsteps;       // steps taken so far
+    long long step_limit;   // stop once nsteps reaches this
+    int halt;               // 1: the step in flight is skipped
+    int err;                // 1: a stage produced rho <= 0, p <= 0 or NaN
+    long long bad_cell;     // smallest cell index of such a failure
+    double sums[8];         // conserved sums (reduction output)
+};
+
+template <typename Real>
+struct Tab {
+    Real wp[4][4];  // w_m at x_* = +1/2, [m][j]
+    Real wm[4][4];  // w_m at x_* = -1/2
+    Real gp[4];     // gamma_m for x_* = +1/2
+    Real gm[4];     // gamma_m for x_* = -1/2
+    Real P[4][4];   // rows v_i / sqrt(lambda_i) of K_m(sigma)
+};
+
+template <typename Real>
+struct SweepArgs {
+    const double* U;    // stage input state (stencil data)
+    const double* Un;   // state at the start of the step (RK base)
+    double* dU;         // direction accumulator of the right-hand side
+    double* Uout;       // stage output (last direction of an RK stage)
+    Ctl* ctl;
+    int n[3];           // cells per axis
+    int nseg;           // runs of cells per pencil along the sweep axis
+    long long ncell;
+    double inv_dx;      // 1/dx along the sweep axis
+    double inv_dx_all[3];
+    double gamma;
+    int first;          // first direction: the accumulator starts at zero
+    int last;           // last direction: finish the stage
+    int stage;          // 0: right-hand side only; 1..3: SSP-RK3 stage
+    int positivity;     // positivity fallback of the Riemann states
+    int use_ctl;        // 1: honour ctl->halt and read dt from ctl
+    Tab<Real> tab;
+};
+
+// Launchers (defined in gpweno_kernels.hip).
+hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, const void* args, hipStream_t s);
+hipError_t launch_dt(Ctl* ctl, hipStream_t s);
+hipError_t launch_set_run(Ctl* ctl, double t_final, long long step_limit, hipStream_t s);
+hipError_t launch_set_time(Ctl* ctl, double t, long long nsteps, double cfl, double fixed_dt, hipStream_t s);
+hipError_t launch_speed(int ndim, const double* U, long long ncell, const int n[3], const double inv_dx[3],
+                        double gamma, Ctl* ctl, hipStream_t s);
+hipError_t launch_sums(int nv, const double* U, long long ncell, double* partials, int npart, Ctl* ctl,
+                       hipStream_t s);
+
+}  // namespace gpw

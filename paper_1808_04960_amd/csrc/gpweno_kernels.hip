@@ -1,0 +1,690 @@
+// GP-WENO FD-Prim sweep kernels for gfx950 (CDNA4, wave64).
+//
+// One kernel launch evaluates one direction's contribution to the right-hand
+// side of Eq. (disc_fd) for every cell, and in the last direction of an RK
+// stage also finishes the stage. Work decomposition:
+//
+//   * A "run" is 64 consecutive cells of one pencil along the sweep axis,
+//     mapped one cell per lane of a wave. Each lane reconstructs the Riemann
+//     states of its cell (stencil of 2R+1 cells read from LDS), the wave then
+//     forms face fluxes, corrected fluxes and flux differences with cross-lane
+//     shuffles. The flux correction needs face fluxes two faces either side
+//     and the difference one more face, so lanes 3..60 produce output: a run
+//     yields 58 cells, and consecutive runs overlap by 6 cells.
+//   * A block holds several pencils (one wave each) and the same run segment.
+//     The input tile [2+ndim fields][pencils][64 + 2R cells] is loaded once
+//     from HBM with periodic wrap, converted to rotated primitive variables and
+//     staged in LDS.
+//   * x sweeps: each wave loads its own row (contiguous along x) and writes its
+//     outputs directly (contiguous). y/z sweeps: a block holds 8 adjacent
+//     x-columns, so every global access covers 8 consecutive doubles; the
+//     outputs are transposed through LDS so the read-modify-write epilogue is
+//     also x-contiguous.
+//
+// Per cell (paper references):
+//   characteristic projection of the primitive stencil at the centre cell
+//     (Sec. 7 intro), GP-WENO per field (Sec. 3.3: Eqs. (candidate_interp),
+//     (beta-eigen), (weights), (weight_sum)), back-projection, HLLC at the face
+//     (Eq. (riemann_prob)), flux correction alpha = -1/24, beta = 3/640
+//     (Eqs. (numFlux_cor), (FD-ders)), flux difference (Eq. (disc_fd)), SSP-RK3.
+//
+// Precision: Real is the sweep arithmetic type (double or float). The state,
+// flux differences, accumulator, RK combination, CFL speeds and sums are
+// always float64; a float32 corrected flux is widened before its difference
+// is taken, so both neighbours of a face subtract the same value.
+#include <float.h>
+#include <limits.h>
+
+#include "gpweno_kernels.h"
+
+namespace gpw {
+
+constexpr int WAVE = 64;
+constexpr int LEFT = 3;             // first output lane of a run
+constexpr int TOUT = WAVE - 6;      // outputs per run
+
+__host__ __device__ constexpr int t1_axis(int dir) { return dir == 0 ? 1 : 0; }
+__host__ __device__ constexpr int t2_axis(int dir) { return dir == 2 ? 1 : 2; }
+
+// Conserved slot of rotated component k (rho, u_n, u_t1, u_t2, p order).
+template <int NDIM, int DIR>
+__host__ __device__ constexpr int cons_slot(int k) {
+    return k == 0 ? 0
+         : k == 1 ? 1 + DIR
+         : k == 1 + NDIM ? 1 + NDIM
+         : k == 2 ? 1 + t1_axis(DIR)
+         : 1 + t2_axis(DIR);
+}
+
+template <typename Real> __device__ __forceinline__ Real fdiv(Real a, Real b);
+template <> __device__ __forceinline__ double fdiv<double>(double a, double b) { return a / b; }
+template <> __device__ __forceinline__ float fdiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+
+template <typename Real> __device__ __forceinline__ Real fsqrt(Real a);
+template <> __device__ __forceinline__ double fsqrt<double>(double a) { return sqrt(a); }
+template <> __device__ __forceinline__ float fsqrt<float>(float a) { return __builtin_amdgcn_sqrtf(a); }
+
+__device__ __forceinline__ int wrap(int x, int n) {
+    int r = x % n;
+    return r < 0 ? r + n : r;
+}
+
+// Conserved -> primitive in the frame rotated to DIR: (rho, u_n[, u_t1[, u_t2]], p).
+template <int NDIM, int DIR>
+__device__ __forceinline__ void cons_to_rot(const double* __restrict__ U, long long ncell, long long cell,
+                                            double gamma, double q[2 + NDIM]) {
+    constexpr int NV = 2 + NDIM;
+    const double rho = U[cell];
+    double mom[3] = {0.0, 0.0, 0.0}, vel[3] = {0.0, 0.0, 0.0};
+    double ke = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+        mom[d] = U[(1 + d) * ncell + cell];
+        vel[d] = mom[d] / rho;
+        ke += vel[d] * mom[d];
+    }
+    const double E = U[(NV - 1) * ncell + cell];
+    q[0] = rho;
+    q[1] = vel[DIR];
+    if (NDIM >= 2) q[2] = vel[t1_axis(DIR)];
+    if (NDIM == 3) q[3] = vel[t2_axis(DIR)];
+    q[NV - 1] = (gamma - 1.0) * (E - 0.5 * ke);
+}
+
+// GP-WENO interpolation of one characteristic field f[0..2R] to x_{i+1/2} (qp)
+// and x_{i-1/2} (qm). beta_m = sum_i (P_i . f_m)^2 is shared by both points.
+// Nonlinear weights gamma_m / (eps + beta_m)^2 are evaluated in the equivalent
+// form gamma_m * ((eps + beta_min)/(eps + beta_m))^2, which cannot overflow or
+// underflow to 0/0 in float32 (eps = 1e-36 squared is below float range).
+template <int R, typename Real>
+__device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Real>& T, Real& qp, Real& qm) {
+    Real e[R + 1], cp[R + 1], cm[R + 1];
+#pragma unroll
+    for (int m = 0; m <= R; ++m) {
+        Real b = Real(0);
+#pragma unroll
+        for (int i = 0; i <= R; ++i) {
+            Real pr = T.P[i][0] * f[m];
+#pragma unroll
+            for (int j = 1; j <= R; ++j) pr = fma(T.P[i][j], f[m + j], pr);
+            b = fma(pr, pr, b);
+        }
+        e[m] = Real(1e-36) + b;
+        Real ap = T.wp[m][0] * f[m];
+        Real am = T.wm[m][0] * f[m];
+#pragma unroll
+        for (int j = 1; j <= R; ++j) {
+            ap = fma(T.wp[m][j], f[m + j], ap);
+            am = fma(T.wm[m][j], f[m + j], am);
+        }
+        cp[m] = ap;
+        cm[m] = am;
+    }
+    Real emin = e[0];
+#pragma unroll
+    for (int m = 1; m <= R; ++m) emin = fmin(emin, e[m]);
+    Real sp = Real(0), sm = Real(0), accp = Real(0), accm = Real(0);
+#pragma unroll
+    for (int m = 0; m <= R; ++m) {
+        const Real r = fdiv(emin, e[m]);
+        const Real w = r * r;
+        const Real op = T.gp[m] * w;
+        const Real om = T.gm[m] * w;
+        sp += op;
+        sm += om;
+        accp = fma(op, cp[m], accp);
+        accm = fma(om, cm[m], accm);
+    }
+    qp = fdiv(accp, sp);
+    qm = fdiv(accm, sm);
+}
+
+// Riemann states of the cell at lane position l: stencil entries l .. l+2R of a
+// pencil in LDS (field k at s[k * fs + .]). Projects the primitive stencil on the
+// left eigenvectors of the primitive Jacobian at the centre cell, interpolates
+// each characteristic field, and projects back with the right eigenvectors:
+//   acoustic -:  -rho/(2c) u_n + p/(2c^2)       r = (1, -c/rho, 0, 0, c^2)
+//   entropy   :  rho - p/c^2                    r = (1, 0, 0, 0, 0)
+//   shear     :  u_t1, u_t2                     r = unit vectors
+//   acoustic +:   rho/(2c) u_n + p/(2c^2)       r = (1,  c/rho, 0, 0, c^2)
+template <int NDIM, int R, typename Real>
+__device__ __forceinline__ void reconstruct(const Real* __restrict__ s, int fs, int l, const Tab<Real>& T,
+                                            Real gamma, int positivity, Real (&qp)[2 + NDIM],
+                                            Real (&qm)[2 + NDIM]) {
+    constexpr int NV = 2 + NDIM;
+    constexpr int NS = 2 * R + 1;
+    Real v[NV][NS];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int j = 0; j < NS; ++j) v[k][j] = s[k * fs + l + j];
+
+    const Real rho = v[0][R], p = v[NV - 1][R];
+    const Real c2 = fdiv(gamma * p, rho);
+    const Real c = fsqrt(c2);
+    const Real ic = fdiv(Real(1), c);
+    const Real ic2 = ic * ic;
+    const Real a = Real(0.5) * rho * ic;
+    const Real b = Real(0.5) * ic2;
+
+    Real f[NS];
+    Real acm_p, acm_m, ent_p, ent_m, acp_p, acp_m;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) f[j] = fma(-a, v[1][j], b * v[NV - 1][j]);
+    gp_weno<R, Real>(f, T, acm_p, acm_m);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) f[j] = fma(-ic2, v[NV - 1][j], v[0][j]);
+    gp_weno<R, Real>(f, T, ent_p, ent_m);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) f[j] = fma(a, v[1][j], b * v[NV - 1][j]);
+    gp_weno<R, Real>(f, T, acp_p, acp_m);
+#pragma unroll
+    for (int t = 0; t < NDIM - 1; ++t) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) f[j] = v[2 + t][j];
+        gp_weno<R, Real>(f, T, qp[2 + t], qm[2 + t]);
+    }
+    const Real cr = c * fdiv(Real(1), rho);
+    qp[0] = acm_p + ent_p + acp_p;
+    qm[0] = acm_m + ent_m + acp_m;
+    qp[1] = cr * (acp_p - acm_p);
+    qm[1] = cr * (acp_m - acm_m);
+    qp[NV - 1] = c2 * (acm_p + acp_p);
+    qm[NV - 1] = c2 * (acm_m + acp_m);
+    if (positivity) {
+        if (!(qp[0] > Real(0)) || !(qp[NV - 1] > Real(0))) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) qp[k] = v[k][R];
+        }
+        if (!(qm[0] > Real(0)) || !(qm[NV - 1] > Real(0))) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) qm[k] = v[k][R];
+        }
+    }
+}
+
+// Euler flux of a rotated primitive state, and its conserved vector.
+template <int NDIM, typename Real>
+__device__ __forceinline__ void flux_of(const Real (&q)[2 + NDIM], Real inv_gm1, Real (&F)[2 + NDIM],
+                                        Real (&Uc)[2 + NDIM]) {
+    constexpr int NV = 2 + NDIM;
+    const Real r = q[0], u = q[1], p = q[NV - 1];
+    Real k2 = u * u;
+#pragma unroll
+    for (int t = 0; t < NDIM - 1; ++t) k2 = fma(q[2 + t], q[2 + t], k2);
+    const Real E = fma(p, inv_gm1, Real(0.5) * r * k2);
+    const Real mu = r * u;
+    F[0] = mu;
+    F[1] = fma(mu, u, p);
+#pragma unroll
+    for (int t = 0; t < NDIM - 1; ++t) F[2 + t] = mu * q[2 + t];
+    F[NV - 1] = u * (E + p);
+    Uc[0] = r;
+    Uc[1] = mu;
+#pragma unroll
+    for (int t = 0; t < NDIM - 1; ++t) Uc[2 + t] = r * q[2 + t];
+    Uc[NV - 1] = E;
+}
+
+// HLLC flux (rotated frame) with Davis wave-speed estimates; at S* = 0 the left
+// star state is used. Branch-free: the star state of the upwind side of the
+// contact is built once and the final flux is selected.
+template <int NDIM, typename Real>
+__device__ __forceinline__ void hllc(const Real (&qL)[2 + NDIM], const Real (&qR)[2 + NDIM], Real gamma,
+                                     Real inv_gm1, Real (&F)[2 + NDIM]) {
+    constexpr int NV = 2 + NDIM;
+    Real FL[NV], FR[NV], UL[NV], UR[NV];
+    flux_of<NDIM, Real>(qL, inv_gm1, FL, UL);
+    flux_of<NDIM, Real>(qR, inv_gm1, FR, UR);
+    const Real rL = qL[0], uL = qL[1], pL = qL[NV - 1];
+    const Real rR = qR[0], uR = qR[1], pR = qR[NV - 1];
+    const Real cL = fsqrt(fdiv(gamma * pL, rL));
+    const Real cR = fsqrt(fdiv(gamma * pR, rR));
+    const Real SL = fmin(uL - cL, uR - cR);
+    const Real SR = fmax(uL + cL, uR + cR);
+    const Real mL = rL * (SL - uL);
+    const Real mR = rR * (SR - uR);
+    const Real Ss = fdiv(pR - pL + uL * mL - uR * mR, mL - mR);
+    const bool left = Ss >= Real(0);
+    const Real r = left ? rL : rR;
+    const Real u = left ? uL : uR;
+    const Real p = left ? pL : pR;
+    const Real S = left ? SL : SR;
+    const Real m = left ? mL : mR;
+    const Real fac = fdiv(m, S - Ss);
+    const Real ir = fdiv(Real(1), r);
+    Real Us[NV], Fs[NV];
+    Us[0] = fac;
+    Us[1] = fac * Ss;
+#pragma unroll
+    for (int t = 0; t < NDIM - 1; ++t) Us[2 + t] = fac * (left ? qL[2 + t] : qR[2 + t]);
+    const Real EK = left ? UL[NV - 1] : UR[NV - 1];
+    Us[NV - 1] = fac * (EK * ir + (Ss - u) * (Ss + fdiv(p, m)));
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const Real Fk = left ? FL[k] : FR[k];
+        const Real Uk = left ? UL[k] : UR[k];
+        Fs[k] = fma(S, Us[k] - Uk, Fk);
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) F[k] = (SL >= Real(0)) ? FL[k] : ((SR <= Real(0)) ? FR[k] : Fs[k]);
+}
+
+template <int NDIM, int DIR, int R, typename Real>
+struct SweepCfg {
+    static constexpr int NV = 2 + NDIM;
+    static constexpr int SLEN = WAVE + 2 * R;
+    static constexpr int PITCH = SLEN | 1;
+    static constexpr int WPB = (DIR == 0) ? 4 : 8;  // pencils (waves) per block
+    static constexpr int THREADS = WPB * WAVE;
+    static constexpr size_t IN_BYTES = sizeof(Real) * NV * WPB * PITCH;
+    static constexpr size_t OUT_BYTES = (DIR == 0) ? 0 : sizeof(double) * NV * TOUT * WPB;
+    static constexpr size_t SMEM = IN_BYTES > OUT_BYTES ? IN_BYTES : OUT_BYTES;
+};
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// Finish one cell: accumulate the direction's contribution and, in the last
+// direction of an RK stage, form the stage output (SSP-RK3, Shu-Osher form),
+// check it is physical and (stage 3) track the CFL speed of the new state.
+template <int NDIM, typename Real>
+__device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long cell, const double (&d)[2 + NDIM],
+                                            double dt, unsigned long long& smax) {
+    constexpr int NV = 2 + NDIM;
+    const long long nc = a.ncell;
+    if (a.stage == 0 || !a.last) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const double v = a.first ? d[k] : a.dU[k * nc + cell] + d[k];
+            a.dU[k * nc + cell] = v;
+        }
+        return;
+    }
+    double o[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double L = a.first ? d[k] : a.dU[k * nc + cell] + d[k];
+        const double adv = a.U[k * nc + cell] + dt * L;
+        double out;
+        if (a.stage == 1) out = adv;
+        else if (a.stage == 2) out = 0.75 * a.Un[k * nc + cell] + 0.25 * adv;
+        else out = (1.0 / 3.0) * a.Un[k * nc + cell] + (2.0 / 3.0) * adv;
+        a.Uout[k * nc + cell] = out;
+        o[k] = out;
+    }
+    const double rho = o[0];
+    double ke = 0.0, vel[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int dd = 0; dd < NDIM; ++dd) {
+        vel[dd] = o[1 + dd] / rho;
+        ke += vel[dd] * o[1 + dd];
+    }
+    const double p = (a.gamma - 1.0) * (o[NV - 1] - 0.5 * ke);
+    if (!(rho > 0.0) || !(p > 0.0)) {
+        atomicOr(&a.ctl->err, 1);
+        atomicMin(&a.ctl->bad_cell, cell);
+    }
+    if (a.stage == 3) {
+        const double c = sqrt(a.gamma * p / rho);
+        double s = 0.0;
+#pragma unroll
+        for (int dd = 0; dd < NDIM; ++dd) s += (fabs(vel[dd]) + c) * a.inv_dx_all[dd];
+        // non-negative doubles order like their bit images; NaN sorts above +inf
+        const unsigned long long bits = (s != s) ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(s);
+        smax = bits > smax ? bits : smax;
+    }
+}
+
+template <int NDIM, int DIR, int R, typename Real>
+__global__ void __launch_bounds__(DIR == 0 ? 4 * WAVE : 8 * WAVE)
+sweep_kernel(const SweepArgs<Real> a) {
+    using C = SweepCfg<NDIM, DIR, R, Real>;
+    constexpr int NV = C::NV, WPB = C::WPB, PITCH = C::PITCH, SLEN = C::SLEN, THREADS = C::THREADS;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
+    __shared__ unsigned long long sred[WPB];
+    Real* sV = reinterpret_cast<Real*>(smem);
+    double* sO = reinterpret_cast<double*>(smem);
+
+    if (a.use_ctl && a.ctl->halt) return;
+    const double dt = a.use_ctl ? a.ctl->dt : 0.0;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int w = tid / WAVE;
+    const int N = a.n[DIR];
+    const int seg = blockIdx.x % a.nseg;
+    const long long grp = blockIdx.x / a.nseg;
+    const int s0 = (int)((long long)seg * N / a.nseg);
+    const int tseg = (int)((long long)(seg + 1) * N / a.nseg) - s0;
+    const int sbase = s0 - LEFT - R;
+    const long long nc = a.ncell;
+    const double gamma = a.gamma;
+
+    // ---- pencil geometry ----------------------------------------------------
+    long long stride;
+    long long blk_base;   // cell of column 0 at s = 0
+    int ncol_valid;       // pencils of this block that exist
+    if (DIR == 0) {
+        stride = 1;
+        const long long nrows = (long long)a.n[1] * a.n[2];
+        const long long row0 = grp * WPB;
+        blk_base = row0 * a.n[0];
+        ncol_valid = (int)((nrows - row0) < WPB ? (nrows - row0) : WPB);
+    } else {
+        const int nxb = (a.n[0] + WPB - 1) / WPB;
+        const int xb = (int)(grp % nxb) * WPB;
+        const long long other = grp / nxb;  // z for DIR 1, y for DIR 2
+        stride = (DIR == 1) ? (long long)a.n[0] : (long long)a.n[0] * a.n[1];
+        blk_base = xb + other * (DIR == 1 ? (long long)a.n[0] * a.n[1] : (long long)a.n[0]);
+        ncol_valid = (a.n[0] - xb) < WPB ? (a.n[0] - xb) : WPB;
+    }
+    // column c of the block starts at blk_base + c * cstride
+    const long long cstride = (DIR == 0) ? (long long)a.n[0] : 1;
+
+    // ---- load the stencil tile (rotated primitive variables) into LDS --------
+    {
+        constexpr int FS = WPB * PITCH;
+        if (DIR == 0) {
+            const int c = w;
+            for (int idx = lane; idx < SLEN; idx += WAVE) {
+                double q[NV];
+                if (c < ncol_valid) {
+                    const long long cell = blk_base + c * cstride + wrap(sbase + idx, N);
+                    cons_to_rot<NDIM, DIR>(a.U, nc, cell, gamma, q);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) q[k] = (k == 0 || k == NV - 1) ? 1.0 : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < NV; ++k) sV[k * FS + c * PITCH + idx] = (Real)q[k];
+            }
+        } else {
+            const int c = tid % WPB;
+            for (int idx = tid / WPB; idx < SLEN; idx += THREADS / WPB) {
+                double q[NV];
+                if (c < ncol_valid) {
+                    const long long cell = blk_base + c * cstride + (long long)wrap(sbase + idx, N) * stride;
+                    cons_to_rot<NDIM, DIR>(a.U, nc, cell, gamma, q);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) q[k] = (k == 0 || k == NV - 1) ? 1.0 : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < NV; ++k) sV[k * FS + c * PITCH + idx] = (Real)q[k];
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- per-lane reconstruction, face flux, correction, difference ----------
+    double dcons[NV];
+    {
+        constexpr int FS = WPB * PITCH;
+        const Real g = (Real)gamma;
+        const Real inv_gm1 = (Real)(1.0 / (gamma - 1.0));
+        Real qp[NV], qm[NV];
+        reconstruct<NDIM, R, Real>(sV + w * PITCH, FS, lane, a.tab, g, a.positivity, qp, qm);
+        Real qR[NV], F[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) qR[k] = __shfl_down(qm[k], 1);
+        hllc<NDIM, Real>(qp, qR, g, inv_gm1, F);
+        const Real alpha = Real(-1.0 / 24.0), beta = Real(3.0 / 640.0);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const Real fm2 = __shfl_up(F[k], 2), fm1 = __shfl_up(F[k], 1);
+            const Real fp1 = __shfl_down(F[k], 1), fp2 = __shfl_down(F[k], 2);
+            const Real d2 = fm1 - Real(2) * F[k] + fp1;
+            const Real d4 = fm2 - Real(4) * fm1 + Real(6) * F[k] - Real(4) * fp1 + fp2;
+            const Real fh = F[k] + alpha * d2 + beta * d4;
+            const Real fhm = __shfl_up(fh, 1);
+            dcons[cons_slot<NDIM, DIR>(k)] = -((double)fh - (double)fhm) * a.inv_dx;
+        }
+    }
+
+    unsigned long long smax = 0;
+    const bool lane_out = lane >= LEFT && lane < LEFT + tseg;
+    if (DIR == 0) {
+        if (w < ncol_valid && lane_out) {
+            const long long cell = blk_base + w * cstride + (s0 + lane - LEFT);
+            finish_cell<NDIM, Real>(a, cell, dcons, dt, smax);
+        }
+    } else {
+        __syncthreads();  // every wave is done reading the stencil tile
+        if (lane_out) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) sO[(k * TOUT + (lane - LEFT)) * WPB + w] = dcons[k];
+        }
+        __syncthreads();
+        for (int idx = tid; idx < tseg * WPB; idx += THREADS) {
+            const int row = idx / WPB, c = idx % WPB;
+            if (c < ncol_valid) {
+                double d[NV];
+#pragma unroll
+                for (int k = 0; k < NV; ++k) d[k] = sO[(k * TOUT + row) * WPB + c];
+                const long long cell = blk_base + c * cstride + (long long)(s0 + row) * stride;
+                finish_cell<NDIM, Real>(a, cell, d, dt, smax);
+            }
+        }
+    }
+    if (a.stage == 3 && a.last && a.use_ctl) {
+        smax = wave_max_u64(smax);
+        if (lane == 0) sred[w] = smax;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long m = sred[0];
+#pragma unroll
+            for (int i = 1; i < WPB; ++i) m = sred[i] > m ? sred[i] : m;
+            atomicMax(&a.ctl->speed_bits, m);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Time-step control and reductions
+// ---------------------------------------------------------------------------
+
+// dt = cfl / max speed (or the fixed dt), clipped so that t does not pass
+// t_final; sets halt when the run is over (dt then keeps the last step's value).
+__global__ void dt_kernel(Ctl* c) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double t = c->t;
+    if (c->err || !(t < c->t_final) || c->nsteps >= c->step_limit) {
+        c->halt = 1;
+        return;
+    }
+    const double speed = __longlong_as_double((long long)c->speed_bits);
+    double dt = c->fixed_dt > 0.0 ? c->fixed_dt : c->cfl / speed;
+    if (t + dt > c->t_final) dt = c->t_final - t;
+    c->dt = dt;
+    c->t = t + dt;
+    c->nsteps += 1;
+    c->halt = 0;
+    c->speed_bits = 0ull;
+}
+
+__global__ void set_run_kernel(Ctl* c, double t_final, long long step_limit) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    c->t_final = t_final;
+    c->step_limit = step_limit;
+}
+
+__global__ void set_time_kernel(Ctl* c, double t, long long nsteps, double cfl, double fixed_dt) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    c->t = t;
+    c->dt = 0.0;
+    c->nsteps = nsteps;
+    c->cfl = cfl;
+    c->fixed_dt = fixed_dt;
+    c->halt = 0;
+    c->err = 0;
+    c->bad_cell = LLONG_MAX;
+    c->speed_bits = 0ull;
+}
+
+// CFL speed max_i sum_d (|u_d| + c)/dx_d of a state, with the physical check.
+template <int NDIM>
+__global__ void __launch_bounds__(256) speed_kernel(const double* __restrict__ U, long long ncell, int n0, int n1,
+                                                    double ix0, double ix1, double ix2, double gamma, Ctl* ctl) {
+    constexpr int NV = 2 + NDIM;
+    __shared__ unsigned long long sred[4];
+    const double ix[3] = {ix0, ix1, ix2};
+    unsigned long long smax = 0;
+    for (long long cell = blockIdx.x * (long long)blockDim.x + threadIdx.x; cell < ncell;
+         cell += (long long)gridDim.x * blockDim.x) {
+        const double rho = U[cell];
+        double ke = 0.0, s = 0.0, vel[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) {
+            const double m = U[(1 + d) * ncell + cell];
+            vel[d] = m / rho;
+            ke += vel[d] * m;
+        }
+        const double p = (gamma - 1.0) * (U[(NV - 1) * ncell + cell] - 0.5 * ke);
+        if (!(rho > 0.0) || !(p > 0.0)) {
+            atomicOr(&ctl->err, 1);
+            atomicMin(&ctl->bad_cell, cell);
+        }
+        const double c = sqrt(gamma * p / rho);
+#pragma unroll
+        for (int d = 0; d < NDIM; ++d) s += (fabs(vel[d]) + c) * ix[d];
+        const unsigned long long bits = (s != s) ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(s);
+        smax = bits > smax ? bits : smax;
+    }
+    smax = wave_max_u64(smax);
+    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = smax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long m = sred[0];
+        for (int i = 1; i < 4; ++i) m = sred[i] > m ? sred[i] : m;
+        atomicMax(&ctl->speed_bits, m);
+    }
+    (void)n0;
+    (void)n1;
+}
+
+// Deterministic float64 sums: fixed per-thread strides, fixed tree per block,
+// then one block adds the per-block partials in index order.
+__global__ void __launch_bounds__(256) sums_partial_kernel(const double* __restrict__ U, long long ncell, int nv,
+                                                           double* __restrict__ partials) {
+    __shared__ double sh[256];
+    for (int k = 0; k < nv; ++k) {
+        double acc = 0.0;
+        for (long long i = blockIdx.x * 256ll + threadIdx.x; i < ncell; i += (long long)gridDim.x * 256)
+            acc += U[k * ncell + i];
+        sh[threadIdx.x] = acc;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partials[k * gridDim.x + blockIdx.x] = sh[0];
+        __syncthreads();
+    }
+}
+
+__global__ void sums_final_kernel(const double* __restrict__ partials, int npart, int nv, Ctl* ctl) {
+    const int k = threadIdx.x;
+    if (k >= nv) return;
+    double acc = 0.0;
+    for (int b = 0; b < npart; ++b) acc += partials[k * npart + b];
+    ctl->sums[k] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int NDIM, int DIR, int R, typename Real>
+hipError_t launch_one(const void* args, hipStream_t s) {
+    using C = SweepCfg<NDIM, DIR, R, Real>;
+    const SweepArgs<Real>& a = *static_cast<const SweepArgs<Real>*>(args);
+    long long groups;
+    if (DIR == 0) {
+        groups = ((long long)a.n[1] * a.n[2] + C::WPB - 1) / C::WPB;
+    } else {
+        const long long nxb = (a.n[0] + C::WPB - 1) / C::WPB;
+        groups = nxb * (DIR == 1 ? a.n[2] : a.n[1]);
+    }
+    const long long blocks = groups * a.nseg;
+    if (blocks <= 0 || blocks > INT_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep_kernel<NDIM, DIR, R, Real>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int NDIM, int R, typename Real>
+hipError_t launch_dir(int dir, const void* args, hipStream_t s) {
+    if (dir == 0) return launch_one<NDIM, 0, R, Real>(args, s);
+    if (NDIM >= 2 && dir == 1) return launch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real>(args, s);
+    if (NDIM == 3 && dir == 2) return launch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real>(args, s);
+    return hipErrorInvalidValue;
+}
+
+template <int NDIM, typename Real>
+hipError_t launch_r(int dir, int R, const void* args, hipStream_t s) {
+    switch (R) {
+        case 1: return launch_dir<NDIM, 1, Real>(dir, args, s);
+        case 2: return launch_dir<NDIM, 2, Real>(dir, args, s);
+        case 3: return launch_dir<NDIM, 3, Real>(dir, args, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename Real>
+hipError_t launch_nd(int ndim, int dir, int R, const void* args, hipStream_t s) {
+    switch (ndim) {
+        case 1: return launch_r<1, Real>(dir, R, args, s);
+        case 2: return launch_r<2, Real>(dir, R, args, s);
+        case 3: return launch_r<3, Real>(dir, R, args, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, const void* args, hipStream_t s) {
+    return fp32 ? launch_nd<float>(ndim, dir, R, args, s) : launch_nd<double>(ndim, dir, R, args, s);
+}
+
+hipError_t launch_dt(Ctl* ctl, hipStream_t s) {
+    hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(64), 0, s, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_run(Ctl* ctl, double t_final, long long step_limit, hipStream_t s) {
+    hipLaunchKernelGGL(set_run_kernel, dim3(1), dim3(64), 0, s, ctl, t_final, step_limit);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_time(Ctl* ctl, double t, long long nsteps, double cfl, double fixed_dt, hipStream_t s) {
+    hipLaunchKernelGGL(set_time_kernel, dim3(1), dim3(64), 0, s, ctl, t, nsteps, cfl, fixed_dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_speed(int ndim, const double* U, long long ncell, const int n[3], const double inv_dx[3],
+                        double gamma, Ctl* ctl, hipStream_t s) {
+    long long blocks = (ncell + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    const dim3 g((unsigned)blocks), b(256);
+    switch (ndim) {
+        case 1: hipLaunchKernelGGL(speed_kernel<1>, g, b, 0, s, U, ncell, n[0], n[1], inv_dx[0], inv_dx[1], inv_dx[2], gamma, ctl); break;
+        case 2: hipLaunchKernelGGL(speed_kernel<2>, g, b, 0, s, U, ncell, n[0], n[1], inv_dx[0], inv_dx[1], inv_dx[2], gamma, ctl); break;
+        case 3: hipLaunchKernelGGL(speed_kernel<3>, g, b, 0, s, U, ncell, n[0], n[1], inv_dx[0], inv_dx[1], inv_dx[2], gamma, ctl); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sums(int nv, const double* U, long long ncell, double* partials, int npart, Ctl* ctl,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(sums_partial_kernel, dim3(npart), dim3(256), 0, s, U, ncell, nv, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sums_final_kernel, dim3(1), dim3(64), 0, s, partials, npart, nv, ctl);
+    return hipGetLastError();
+}
+
+}  // namespace gpw
