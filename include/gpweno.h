@@ -123,11 +123,22 @@ int gpweno_set_time(gpweno_ctx *ctx, double t, long nsteps);
  * blocking call (gpweno_get_time / gpweno_run) as ENONPHYS. */
 int gpweno_step(gpweno_ctx *ctx, double t_final);
 
+/* The k-th of the 3 * ndim kernel launches that make up one gpweno_step
+ * (stage k / ndim + 1, direction k % ndim), enqueued on its own. Enqueuing
+ * k = 0 .. 3 ndim - 1 in order performs exactly one step, with the end time and
+ * step limit left as the last gpweno_step / gpweno_run set them. For
+ * instrumentation (e.g. timing each kernel with events on the context's stream).
+ * Errors: EINVAL for k out of range, ESTATE if not bound. */
+int gpweno_step_kernel(gpweno_ctx *ctx, int k);
+
 /* Advances until t >= t_final or max_steps more steps were taken (max_steps < 0:
  * no limit). Blocking. Steps are replayed from captured HIP graphs. On return
  * *nsteps_out (nullable) holds the steps taken by this call and *t_out (nullable)
  * the time reached. Returns ENONPHYS if a stage produced rho <= 0, p <= 0 or a
- * NaN (the state then holds the failing stage's output). */
+ * NaN; the remaining launches of that step are skipped and no further step
+ * starts, so the state then holds either the state at the start of the
+ * failing step (failure in stage 1 or 2) or that step's non-physical output
+ * (stage 3). gpweno_set_time clears the condition. */
 int gpweno_run(gpweno_ctx *ctx, double t_final, long max_steps, long *nsteps_out, double *t_out);
 
 /* Blocking: current time, the last step's dt, and the total step count

@@ -69,6 +69,7 @@ def lib():
         L.gpweno_get_time.argtypes = [vp, _dp, _dp, ctypes.POINTER(ctypes.c_long)]
         L.gpweno_rhs.argtypes = [vp, vp, vp]
         L.gpweno_rhs_dir.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int]
+        L.gpweno_step_kernel.argtypes = [vp, ctypes.c_int]
         L.gpweno_conserved_sums.argtypes = [vp, _dp]
         L.gpweno_compute_tables.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp, _dp]
         L.gpweno_last_error.argtypes = [vp]
@@ -186,6 +187,10 @@ class Solver:
     # -- time stepping ---------------------------------------------------------
     def step(self, t_final):
         _check(lib().gpweno_step(self._ctx, t_final), self._ctx)
+
+    def step_kernel(self, k):
+        """Enqueue the k-th of the 3*ndim launches of a step (instrumentation)."""
+        _check(lib().gpweno_step_kernel(self._ctx, k), self._ctx)
 
     def run(self, t_final, max_steps=-1):
         """Blocking: advance to t_final (or max_steps more steps). Returns (nsteps, t)."""

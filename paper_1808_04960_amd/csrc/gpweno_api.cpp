@@ -2,12 +2,12 @@
 //
 // A context holds the grid, the pre-simulation tables (binary128 -> float64 /
 // float32), the options and a small device control block. The caller binds its
-// own device state and workspace. A step is a fixed sequence of launches on the
-// context's stream:
-//   dt kernel (reads the CFL speed of U^n, writes dt, advances t)
-//   stage k = 1..3: one sweep per direction; the last direction of each stage
-//   forms the SSP-RK3 stage output, stage 3 writes U^{n+1} in place and
-//   reduces the CFL speed of U^{n+1} for the next step.
+// own device state and workspace. A step is a fixed sequence of 3 * ndim sweep
+// launches on the context's stream: stage k = 1..3, one sweep per direction.
+// Every sweep derives the step's dt (CFL speed of U^n) from the control block;
+// the last direction of each stage forms the SSP-RK3 stage output; stage 3
+// writes U^{n+1} in place, reduces its CFL speed for the next step, and its
+// last block advances t and the step count.
 // Because dt, t and the stop condition live on the device, a run replays a
 // captured HIP graph of several steps and synchronises once per replay.
 #include <hip/hip_runtime.h>
@@ -108,34 +108,38 @@ gpw::SweepArgs<Real> base_args(const gpweno_ctx* c, int dir) {
 
 // One sweep launch (direction dir) in the configured precision.
 int launch(gpweno_ctx* c, int dir, const double* in, const double* un, double* acc, double* out, int stage,
-           int use_ctl, hipStream_t s) {
+           bool fin, bool first, bool step_start, hipStream_t s) {
     const bool fp32 = c->opt.precision == GPWENO_FP32;
     hipError_t e;
     if (fp32) {
         auto a = base_args<float>(c, dir);
         a.U = in; a.Un = un; a.dU = acc; a.Uout = out;
-        a.first = dir == 0; a.last = dir == c->grid.ndim - 1; a.stage = stage; a.use_ctl = use_ctl;
-        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, true, &a, s);
+        a.first = first; a.stage = stage; a.step_start = step_start;
+        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, true, fin, &a, s);
     } else {
         auto a = base_args<double>(c, dir);
         a.U = in; a.Un = un; a.dU = acc; a.Uout = out;
-        a.first = dir == 0; a.last = dir == c->grid.ndim - 1; a.stage = stage; a.use_ctl = use_ctl;
-        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, false, &a, s);
+        a.first = first; a.stage = stage; a.step_start = step_start;
+        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, false, fin, &a, s);
     }
     if (e != hipSuccess) return fail(c, GPWENO_EHIP, "sweep launch (dir %d): %s", dir, hipGetErrorString(e));
     return GPWENO_OK;
 }
 
-int enqueue_step(gpweno_ctx* c, hipStream_t s) {
-    hipError_t e = gpw::launch_dt(c->d_ctl, s);
-    if (e != hipSuccess) return fail(c, GPWENO_EHIP, "dt launch: %s", hipGetErrorString(e));
+// The k-th launch of a step: stage k / ndim + 1, direction k % ndim.
+int launch_step_kernel(gpweno_ctx* c, int k, hipStream_t s) {
+    const int ndim = c->grid.ndim;
+    const int stage = k / ndim + 1, dir = k % ndim;
     const double* ins[3] = {c->state, c->U1, c->U2};
     double* outs[3] = {c->U1, c->U2, c->state};
-    for (int stage = 1; stage <= 3; ++stage) {
-        for (int dir = 0; dir < c->grid.ndim; ++dir) {
-            int st = launch(c, dir, ins[stage - 1], c->state, c->dU, outs[stage - 1], stage, 1, s);
-            if (st) return st;
-        }
+    return launch(c, dir, ins[stage - 1], c->state, c->dU, outs[stage - 1], stage, dir == ndim - 1, dir == 0,
+                  k == 0, s);
+}
+
+int enqueue_step(gpweno_ctx* c, hipStream_t s) {
+    for (int k = 0; k < 3 * c->grid.ndim; ++k) {
+        int st = launch_step_kernel(c, k, s);
+        if (st) return st;
     }
     return GPWENO_OK;
 }
@@ -407,7 +411,7 @@ int gpweno_rhs(gpweno_ctx* c, const double* d_U, double* d_L) {
     const char *u = reinterpret_cast<const char*>(d_U), *l = reinterpret_cast<const char*>(d_L);
     if (u < l + bytes && l < u + bytes) return fail(c, GPWENO_EINVAL, "input and output overlap");
     for (int dir = 0; dir < c->grid.ndim; ++dir) {
-        int st = launch(c, dir, d_U, d_U, d_L, d_L, 0, 0, user_stream(c));
+        int st = launch(c, dir, d_U, d_U, d_L, d_L, 0, false, dir == 0, false, user_stream(c));
         if (st) return st;
     }
     return GPWENO_OK;
@@ -420,21 +424,14 @@ int gpweno_rhs_dir(gpweno_ctx* c, int dir, const double* d_U, double* d_L, int a
     const size_t bytes = sizeof(double) * (size_t)c->nv * (size_t)c->ncell;
     const char *u = reinterpret_cast<const char*>(d_U), *l = reinterpret_cast<const char*>(d_L);
     if (u < l + bytes && l < u + bytes) return fail(c, GPWENO_EINVAL, "input and output overlap");
-    const bool fp32 = c->opt.precision == GPWENO_FP32;
-    hipError_t e;
-    if (fp32) {
-        auto a = base_args<float>(c, dir);
-        a.U = d_U; a.Un = d_U; a.dU = d_L; a.Uout = d_L;
-        a.first = accumulate ? 0 : 1; a.last = 0; a.stage = 0; a.use_ctl = 0;
-        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, true, &a, user_stream(c));
-    } else {
-        auto a = base_args<double>(c, dir);
-        a.U = d_U; a.Un = d_U; a.dU = d_L; a.Uout = d_L;
-        a.first = accumulate ? 0 : 1; a.last = 0; a.stage = 0; a.use_ctl = 0;
-        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, false, &a, user_stream(c));
-    }
-    if (e != hipSuccess) return fail(c, GPWENO_EHIP, "sweep launch (dir %d): %s", dir, hipGetErrorString(e));
-    return GPWENO_OK;
+    return launch(c, dir, d_U, d_U, d_L, d_L, 0, false, accumulate == 0, false, user_stream(c));
+}
+
+int gpweno_step_kernel(gpweno_ctx* c, int k) {
+    if (!c) return fail(nullptr, GPWENO_EINVAL, "NULL context");
+    if (!c->state) return fail(c, GPWENO_ESTATE, "no state bound");
+    if (k < 0 || k >= 3 * c->grid.ndim) return fail(c, GPWENO_EINVAL, "k must be in [0, 3 ndim)");
+    return launch_step_kernel(c, k, user_stream(c));
 }
 
 int gpweno_conserved_sums(gpweno_ctx* c, double* out) {

@@ -6,21 +6,27 @@
 
 namespace gpw {
 
-// Control block in device memory. Written by the time-step kernel and read by
-// the sweeps, so a captured sequence of steps needs no host involvement.
+// Control block in device memory. Every sweep of a step derives the step's dt
+// and its go/no-go decision from these fields, which change only at the end of
+// a step (by the last block of the step's final sweep), so a captured sequence
+// of steps needs no host involvement and no separate time-step kernel.
 struct Ctl {
-    double t;               // time reached after the step in flight
-    double dt;              // time step of the step in flight
+    double t;               // time at the start of the next step
+    double dt;              // time step of the last completed step
     double t_final;         // stop time of the current run
     double cfl;             // CFL number
     double fixed_dt;        // > 0: fixed time step
-    unsigned long long speed_bits;  // max_i sum_d (|u_d|+c)/dx_d of the current state,
-                                    // bit image of a non-negative double (atomic max)
+    unsigned long long speed[2];  // max_i sum_d (|u_d|+c)/dx_d, bit image of a non-negative
+                                  // double (atomic max); speed[parity] belongs to the state
+                                  // at the start of the next step, the other slot is filled
+                                  // by the step in flight
     long long nsteps;       // steps taken so far
-    long long step_limit;   // stop once nsteps reaches this
-    int halt;               // 1: the step in flight is skipped
+    long long step_limit;   // a step starts only while nsteps < step_limit
+    int parity;             // which speed slot is current
     int err;                // 1: a stage produced rho <= 0, p <= 0 or NaN
     long long bad_cell;     // smallest cell index of such a failure
+    unsigned int ticket;    // blocks of the step's final sweep that have finished
+    unsigned int pad;
     double sums[8];         // conserved sums (reduction output)
 };
 
@@ -47,16 +53,15 @@ struct SweepArgs {
     double inv_dx_all[3];
     double gamma;
     int first;          // first direction: the accumulator starts at zero
-    int last;           // last direction: finish the stage
     int stage;          // 0: right-hand side only; 1..3: SSP-RK3 stage
     int positivity;     // positivity fallback of the Riemann states
-    int use_ctl;        // 1: honour ctl->halt and read dt from ctl
+    int step_start;     // first sweep of a step: clears the next speed slot
     Tab<Real> tab;
 };
 
-// Launchers (defined in gpweno_kernels.hip).
-hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, const void* args, hipStream_t s);
-hipError_t launch_dt(Ctl* ctl, hipStream_t s);
+// Launchers (defined in gpweno_kernels.hip). fin: the sweep finishes an RK
+// stage (last direction of stages 1..3); otherwise it accumulates into dU.
+hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, const void* args, hipStream_t s);
 hipError_t launch_set_run(Ctl* ctl, double t_final, long long step_limit, hipStream_t s);
 hipError_t launch_set_time(Ctl* ctl, double t, long long nsteps, double cfl, double fixed_dt, hipStream_t s);
 hipError_t launch_speed(int ndim, const double* U, long long ncell, const int n[3], const double inv_dx[3],

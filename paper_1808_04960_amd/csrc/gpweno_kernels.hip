@@ -56,17 +56,54 @@ __host__ __device__ constexpr int cons_slot(int k) {
          : 1 + t2_axis(DIR);
 }
 
-template <typename Real> __device__ __forceinline__ Real fdiv(Real a, Real b);
-template <> __device__ __forceinline__ double fdiv<double>(double a, double b) { return a / b; }
-template <> __device__ __forceinline__ float fdiv<float>(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+// Reciprocal and reciprocal square root. float: the hardware approximations
+// (about 1 ulp). double: the hardware approximation refined by two Newton-Raphson
+// steps, r <- r + r (1 - x r) and y <- y + y (1 - x y^2)/2, each of which squares
+// the relative error, giving float64 accuracy to within an ulp or two; cheaper
+// than the IEEE division and square-root sequences. Arguments are positive and
+// normal wherever these are used on a selected value.
+template <typename Real> __device__ __forceinline__ Real frcp(Real x);
+template <> __device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double frcp<double>(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+template <typename Real> __device__ __forceinline__ Real frsq(Real x);
+template <> __device__ __forceinline__ float frsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ __forceinline__ double frsq<double>(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
 
-template <typename Real> __device__ __forceinline__ Real fsqrt(Real a);
-template <> __device__ __forceinline__ double fsqrt<double>(double a) { return sqrt(a); }
-template <> __device__ __forceinline__ float fsqrt<float>(float a) { return __builtin_amdgcn_sqrtf(a); }
-
+// Periodic index. For n >= 64 every index a sweep forms lies in [-n, 2n), so a
+// compare-and-add suffices; shorter axes (tests) take the general modulo.
 __device__ __forceinline__ int wrap(int x, int n) {
+    if (n >= WAVE) {
+        x += (x < 0) ? n : 0;
+        return x - ((x >= n) ? n : 0);
+    }
     int r = x % n;
     return r < 0 ? r + n : r;
+}
+
+// Time step of the step in flight and whether it runs. Every sweep of a step
+// reads the same control-block values (they change only when the step ends),
+// so all of them take the same decision and the same dt.
+__device__ __forceinline__ bool step_go(const Ctl* c, double& t0, double& dt, int& par) {
+    t0 = c->t;
+    par = c->parity;
+    if (c->err || !(t0 < c->t_final) || c->nsteps >= c->step_limit) return false;
+    const double speed = __longlong_as_double((long long)c->speed[par]);
+    double d = c->fixed_dt > 0.0 ? c->fixed_dt : c->cfl / speed;
+    if (t0 + d > c->t_final) d = c->t_final - t0;
+    dt = d;
+    return true;
 }
 
 // Conserved -> primitive in the frame rotated to DIR: (rho, u_n[, u_t1[, u_t2]], p).
@@ -75,12 +112,13 @@ __device__ __forceinline__ void cons_to_rot(const double* __restrict__ U, long l
                                             double gamma, double q[2 + NDIM]) {
     constexpr int NV = 2 + NDIM;
     const double rho = U[cell];
+    const double irho = frcp(rho);
     double mom[3] = {0.0, 0.0, 0.0}, vel[3] = {0.0, 0.0, 0.0};
     double ke = 0.0;
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) {
         mom[d] = U[(1 + d) * ncell + cell];
-        vel[d] = mom[d] / rho;
+        vel[d] = mom[d] * irho;
         ke += vel[d] * mom[d];
     }
     const double E = U[(NV - 1) * ncell + cell];
@@ -126,7 +164,7 @@ __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Re
     Real sp = Real(0), sm = Real(0), accp = Real(0), accm = Real(0);
 #pragma unroll
     for (int m = 0; m <= R; ++m) {
-        const Real r = fdiv(emin, e[m]);
+        const Real r = emin * frcp(e[m]);
         const Real w = r * r;
         const Real op = T.gp[m] * w;
         const Real om = T.gm[m] * w;
@@ -135,8 +173,10 @@ __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Re
         accp = fma(op, cp[m], accp);
         accm = fma(om, cm[m], accm);
     }
-    qp = fdiv(accp, sp);
-    qm = fdiv(accm, sm);
+    // both normalisations from one reciprocal: 1/sp = sm/(sp sm), 1/sm = sp/(sp sm)
+    const Real inv = frcp(sp * sm);
+    qp = accp * (sm * inv);
+    qm = accm * (sp * inv);
 }
 
 // Riemann states of the cell at lane position l: stencil entries l .. l+2R of a
@@ -160,9 +200,10 @@ __device__ __forceinline__ void reconstruct(const Real* __restrict__ s, int fs, 
         for (int j = 0; j < NS; ++j) v[k][j] = s[k * fs + l + j];
 
     const Real rho = v[0][R], p = v[NV - 1][R];
-    const Real c2 = fdiv(gamma * p, rho);
-    const Real c = fsqrt(c2);
-    const Real ic = fdiv(Real(1), c);
+    const Real irho = frcp(rho);
+    const Real c2 = gamma * p * irho;
+    const Real ic = frsq(c2);
+    const Real c = c2 * ic;
     const Real ic2 = ic * ic;
     const Real a = Real(0.5) * rho * ic;
     const Real b = Real(0.5) * ic2;
@@ -184,7 +225,7 @@ __device__ __forceinline__ void reconstruct(const Real* __restrict__ s, int fs, 
         for (int j = 0; j < NS; ++j) f[j] = v[2 + t][j];
         gp_weno<R, Real>(f, T, qp[2 + t], qm[2 + t]);
     }
-    const Real cr = c * fdiv(Real(1), rho);
+    const Real cr = c * irho;
     qp[0] = acm_p + ent_p + acp_p;
     qm[0] = acm_m + ent_m + acp_m;
     qp[1] = cr * (acp_p - acm_p);
@@ -238,28 +279,36 @@ __device__ __forceinline__ void hllc(const Real (&qL)[2 + NDIM], const Real (&qR
     flux_of<NDIM, Real>(qR, inv_gm1, FR, UR);
     const Real rL = qL[0], uL = qL[1], pL = qL[NV - 1];
     const Real rR = qR[0], uR = qR[1], pR = qR[NV - 1];
-    const Real cL = fsqrt(fdiv(gamma * pL, rL));
-    const Real cR = fsqrt(fdiv(gamma * pR, rR));
+    // 1/rho_L and 1/rho_R from one reciprocal
+    const Real irLR = frcp(rL * rR);
+    const Real c2L = gamma * pL * (rR * irLR);
+    const Real c2R = gamma * pR * (rL * irLR);
+    const Real cL = c2L * frsq(c2L);
+    const Real cR = c2R * frsq(c2R);
     const Real SL = fmin(uL - cL, uR - cR);
     const Real SR = fmax(uL + cL, uR + cR);
     const Real mL = rL * (SL - uL);
     const Real mR = rR * (SR - uR);
-    const Real Ss = fdiv(pR - pL + uL * mL - uR * mR, mL - mR);
+    const Real Ss = (pR - pL + uL * mL - uR * mR) * frcp(mL - mR);
     const bool left = Ss >= Real(0);
-    const Real r = left ? rL : rR;
     const Real u = left ? uL : uR;
     const Real p = left ? pL : pR;
     const Real S = left ? SL : SR;
     const Real m = left ? mL : mR;
-    const Real fac = fdiv(m, S - Ss);
-    const Real ir = fdiv(Real(1), r);
+    // with X = m (S - S*): m/(S - S*) = m^2/X, 1/m = (S - S*)/X and
+    // 1/rho = (S - u)/m = (S - u)(S - S*)/X, all from one reciprocal
+    const Real dS = S - Ss;
+    const Real iX = frcp(m * dS);
+    const Real fac = m * m * iX;
+    const Real im = dS * iX;
+    const Real ir = (S - u) * im;
     Real Us[NV], Fs[NV];
     Us[0] = fac;
     Us[1] = fac * Ss;
 #pragma unroll
     for (int t = 0; t < NDIM - 1; ++t) Us[2 + t] = fac * (left ? qL[2 + t] : qR[2 + t]);
     const Real EK = left ? UL[NV - 1] : UR[NV - 1];
-    Us[NV - 1] = fac * (EK * ir + (Ss - u) * (Ss + fdiv(p, m)));
+    Us[NV - 1] = fac * (EK * ir + (Ss - u) * (Ss + p * im));
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         const Real Fk = left ? FL[k] : FR[k];
@@ -278,7 +327,8 @@ struct SweepCfg {
     static constexpr int WPB = (DIR == 0) ? 4 : 8;  // pencils (waves) per block
     static constexpr int THREADS = WPB * WAVE;
     static constexpr size_t IN_BYTES = sizeof(Real) * NV * WPB * PITCH;
-    static constexpr size_t OUT_BYTES = (DIR == 0) ? 0 : sizeof(double) * NV * TOUT * WPB;
+    static constexpr int OPITCH = WPB + 1;  // padded row of the output tile (no bank conflicts)
+    static constexpr size_t OUT_BYTES = (DIR == 0) ? 0 : sizeof(double) * NV * TOUT * OPITCH;
     static constexpr size_t SMEM = IN_BYTES > OUT_BYTES ? IN_BYTES : OUT_BYTES;
 };
 
@@ -291,39 +341,39 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
     return v;
 }
 
-// Finish one cell: accumulate the direction's contribution and, in the last
-// direction of an RK stage, form the stage output (SSP-RK3, Shu-Osher form),
-// check it is physical and (stage 3) track the CFL speed of the new state.
-template <int NDIM, typename Real>
+// Finish one cell. FIN = false: accumulate the direction's contribution into
+// dU. FIN = true (last direction of an RK stage): form the stage output
+// (SSP-RK3, Shu-Osher form), check it is physical and, in stage 3, track the
+// CFL speed of the new state.
+template <int NDIM, bool FIN, typename Real>
 __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long cell, const double (&d)[2 + NDIM],
-                                            double dt, unsigned long long& smax) {
+                                            const double (&pd)[2 + NDIM], const double (&pu)[2 + NDIM],
+                                            const double (&pn)[2 + NDIM], double dt, unsigned long long& smax) {
     constexpr int NV = 2 + NDIM;
     const long long nc = a.ncell;
-    if (a.stage == 0 || !a.last) {
+    if (!FIN) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            const double v = a.first ? d[k] : a.dU[k * nc + cell] + d[k];
-            a.dU[k * nc + cell] = v;
-        }
+        for (int k = 0; k < NV; ++k) a.dU[k * nc + cell] = a.first ? d[k] : pd[k] + d[k];
         return;
     }
     double o[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-        const double L = a.first ? d[k] : a.dU[k * nc + cell] + d[k];
-        const double adv = a.U[k * nc + cell] + dt * L;
+        const double L = a.first ? d[k] : pd[k] + d[k];
+        const double adv = pu[k] + dt * L;
         double out;
         if (a.stage == 1) out = adv;
-        else if (a.stage == 2) out = 0.75 * a.Un[k * nc + cell] + 0.25 * adv;
-        else out = (1.0 / 3.0) * a.Un[k * nc + cell] + (2.0 / 3.0) * adv;
+        else if (a.stage == 2) out = 0.75 * pn[k] + 0.25 * adv;
+        else out = (1.0 / 3.0) * pn[k] + (2.0 / 3.0) * adv;
         a.Uout[k * nc + cell] = out;
         o[k] = out;
     }
     const double rho = o[0];
+    const double irho = frcp(rho);
     double ke = 0.0, vel[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int dd = 0; dd < NDIM; ++dd) {
-        vel[dd] = o[1 + dd] / rho;
+        vel[dd] = o[1 + dd] * irho;
         ke += vel[dd] * o[1 + dd];
     }
     const double p = (a.gamma - 1.0) * (o[NV - 1] - 0.5 * ke);
@@ -332,7 +382,7 @@ __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long 
         atomicMin(&a.ctl->bad_cell, cell);
     }
     if (a.stage == 3) {
-        const double c = sqrt(a.gamma * p / rho);
+        const double c = sqrt(a.gamma * p * irho);
         double s = 0.0;
 #pragma unroll
         for (int dd = 0; dd < NDIM; ++dd) s += (fabs(vel[dd]) + c) * a.inv_dx_all[dd];
@@ -342,7 +392,7 @@ __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long 
     }
 }
 
-template <int NDIM, int DIR, int R, typename Real>
+template <int NDIM, int DIR, int R, typename Real, bool FIN>
 __global__ void __launch_bounds__(DIR == 0 ? 4 * WAVE : 8 * WAVE)
 sweep_kernel(const SweepArgs<Real> a) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
@@ -352,15 +402,44 @@ sweep_kernel(const SweepArgs<Real> a) {
     Real* sV = reinterpret_cast<Real*>(smem);
     double* sO = reinterpret_cast<double*>(smem);
 
-    if (a.use_ctl && a.ctl->halt) return;
-    const double dt = a.use_ctl ? a.ctl->dt : 0.0;
+    double t0 = 0.0, dt = 0.0;
+    int par = 0;
+    if (a.stage > 0) {
+        if (!step_go(a.ctl, t0, dt, par)) return;
+        if (a.step_start && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->speed[1 - par] = 0ull;
+    }
 
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int w = tid / WAVE;
     const int N = a.n[DIR];
-    const int seg = blockIdx.x % a.nseg;
-    const long long grp = blockIdx.x / a.nseg;
+    // XCD-aware block order. Workgroups are dealt to the 8 XCDs round-robin by
+    // index; renumber them so that each XCD gets one contiguous range of logical
+    // blocks. Logical order is "band-major" in every direction (rows for x
+    // sweeps, runs along y / z for y / z sweeps), so an XCD keeps working on
+    // roughly the same slab of the grid in every sweep, and the slab's stage
+    // states and accumulator stay in that XCD's L2 between kernels.
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned q8 = nb >> 3, r8 = nb & 7u, xcd = b & 7u;
+    const long long L = (long long)(xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3));
+    int seg;
+    long long grp;       // DIR 0: row group; else x group
+    long long other = 0; // z for DIR 1, y for DIR 2
+    const int nxb = (a.n[0] + WPB - 1) / WPB;
+    if (DIR == 0) {
+        seg = (int)(L % a.nseg);
+        grp = L / a.nseg;
+    } else if (DIR == 1) {
+        grp = L % nxb;
+        const long long t = L / nxb;
+        seg = (int)(t % a.nseg);
+        other = t / a.nseg;
+    } else {
+        grp = L % nxb;
+        const long long t = L / nxb;
+        other = t % a.n[1];
+        seg = (int)(t / a.n[1]);
+    }
     const int s0 = (int)((long long)seg * N / a.nseg);
     const int tseg = (int)((long long)(seg + 1) * N / a.nseg) - s0;
     const int sbase = s0 - LEFT - R;
@@ -378,9 +457,7 @@ sweep_kernel(const SweepArgs<Real> a) {
         blk_base = row0 * a.n[0];
         ncol_valid = (int)((nrows - row0) < WPB ? (nrows - row0) : WPB);
     } else {
-        const int nxb = (a.n[0] + WPB - 1) / WPB;
-        const int xb = (int)(grp % nxb) * WPB;
-        const long long other = grp / nxb;  // z for DIR 1, y for DIR 2
+        const int xb = (int)grp * WPB;
         stride = (DIR == 1) ? (long long)a.n[0] : (long long)a.n[0] * a.n[1];
         blk_base = xb + other * (DIR == 1 ? (long long)a.n[0] * a.n[1] : (long long)a.n[0]);
         ncol_valid = (a.n[0] - xb) < WPB ? (a.n[0] - xb) : WPB;
@@ -388,22 +465,48 @@ sweep_kernel(const SweepArgs<Real> a) {
     // column c of the block starts at blk_base + c * cstride
     const long long cstride = (DIR == 0) ? (long long)a.n[0] : 1;
 
+    // ---- epilogue operands, fetched now so their latency hides behind the sweep
+    // Each thread finishes at most one cell: its own lane's cell in x sweeps,
+    // one cell of the transposed output tile in y / z sweeps.
+    static_assert(DIR == 0 || TOUT * WPB <= THREADS, "one epilogue cell per thread");
+    long long ecell = -1;
+    if (DIR == 0) {
+        if (w < ncol_valid && lane >= LEFT && lane < LEFT + tseg)
+            ecell = blk_base + w * cstride + (s0 + lane - LEFT);
+    } else {
+        const int row = tid / WPB, c = tid % WPB;
+        if (row < tseg && c < ncol_valid) ecell = blk_base + c * cstride + (long long)(s0 + row) * stride;
+    }
+    double pd[NV], pu[NV], pn[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) pd[k] = pu[k] = pn[k] = 0.0;
+    if (ecell >= 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            if (!a.first) pd[k] = a.dU[k * nc + ecell];
+            if (FIN) pu[k] = a.U[k * nc + ecell];
+            if (FIN && a.stage >= 2) pn[k] = a.Un[k * nc + ecell];
+        }
+    }
+
     // ---- load the stencil tile (rotated primitive variables) into LDS --------
     {
         constexpr int FS = WPB * PITCH;
         if (DIR == 0) {
-            const int c = w;
-            for (int idx = lane; idx < SLEN; idx += WAVE) {
+            // the block's rows are loaded as one flat range, so only the last
+            // wave takes a partial second round
+            for (int idx = tid; idx < WPB * SLEN; idx += THREADS) {
+                const int c = idx / SLEN, pos = idx - c * SLEN;
                 double q[NV];
                 if (c < ncol_valid) {
-                    const long long cell = blk_base + c * cstride + wrap(sbase + idx, N);
+                    const long long cell = blk_base + c * cstride + wrap(sbase + pos, N);
                     cons_to_rot<NDIM, DIR>(a.U, nc, cell, gamma, q);
                 } else {
 #pragma unroll
                     for (int k = 0; k < NV; ++k) q[k] = (k == 0 || k == NV - 1) ? 1.0 : 0.0;
                 }
 #pragma unroll
-                for (int k = 0; k < NV; ++k) sV[k * FS + c * PITCH + idx] = (Real)q[k];
+                for (int k = 0; k < NV; ++k) sV[k * FS + c * PITCH + pos] = (Real)q[k];
             }
         } else {
             const int c = tid % WPB;
@@ -451,29 +554,29 @@ sweep_kernel(const SweepArgs<Real> a) {
     unsigned long long smax = 0;
     const bool lane_out = lane >= LEFT && lane < LEFT + tseg;
     if (DIR == 0) {
-        if (w < ncol_valid && lane_out) {
-            const long long cell = blk_base + w * cstride + (s0 + lane - LEFT);
-            finish_cell<NDIM, Real>(a, cell, dcons, dt, smax);
-        }
+        if (ecell >= 0) finish_cell<NDIM, FIN, Real>(a, ecell, dcons, pd, pu, pn, dt, smax);
     } else {
         __syncthreads();  // every wave is done reading the stencil tile
         if (lane_out) {
 #pragma unroll
-            for (int k = 0; k < NV; ++k) sO[(k * TOUT + (lane - LEFT)) * WPB + w] = dcons[k];
+            for (int k = 0; k < NV; ++k) sO[(k * TOUT + (lane - LEFT)) * C::OPITCH + w] = dcons[k];
         }
         __syncthreads();
-        for (int idx = tid; idx < tseg * WPB; idx += THREADS) {
-            const int row = idx / WPB, c = idx % WPB;
-            if (c < ncol_valid) {
-                double d[NV];
+        if (ecell >= 0) {
+            const int row = tid / WPB, c = tid % WPB;
+            double d[NV];
 #pragma unroll
-                for (int k = 0; k < NV; ++k) d[k] = sO[(k * TOUT + row) * WPB + c];
-                const long long cell = blk_base + c * cstride + (long long)(s0 + row) * stride;
-                finish_cell<NDIM, Real>(a, cell, d, dt, smax);
-            }
+            for (int k = 0; k < NV; ++k) d[k] = sO[(k * TOUT + row) * C::OPITCH + c];
+            finish_cell<NDIM, FIN, Real>(a, ecell, d, pd, pu, pn, dt, smax);
         }
     }
-    if (a.stage == 3 && a.last && a.use_ctl) {
+    if (FIN && a.stage == 3) {
+        // CFL speed of the new state into the next step's slot; then the last
+        // block to take a ticket closes the step. It writes only values every
+        // block derived at its start from the unchanged control block, and the
+        // next kernel on the stream sees them (and every speed update) after
+        // this kernel completes, so no fence is needed: an agent-scope fence
+        // would write back and invalidate the L2 of the XCD once per block.
         smax = wave_max_u64(smax);
         if (lane == 0) sred[w] = smax;
         __syncthreads();
@@ -481,7 +584,16 @@ sweep_kernel(const SweepArgs<Real> a) {
             unsigned long long m = sred[0];
 #pragma unroll
             for (int i = 1; i < WPB; ++i) m = sred[i] > m ? sred[i] : m;
-            atomicMax(&a.ctl->speed_bits, m);
+            Ctl* c = a.ctl;
+            atomicMax(&c->speed[1 - par], m);
+            const unsigned int done = atomicAdd(&c->ticket, 1u);
+            if (done == gridDim.x - 1) {
+                c->t = t0 + dt;
+                c->dt = dt;
+                c->nsteps = c->nsteps + 1;
+                c->parity = 1 - par;
+                c->ticket = 0u;
+            }
         }
     }
 }
@@ -490,29 +602,11 @@ sweep_kernel(const SweepArgs<Real> a) {
 // Time-step control and reductions
 // ---------------------------------------------------------------------------
 
-// dt = cfl / max speed (or the fixed dt), clipped so that t does not pass
-// t_final; sets halt when the run is over (dt then keeps the last step's value).
-__global__ void dt_kernel(Ctl* c) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double t = c->t;
-    if (c->err || !(t < c->t_final) || c->nsteps >= c->step_limit) {
-        c->halt = 1;
-        return;
-    }
-    const double speed = __longlong_as_double((long long)c->speed_bits);
-    double dt = c->fixed_dt > 0.0 ? c->fixed_dt : c->cfl / speed;
-    if (t + dt > c->t_final) dt = c->t_final - t;
-    c->dt = dt;
-    c->t = t + dt;
-    c->nsteps += 1;
-    c->halt = 0;
-    c->speed_bits = 0ull;
-}
-
 __global__ void set_run_kernel(Ctl* c, double t_final, long long step_limit) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     c->t_final = t_final;
     c->step_limit = step_limit;
+    c->ticket = 0u;
 }
 
 __global__ void set_time_kernel(Ctl* c, double t, long long nsteps, double cfl, double fixed_dt) {
@@ -522,10 +616,12 @@ __global__ void set_time_kernel(Ctl* c, double t, long long nsteps, double cfl, 
     c->nsteps = nsteps;
     c->cfl = cfl;
     c->fixed_dt = fixed_dt;
-    c->halt = 0;
     c->err = 0;
     c->bad_cell = LLONG_MAX;
-    c->speed_bits = 0ull;
+    c->speed[0] = 0ull;
+    c->speed[1] = 0ull;
+    c->parity = 0;
+    c->ticket = 0u;
 }
 
 // CFL speed max_i sum_d (|u_d| + c)/dx_d of a state, with the physical check.
@@ -563,7 +659,7 @@ __global__ void __launch_bounds__(256) speed_kernel(const double* __restrict__ U
     if (threadIdx.x == 0) {
         unsigned long long m = sred[0];
         for (int i = 1; i < 4; ++i) m = sred[i] > m ? sred[i] : m;
-        atomicMax(&ctl->speed_bits, m);
+        atomicMax(&ctl->speed[ctl->parity], m);
     }
     (void)n0;
     (void)n1;
@@ -600,7 +696,7 @@ __global__ void sums_final_kernel(const double* __restrict__ partials, int npart
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int NDIM, int DIR, int R, typename Real>
+template <int NDIM, int DIR, int R, typename Real, bool FIN>
 hipError_t launch_one(const void* args, hipStream_t s) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     const SweepArgs<Real>& a = *static_cast<const SweepArgs<Real>*>(args);
@@ -613,45 +709,45 @@ hipError_t launch_one(const void* args, hipStream_t s) {
     }
     const long long blocks = groups * a.nseg;
     if (blocks <= 0 || blocks > INT_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sweep_kernel<NDIM, DIR, R, Real>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
+    hipLaunchKernelGGL((sweep_kernel<NDIM, DIR, R, Real, FIN>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
+// A finishing kernel exists only for the last direction.
 template <int NDIM, int R, typename Real>
-hipError_t launch_dir(int dir, const void* args, hipStream_t s) {
-    if (dir == 0) return launch_one<NDIM, 0, R, Real>(args, s);
-    if (NDIM >= 2 && dir == 1) return launch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real>(args, s);
-    if (NDIM == 3 && dir == 2) return launch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real>(args, s);
+hipError_t launch_dir(int dir, bool fin, const void* args, hipStream_t s) {
+    if (fin) {
+        if (dir != NDIM - 1) return hipErrorInvalidValue;
+        return launch_one<NDIM, NDIM - 1, R, Real, true>(args, s);
+    }
+    if (dir == 0) return launch_one<NDIM, 0, R, Real, false>(args, s);
+    if (NDIM >= 2 && dir == 1) return launch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false>(args, s);
+    if (NDIM == 3 && dir == 2) return launch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false>(args, s);
     return hipErrorInvalidValue;
 }
 
 template <int NDIM, typename Real>
-hipError_t launch_r(int dir, int R, const void* args, hipStream_t s) {
+hipError_t launch_r(int dir, int R, bool fin, const void* args, hipStream_t s) {
     switch (R) {
-        case 1: return launch_dir<NDIM, 1, Real>(dir, args, s);
-        case 2: return launch_dir<NDIM, 2, Real>(dir, args, s);
-        case 3: return launch_dir<NDIM, 3, Real>(dir, args, s);
+        case 1: return launch_dir<NDIM, 1, Real>(dir, fin, args, s);
+        case 2: return launch_dir<NDIM, 2, Real>(dir, fin, args, s);
+        case 3: return launch_dir<NDIM, 3, Real>(dir, fin, args, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename Real>
-hipError_t launch_nd(int ndim, int dir, int R, const void* args, hipStream_t s) {
+hipError_t launch_nd(int ndim, int dir, int R, bool fin, const void* args, hipStream_t s) {
     switch (ndim) {
-        case 1: return launch_r<1, Real>(dir, R, args, s);
-        case 2: return launch_r<2, Real>(dir, R, args, s);
-        case 3: return launch_r<3, Real>(dir, R, args, s);
+        case 1: return launch_r<1, Real>(dir, R, fin, args, s);
+        case 2: return launch_r<2, Real>(dir, R, fin, args, s);
+        case 3: return launch_r<3, Real>(dir, R, fin, args, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, const void* args, hipStream_t s) {
-    return fp32 ? launch_nd<float>(ndim, dir, R, args, s) : launch_nd<double>(ndim, dir, R, args, s);
-}
-
-hipError_t launch_dt(Ctl* ctl, hipStream_t s) {
-    hipLaunchKernelGGL(dt_kernel, dim3(1), dim3(64), 0, s, ctl);
-    return hipGetLastError();
+hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, const void* args, hipStream_t s) {
+    return fp32 ? launch_nd<float>(ndim, dir, R, fin, args, s) : launch_nd<double>(ndim, dir, R, fin, args, s);
 }
 
 hipError_t launch_set_run(Ctl* ctl, double t_final, long long step_limit, hipStream_t s) {

@@ -1,0 +1,145 @@
+"""Full-size parity at the benchmark-scale configurations, on sampled outputs.
+
+The GPU runs the whole grid in the launch configuration the benchmark times
+(graph-replayed gpweno_run steps, or one right-hand side). The oracle then
+recomputes sampled boxes of cells one box at a time. A cell's right-hand side
+depends only on cells within G = R+3 along each axis, so a box padded by G
+(periodic padding that never reaches the compared interior) gives the oracle
+value exactly. One SSP-RK3 step chains three right-hand sides, so there the
+padding is 3G and the oracle takes the step with the GPU's dt. The dt itself
+is checked against the oracle's CFL rule on the full state.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1808_04960_amd as gw  # noqa: E402
+
+
+def announce(msg):
+    print(f"[gpu-fullsize] {msg}", file=sys.stderr, flush=True)
+
+
+CONFIGS = {
+    "C2-vortex-512": (lambda: inputs.isentropic_vortex_2d(512), 2),
+    "C3-kh-2048x1024": (lambda: inputs.kelvin_helmholtz_2d(2048, 1024), 3),
+    "C4-wave-256": (lambda: inputs.density_wave_3d(256), 2),
+    "C4-vortex-256": (lambda: inputs.isentropic_vortex_3d(256), 2),
+}
+
+
+def box_indices(grid, starts, size, pad):
+    """Per-axis index arrays (slowest axis first, as the state is laid out)."""
+    idx = []
+    for d in reversed(range(grid.ndim)):
+        idx.append(np.arange(starts[d] - pad, starts[d] + size + pad) % grid.n[d])
+    return idx
+
+
+def box_grid(grid, size, pad):
+    n = [size + 2 * pad] * grid.ndim
+    lo = [0.0] * grid.ndim
+    hi = [n[d] * grid.dx[d] for d in range(grid.ndim)]
+    if grid.ndim == 1:
+        return inputs.grid1d(n[0], 0.0, hi[0])
+    if grid.ndim == 2:
+        return inputs.grid2d(n[0], n[1], lo, hi)
+    return inputs.grid3d(n[0], n[1], n[2], lo, hi)
+
+
+def extract(U, idx):
+    return np.ascontiguousarray(U[(slice(None),) + np.ix_(*idx)])
+
+
+def interior(A, ndim, pad, size):
+    sl = (slice(None),) + tuple(slice(pad, pad + size) for _ in range(ndim))
+    return A[sl]
+
+
+def sample_starts(grid, rng, count):
+    """Box corners: one straddling the periodic seam, the rest random."""
+    out = [[grid.n[d] - 3 for d in range(grid.ndim)]]
+    for _ in range(count - 1):
+        out.append([int(rng.integers(0, grid.n[d])) for d in range(grid.ndim)])
+    return out
+
+
+EPS = {"fp64": 2.0**-53, "fp32": 2.0**-24}
+
+
+def flux_scale(g, U, gamma=1.4):
+    rho, vel, p = inputs.cons_to_prim(g, U, gamma)
+    E = U[g.nv - 1]
+    tot = 0.0
+    for d in range(g.ndim):
+        un = vel[d]
+        F = np.abs(rho * un) + np.abs(un * (E + p)) + sum(np.abs(U[1 + e] * un) for e in range(g.ndim)) + np.abs(p)
+        tot += F.sum() / g.dx[d]
+    return float(tot)
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fullsize_rhs_sampled(name, prec):
+    make, R = CONFIGS[name]
+    g, U = make()
+    announce(f"{name} {prec}: full-size right-hand side, n={g.n[:g.ndim]}")
+    dx = g.dx[0]
+    s = gw.Solver(g, R, 12 * dx, 3 * dx, precision=prec, U0=U)
+    L = s.rhs(U)
+    G = R + 3
+    size = 12 if g.ndim < 3 else 6
+    bg = box_grid(g, size, G)
+    o = oracle.OracleSolver(bg, R, 12 * dx, 3 * dx)
+    rng = np.random.default_rng(1)
+    for starts in sample_starts(g, rng, 4):
+        idx = box_indices(g, starts, size, G)
+        Ub = extract(U, idx)
+        ref = interior(o.rhs(Ub), g.ndim, G, size)
+        got = interior(extract(L, idx), g.ndim, G, size)
+        err = float(np.abs(got - ref).sum())
+        bound = 16 * EPS[prec] * flux_scale(bg, interior(Ub, g.ndim, G, size))
+        assert err < bound, (starts, err, bound)
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_fullsize_step_sampled(name, prec, tol):
+    make, R = CONFIGS[name]
+    g, U = make()
+    announce(f"{name} {prec}: one full-size SSP-RK3 step through gpweno_run")
+    dx = g.dx[0]
+    s = gw.Solver(g, R, 12 * dx, 3 * dx, precision=prec, U0=U)
+    n, t = s.run(1e9, max_steps=1)
+    assert n == 1
+    t_gpu, dt_gpu, _ = s.time()
+    assert t_gpu == dt_gpu
+    # the CFL time step of the full state (float64 on both sides)
+    dt_ref = oracle.OracleSolver(g, R, 12 * dx, 3 * dx).dt(U, 0.0, 1e9)
+    assert abs(dt_gpu - dt_ref) <= 1e-14 * dt_ref
+    U1 = s.get_state()
+    G = 3 * (R + 3)
+    size = 10 if g.ndim < 3 else 4
+    bg = box_grid(g, size, G)
+    o = oracle.OracleSolver(bg, R, 12 * dx, 3 * dx)
+    rng = np.random.default_rng(2)
+    num = den = 0.0
+    for starts in sample_starts(g, rng, 4):
+        idx = box_indices(g, starts, size, G)
+        Ub = extract(U, idx)
+        o.step(Ub, dt_gpu)
+        ref = interior(Ub, g.ndim, G, size)
+        got = interior(extract(U1, idx), g.ndim, G, size)
+        num += float(np.abs(got - ref).sum())
+        den += float(np.abs(ref).sum())
+    assert num / den < tol, num / den

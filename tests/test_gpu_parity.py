@@ -213,3 +213,18 @@ def test_fixed_dt_matches_oracle():
     n, _ = s.run(1e9, max_steps=50)
     assert n == 50
     assert rel_l1(s.get_state(), Uo) < 1e-12
+
+
+def test_step_kernels_compose_a_step():
+    """The 3*ndim launches exposed one by one (gpweno_step_kernel) form exactly one step."""
+    announce("step kernels")
+    g, U = inputs.isentropic_vortex_2d(64)
+    a = gw.Solver(g, 2, 12 * g.dx[0], 3 * g.dx[0], U0=U)
+    b = gw.Solver(g, 2, 12 * g.dx[0], 3 * g.dx[0], U0=U)
+    a.step(10.0)
+    for k in range(3 * g.ndim):
+        a.step_kernel(k)
+    a.synchronize()
+    b.run(10.0, max_steps=2)
+    assert a.time() == b.time()
+    assert np.array_equal(a.get_state(), b.get_state())
