@@ -95,7 +95,7 @@ def main():
     ap.add_argument("--solves", type=int, default=5, help="full solves for latency and exact-solution error")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-steps", type=int, default=64, help="instrumented steps for per-kernel timing")
+    ap.add_argument("--kernel-reps", type=int, default=100, help="back-to-back launches per timed kernel")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -139,36 +139,37 @@ def main():
         timing[prec] = el
         log(f"{prec}: {args.steps} steps in {el * 1e3:.2f} ms -> {ncell * 3 * args.steps / el:.4e} cell-updates/s")
 
-    # per-kernel times inside real steps: eager steps launched one kernel at a time
-    # (gpweno_step_kernel), HIP events recorded on the solver's stream between them
+    # per-kernel launch durations: each launch of the step sequence
+    # (gpweno_step_kernel k) repeated back to back between two HIP events on
+    # the solver's stream. Every launch reads and writes the same buffers as in
+    # a step, so a repeat does the same work; the host enqueues while the stream
+    # is held in a bounded spin, so the kernels run back to back.
     nk = 3 * grid.ndim
     kern = {}
     for prec in ("fp32", "fp64"):
         s = solvers[prec]
         real = "float" if prec == "fp32" else "double"
-        s.set_state(U0)
-        s.step(t_run)  # sets the end time and lifts the step limit
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nk + 1)] for _ in range(args.kernel_steps)]
-        # hold the stream in a bounded spin while the host enqueues, so the timed
-        # kernels run back to back instead of at the host's launch rate
-        with torch.cuda.stream(s.stream):
-            torch.cuda._sleep(int(2.4e9 * 0.02))
-        for i in range(args.kernel_steps):
-            for k in range(nk):
-                evs[i][k].record(s.stream)
-                s.step_kernel(k)
-            evs[i][nk].record(s.stream)
-        s.synchronize()
         per_sym = {}
         for k in range(nk):
+            s.set_state(U0)
+            s.step(t_run)  # sets the end time and lifts the step limit
+            s.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            with torch.cuda.stream(s.stream):
+                torch.cuda._sleep(int(2.4e9 * 0.01))
+            e0.record(s.stream)
+            for _ in range(args.kernel_reps):
+                s.step_kernel(k)
+            e1.record(s.stream)
+            e1.synchronize()
             d = k % grid.ndim
             fin = d == grid.ndim - 1
             sym = f"sweep_kernel<{grid.ndim}, {d}, {R}, {real}, {'true' if fin else 'false'}>"
-            for i in range(args.kernel_steps):
-                per_sym.setdefault(sym, []).append(evs[i][k].elapsed_time(evs[i][k + 1]) * 1e-3)
+            per_sym.setdefault(sym, []).append(e0.elapsed_time(e1) / args.kernel_reps * 1e-3)
         for sym, ts in per_sym.items():
-            kern[(prec, sym)] = (float(np.mean(ts)), len(ts) // args.kernel_steps)
-            log(f"{sym}: {np.mean(ts) * 1e6:.1f} us per launch, {len(ts) // args.kernel_steps} per step")
+            kern[(prec, sym)] = (float(np.mean(ts)), len(ts))
+            log(f"{sym}: {np.mean(ts) * 1e6:.1f} us per launch, {len(ts)} per step")
 
     if args.copy_probe:
         nbytes = 1 << 30

@@ -172,6 +172,53 @@ int gpweno_compute_tables(int R, double ell_over_dx, double sigma_over_dx,
                           double *w_plus, double *w_minus, double *gam_plus,
                           double *gam_minus, double *P);
 
+/* Sets the end time and the absolute step limit (step_limit < 0: none) of the
+ * context's runs without stepping (enqueued). gpweno_batch_run honours them;
+ * gpweno_step and gpweno_run set their own. ESTATE if not bound. */
+int gpweno_set_end(gpweno_ctx *ctx, double t_final, long step_limit);
+
+/* ---- Batched execution of many independent problems ------------------------
+ * A batch advances a set of bound contexts together: every launch of the step
+ * sequence covers all problems of a group (same ndim, R, precision and GP
+ * tables) with one kernel whose blocks are dealt problem by problem. Each
+ * problem keeps its own dt, time, end time and step limit in its own control
+ * block; a problem that is done skips its blocks. A block computes exactly
+ * what the single-problem sweep computes for its cells, so each problem's
+ * result does not depend on the rest of the batch.
+ * Serves a request loop (continuous batching): the caller changes the set as
+ * problems arrive and finish (gpweno_batch_set), advances it in chunks of
+ * steps (gpweno_batch_run) and polls progress (gpweno_batch_status).
+ * All calls on a batch, and the contexts' own work, must be ordered on one
+ * stream (pass the contexts' stream). */
+typedef struct gpweno_batch gpweno_batch;
+
+/* Creates an empty batch on the current device. Errors: ENOMEM, EHIP. */
+int gpweno_batch_create(gpweno_batch **out);
+
+/* Sets the batch's problems: n (<= 4096) distinct bound contexts on the batch's
+ * device. Waits for the stream, then uploads the launch descriptors (the
+ * batch owns its device buffers and grows them as needed) and drops the
+ * captured step graph. The contexts must stay alive and bound until they are
+ * removed by the next gpweno_batch_set. n = 0 empties the batch.
+ * Errors: EINVAL (NULL, repeated or unbound context, mixed devices), ENOMEM, EHIP. */
+int gpweno_batch_set(gpweno_batch *b, gpweno_ctx *const *ctxs, int n, void *stream);
+
+/* Enqueues nsteps batched steps (nsteps >= 1) on stream by replaying a captured
+ * graph of one batched step. Errors: EINVAL, EHIP. */
+int gpweno_batch_run(gpweno_batch *b, int nsteps, void *stream);
+
+/* Blocking: for every problem of the set, in set order, its time, last dt, step
+ * count and error flag (1: non-physical state) into host arrays of length n
+ * (each nullable). Errors: EINVAL, EHIP. */
+int gpweno_batch_status(gpweno_batch *b, double *t, double *dt, long *nsteps, int *err, void *stream);
+
+/* Waits for the batch's last stream and frees its resources. NULL is ignored. */
+void gpweno_batch_destroy(gpweno_batch *b);
+
+/* Text of the last failure on this batch (NULL: the thread's last failure of
+ * a call given a NULL batch). Never NULL. */
+const char *gpweno_batch_last_error(const gpweno_batch *b);
+
 /* Text of the last failure on this context (ctx may be NULL for failures of
  * gpweno_init and of calls given a NULL context). Never NULL. */
 const char *gpweno_last_error(const gpweno_ctx *ctx);

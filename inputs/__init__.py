@@ -226,6 +226,9 @@ def mirror(grid: Grid, U, axis: int):
 # --------------------------------------------------------------------------
 @dataclasses.dataclass
 class Request:
+    """One independent Euler problem of a serving stream. The initial state is
+    built on demand (``state()``) so a long stream costs no memory up front."""
+
     rid: int
     arrival: float
     n: int
@@ -233,15 +236,25 @@ class Request:
     steps: int
     kind: str  # "vortex" or "quadrant"
     grid: Grid
-    U0: np.ndarray
+    seed: int
     gamma: float = 1.4
+
+    def state(self):
+        if self.kind == "vortex":
+            return isentropic_vortex_2d(self.n, gamma=self.gamma)[1]
+        return four_quadrant_2d(self.n, np.random.default_rng(self.seed), gamma=self.gamma)[1]
+
+    @property
+    def cells(self) -> int:
+        return self.grid.ncells
 
 
 def serving_stream(count=200, rate=20.0, seed=0, sizes=(64, 128, 256, 512, 1024),
-                   radii=(1, 2, 3), steps=(100, 500), make_state=True):
+                   radii=(1, 2, 3), steps=(100, 500)):
     """Poisson arrivals (mean ``rate`` per second) of independent 2D Euler problems:
     grid edge uniform from ``sizes``, R uniform from ``radii``, step count uniform
-    integer in ``steps``, initial data half isentropic vortex, half four-quadrant."""
+    integer in ``steps``, initial data half isentropic vortex on [-5,5]^2, half
+    four-quadrant Riemann data on [0,1]^2."""
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
@@ -251,12 +264,10 @@ def serving_stream(count=200, rate=20.0, seed=0, sizes=(64, 128, 256, 512, 1024)
         R = int(rng.choice(radii))
         st = int(rng.integers(steps[0], steps[1] + 1))
         kind = "vortex" if rng.random() < 0.5 else "quadrant"
-        sub = np.random.default_rng(rng.integers(0, 2**63 - 1))
+        sub = int(rng.integers(0, 2**62))
         if kind == "vortex":
             g = grid2d(n, n, (-5.0, -5.0), (5.0, 5.0))
-            U0 = isentropic_vortex_2d(n)[1] if make_state else None
         else:
             g = grid2d(n, n)
-            U0 = four_quadrant_2d(n, sub)[1] if make_state else None
-        out.append(Request(rid, t, n, R, st, kind, g, U0))
+        out.append(Request(rid, t, n, R, st, kind, g, sub))
     return out

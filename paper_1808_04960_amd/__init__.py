@@ -72,6 +72,15 @@ def lib():
         L.gpweno_step_kernel.argtypes = [vp, ctypes.c_int]
         L.gpweno_conserved_sums.argtypes = [vp, _dp]
         L.gpweno_compute_tables.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp, _dp]
+        L.gpweno_set_end.argtypes = [vp, ctypes.c_double, ctypes.c_long]
+        L.gpweno_batch_create.argtypes = [ctypes.POINTER(vp)]
+        L.gpweno_batch_set.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, vp]
+        L.gpweno_batch_run.argtypes = [vp, ctypes.c_int, vp]
+        L.gpweno_batch_status.argtypes = [vp, _dp, _dp, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_int), vp]
+        L.gpweno_batch_destroy.argtypes = [vp]
+        L.gpweno_batch_destroy.restype = None
+        L.gpweno_batch_last_error.argtypes = [vp]
+        L.gpweno_batch_last_error.restype = ctypes.c_char_p
         L.gpweno_last_error.argtypes = [vp]
         L.gpweno_last_error.restype = ctypes.c_char_p
         L.gpweno_destroy.argtypes = [vp]
@@ -188,6 +197,10 @@ class Solver:
     def step(self, t_final):
         _check(lib().gpweno_step(self._ctx, t_final), self._ctx)
 
+    def set_end(self, t_final, step_limit=-1):
+        """End time and absolute step limit honoured by batched execution (enqueued)."""
+        _check(lib().gpweno_set_end(self._ctx, t_final, step_limit), self._ctx)
+
     def step_kernel(self, k):
         """Enqueue the k-th of the 3*ndim launches of a step (instrumentation)."""
         _check(lib().gpweno_step_kernel(self._ctx, k), self._ctx)
@@ -234,6 +247,52 @@ class Solver:
         if self._ctx:
             lib().gpweno_destroy(self._ctx)
             self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _bcheck(code, b=None):
+    if code != OK:
+        raise GpwenoError(code, lib().gpweno_batch_last_error(b).decode())
+
+
+class Batch:
+    """Advances many independent Solvers together (one batched launch per sweep
+    and group of equal ndim, R and precision). All member solvers and the batch
+    must use the same stream."""
+
+    def __init__(self, stream):
+        self._b = ctypes.c_void_p()
+        self.stream = stream
+        _bcheck(lib().gpweno_batch_create(ctypes.byref(self._b)))
+        self.members = []
+
+    def set(self, solvers):
+        arr = (ctypes.c_void_p * max(1, len(solvers)))(*[sv._ctx.value for sv in solvers])
+        _bcheck(lib().gpweno_batch_set(self._b, arr, len(solvers), ctypes.c_void_p(self.stream.cuda_stream)), self._b)
+        self.members = list(solvers)
+
+    def run(self, nsteps):
+        _bcheck(lib().gpweno_batch_run(self._b, nsteps, ctypes.c_void_p(self.stream.cuda_stream)), self._b)
+
+    def status(self):
+        """Blocking: (t, dt, nsteps, err) arrays in member order."""
+        n = len(self.members)
+        t, dt = np.zeros(max(n, 1)), np.zeros(max(n, 1))
+        ns = (ctypes.c_long * max(n, 1))()
+        er = (ctypes.c_int * max(n, 1))()
+        _bcheck(lib().gpweno_batch_status(self._b, t.ctypes.data_as(_dp), dt.ctypes.data_as(_dp), ns, er,
+                                          ctypes.c_void_p(self.stream.cuda_stream)), self._b)
+        return t[:n], dt[:n], np.array(ns[:n], dtype=np.int64), np.array(er[:n], dtype=np.int32)
+
+    def close(self):
+        if self._b:
+            lib().gpweno_batch_destroy(self._b)
+            self._b = ctypes.c_void_p()
 
     def __del__(self):
         try:

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/gpweno.h"
 #include "gp_tables.h"
@@ -458,5 +459,324 @@ void gpweno_destroy(gpweno_ctx* c) {
     if (c->h_ctl) (void)hipHostFree(c->h_ctl);
     delete c;
 }
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched execution
+// ===========================================================================
+namespace {
+
+constexpr int BATCH_MAX = 4096;
+
+// Problems sharing one kernel instantiation and one set of GP tables.
+struct BatchGroup {
+    int ndim = 0, R = 0;
+    bool fp32 = false;
+    const gpweno_ctx* proto = nullptr;      // supplies the tables
+    std::vector<int> members;               // indices into the set
+    long long blocks[3] = {0, 0, 0};        // per direction
+    size_t owner_off[3] = {0, 0, 0};        // element offsets into the owner table
+    size_t desc_off[3][3] = {};             // [stage-1][dir] offsets into the descriptor table
+};
+
+bool same_tables(const gpweno_ctx* a, const gpweno_ctx* b) {
+    for (int d = 0; d < a->grid.ndim; ++d)
+        if (std::memcmp(&a->tab64[d], &b->tab64[d], sizeof(GpTablesF64)) != 0) return false;
+    // the batched kernel takes one table set per launch; problems whose axes
+    // carry different tables (non-square cells) form their own groups
+    for (int d = 1; d < a->grid.ndim; ++d)
+        if (std::memcmp(&a->tab64[d], &a->tab64[0], sizeof(GpTablesF64)) != 0) return false;
+    return true;
+}
+
+}  // namespace
+
+struct gpweno_batch {
+    int device = 0;
+    hipStream_t own_stream = nullptr;
+    hipStream_t last_stream = nullptr;
+    std::vector<gpweno_ctx*> set;
+    std::vector<BatchGroup> groups;
+    gpw::ProbDesc* d_desc = nullptr;
+    size_t desc_cap = 0;
+    unsigned short* d_owner = nullptr;
+    size_t owner_cap = 0;
+    gpw::Ctl** d_ctls = nullptr;
+    gpw::BatchStatus* d_status = nullptr;
+    gpw::BatchStatus* h_status = nullptr;
+    hipGraphExec_t graph = nullptr;
+    std::string err;
+};
+
+namespace {
+
+int bfail(gpweno_batch* b, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (b) b->err = buf;
+    else g_tls_error = buf;
+    return code;
+}
+
+#define BHIP_TRY(b, expr)                                                                          \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) return bfail((b), GPWENO_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+void batch_drop_graph(gpweno_batch* b) {
+    if (b->graph) {
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+}
+
+// One batched launch: position k of the step sequence for group g.
+int batch_launch(gpweno_batch* b, const BatchGroup& g, int k, hipStream_t s) {
+    const int stage = k / g.ndim + 1, dir = k % g.ndim;
+    const bool fin = dir == g.ndim - 1;
+    hipError_t e;
+    if (g.fp32) {
+        gpw::BatchArgs<float> a;
+        std::memset(&a, 0, sizeof a);
+        a.probs = b->d_desc + g.desc_off[stage - 1][dir];
+        a.owner = b->d_owner + g.owner_off[dir];
+        a.first = dir == 0;
+        a.stage = stage;
+        a.step_start = k == 0;
+        a.tab = g.proto->tabf[0];
+        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, true, fin, &a, g.blocks[dir], s);
+    } else {
+        gpw::BatchArgs<double> a;
+        std::memset(&a, 0, sizeof a);
+        a.probs = b->d_desc + g.desc_off[stage - 1][dir];
+        a.owner = b->d_owner + g.owner_off[dir];
+        a.first = dir == 0;
+        a.stage = stage;
+        a.step_start = k == 0;
+        a.tab = g.proto->tabd[0];
+        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, false, fin, &a, g.blocks[dir], s);
+    }
+    if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "batched sweep launch: %s", hipGetErrorString(e));
+    return GPWENO_OK;
+}
+
+int batch_enqueue_step(gpweno_batch* b, hipStream_t s) {
+    int kmax = 0;
+    for (const auto& g : b->groups) kmax = std::max(kmax, 3 * g.ndim);
+    for (int k = 0; k < kmax; ++k)
+        for (const auto& g : b->groups)
+            if (k < 3 * g.ndim) {
+                int st = batch_launch(b, g, k, s);
+                if (st) return st;
+            }
+    return GPWENO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gpweno_set_end(gpweno_ctx* c, double t_final, long step_limit) {
+    if (!c) return fail(nullptr, GPWENO_EINVAL, "NULL context");
+    if (!c->state) return fail(c, GPWENO_ESTATE, "no state bound");
+    hipError_t e = gpw::launch_set_run(c->d_ctl, t_final, step_limit < 0 ? LLONG_MAX : (long long)step_limit,
+                                       user_stream(c));
+    if (e != hipSuccess) return fail(c, GPWENO_EHIP, "set_run launch: %s", hipGetErrorString(e));
+    return GPWENO_OK;
+}
+
+int gpweno_batch_create(gpweno_batch** out) {
+    if (!out) return bfail(nullptr, GPWENO_EINVAL, "NULL output pointer");
+    *out = nullptr;
+    gpweno_batch* b = new (std::nothrow) gpweno_batch();
+    if (!b) return bfail(nullptr, GPWENO_ENOMEM, "out of host memory");
+    hipError_t e = hipGetDevice(&b->device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&b->d_ctls, sizeof(gpw::Ctl*) * BATCH_MAX);
+    if (e == hipSuccess) e = hipMalloc(&b->d_status, sizeof(gpw::BatchStatus) * BATCH_MAX);
+    if (e == hipSuccess) e = hipHostMalloc(&b->h_status, sizeof(gpw::BatchStatus) * BATCH_MAX, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        int code = bfail(nullptr, GPWENO_EHIP, "batch set-up: %s", hipGetErrorString(e));
+        gpweno_batch_destroy(b);
+        return code;
+    }
+    *out = b;
+    return GPWENO_OK;
+}
+
+int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stream) {
+    if (!b) return bfail(nullptr, GPWENO_EINVAL, "NULL batch");
+    if (n < 0 || n > BATCH_MAX || (n > 0 && !ctxs)) return bfail(b, GPWENO_EINVAL, "need 0 <= n <= %d", BATCH_MAX);
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i] || !ctxs[i]->state) return bfail(b, GPWENO_EINVAL, "context %d is NULL or not bound", i);
+        if (ctxs[i]->device != b->device) return bfail(b, GPWENO_EINVAL, "context %d is on another device", i);
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return bfail(b, GPWENO_EINVAL, "context %d repeated", i);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // the previous launches may still read the descriptor tables
+    BHIP_TRY(b, hipStreamSynchronize(s));
+    if (b->last_stream && b->last_stream != s) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
+    batch_drop_graph(b);
+    b->set.assign(ctxs, ctxs + n);
+    b->groups.clear();
+    for (int i = 0; i < n; ++i) {
+        const gpweno_ctx* c = ctxs[i];
+        const bool fp32 = c->opt.precision == GPWENO_FP32;
+        BatchGroup* g = nullptr;
+        for (auto& h : b->groups)
+            if (h.ndim == c->grid.ndim && h.R == c->R && h.fp32 == fp32 && same_tables(h.proto, c)) g = &h;
+        if (!g) {
+            b->groups.emplace_back();
+            g = &b->groups.back();
+            g->ndim = c->grid.ndim;
+            g->R = c->R;
+            g->fp32 = fp32;
+            g->proto = c;
+        }
+        g->members.push_back(i);
+    }
+    // per-axis tables must agree inside a problem for the batched kernel
+    for (const auto& g : b->groups)
+        for (int m : g.members)
+            if (!same_tables(b->set[m], b->set[m]))
+                return bfail(b, GPWENO_EINVAL, "context %d has different GP tables per axis (non-square "
+                                              "cells); batched execution needs equal tables", m);
+    // descriptors and block owners
+    std::vector<gpw::ProbDesc> desc;
+    std::vector<unsigned short> owner;
+    for (auto& g : b->groups) {
+        for (int dir = 0; dir < g.ndim; ++dir) {
+            g.owner_off[dir] = owner.size();
+            long long total = 0;
+            std::vector<long long> nblk(g.members.size()), b0(g.members.size());
+            for (size_t j = 0; j < g.members.size(); ++j) {
+                const gpweno_ctx* c = b->set[g.members[j]];
+                int nn[3] = {c->grid.n[0], c->grid.n[1], c->grid.n[2]};
+                const int nseg = (nn[dir] + TOUT - 1) / TOUT;
+                nblk[j] = gpw::sweep_blocks(g.ndim, dir, nn, nseg);
+                b0[j] = total;
+                total += nblk[j];
+                for (long long q = 0; q < nblk[j]; ++q) owner.push_back((unsigned short)j);
+            }
+            if (total > INT_MAX) return bfail(b, GPWENO_EINVAL, "batch too large");
+            g.blocks[dir] = total;
+            for (int stage = 1; stage <= 3; ++stage) {
+                g.desc_off[stage - 1][dir] = desc.size();
+                for (size_t j = 0; j < g.members.size(); ++j) {
+                    gpweno_ctx* c = b->set[g.members[j]];
+                    gpw::ProbDesc P;
+                    std::memset(&P, 0, sizeof P);
+                    const double* ins[3] = {c->state, c->U1, c->U2};
+                    double* outs[3] = {c->U1, c->U2, c->state};
+                    P.U = ins[stage - 1];
+                    P.Un = c->state;
+                    P.dU = c->dU;
+                    P.Uout = outs[stage - 1];
+                    P.ctl = c->d_ctl;
+                    for (int d = 0; d < 3; ++d) P.n[d] = c->grid.n[d];
+                    P.nseg = (c->grid.n[dir] + TOUT - 1) / TOUT;
+                    P.ncell = c->ncell;
+                    P.inv_dx = 1.0 / c->dx[dir];
+                    for (int d = 0; d < 3; ++d) P.inv_dx_all[d] = d < c->grid.ndim ? 1.0 / c->dx[d] : 0.0;
+                    P.gamma = c->gamma;
+                    P.positivity = c->opt.positivity_fallback ? 1 : 0;
+                    P.nblk = (unsigned)nblk[j];
+                    P.block0 = b0[j];
+                    desc.push_back(P);
+                }
+            }
+        }
+    }
+    if (desc.size() > b->desc_cap) {
+        if (b->d_desc) (void)hipFree(b->d_desc);
+        b->d_desc = nullptr;
+        b->desc_cap = 0;
+        BHIP_TRY(b, hipMalloc(&b->d_desc, sizeof(gpw::ProbDesc) * desc.size()));
+        b->desc_cap = desc.size();
+    }
+    if (owner.size() > b->owner_cap) {
+        if (b->d_owner) (void)hipFree(b->d_owner);
+        b->d_owner = nullptr;
+        b->owner_cap = 0;
+        BHIP_TRY(b, hipMalloc(&b->d_owner, sizeof(unsigned short) * owner.size()));
+        b->owner_cap = owner.size();
+    }
+    std::vector<gpw::Ctl*> ctls(n);
+    for (int i = 0; i < n; ++i) ctls[i] = ctxs[i]->d_ctl;
+    if (!desc.empty())
+        BHIP_TRY(b, hipMemcpy(b->d_desc, desc.data(), sizeof(gpw::ProbDesc) * desc.size(), hipMemcpyHostToDevice));
+    if (!owner.empty())
+        BHIP_TRY(b, hipMemcpy(b->d_owner, owner.data(), sizeof(unsigned short) * owner.size(), hipMemcpyHostToDevice));
+    if (n) BHIP_TRY(b, hipMemcpy(b->d_ctls, ctls.data(), sizeof(gpw::Ctl*) * n, hipMemcpyHostToDevice));
+    b->last_stream = s;
+    return GPWENO_OK;
+}
+
+int gpweno_batch_run(gpweno_batch* b, int nsteps, void* stream) {
+    if (!b) return bfail(nullptr, GPWENO_EINVAL, "NULL batch");
+    if (nsteps < 1) return bfail(b, GPWENO_EINVAL, "nsteps must be >= 1");
+    if (b->set.empty()) return GPWENO_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!b->graph) {
+        BHIP_TRY(b, hipStreamBeginCapture(b->own_stream, hipStreamCaptureModeThreadLocal));
+        int st = batch_enqueue_step(b, b->own_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->own_stream, &g);
+        if (st) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            b->graph = nullptr;
+            return bfail(b, GPWENO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+    }
+    for (int i = 0; i < nsteps; ++i) BHIP_TRY(b, hipGraphLaunch(b->graph, s));
+    b->last_stream = s;
+    return GPWENO_OK;
+}
+
+int gpweno_batch_status(gpweno_batch* b, double* t, double* dt, long* nsteps, int* err, void* stream) {
+    if (!b) return bfail(nullptr, GPWENO_EINVAL, "NULL batch");
+    const int n = (int)b->set.size();
+    if (n == 0) return GPWENO_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = gpw::launch_gather_status(b->d_ctls, n, b->d_status, s);
+    if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "status launch: %s", hipGetErrorString(e));
+    BHIP_TRY(b, hipMemcpyAsync(b->h_status, b->d_status, sizeof(gpw::BatchStatus) * n, hipMemcpyDeviceToHost, s));
+    BHIP_TRY(b, hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i) {
+        if (t) t[i] = b->h_status[i].t;
+        if (dt) dt[i] = b->h_status[i].dt;
+        if (nsteps) nsteps[i] = (long)b->h_status[i].nsteps;
+        if (err) err[i] = b->h_status[i].err;
+    }
+    return GPWENO_OK;
+}
+
+void gpweno_batch_destroy(gpweno_batch* b) {
+    if (!b) return;
+    if (b->last_stream) (void)hipStreamSynchronize(b->last_stream);
+    if (b->own_stream) (void)hipStreamSynchronize(b->own_stream);
+    batch_drop_graph(b);
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->d_owner) (void)hipFree(b->d_owner);
+    if (b->d_ctls) (void)hipFree(b->d_ctls);
+    if (b->d_status) (void)hipFree(b->d_status);
+    if (b->h_status) (void)hipHostFree(b->h_status);
+    if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
+    delete b;
+}
+
+const char* gpweno_batch_last_error(const gpweno_batch* b) { return b ? b->err.c_str() : g_tls_error.c_str(); }
 
 }  // extern "C"

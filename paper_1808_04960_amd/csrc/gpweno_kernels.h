@@ -59,10 +59,51 @@ struct SweepArgs {
     Tab<Real> tab;
 };
 
+// One problem of a batched launch: its buffers and geometry for one launch of
+// the step sequence, and its range of logical blocks.
+struct ProbDesc {
+    const double* U;
+    const double* Un;
+    double* dU;
+    double* Uout;
+    Ctl* ctl;
+    int n[3];
+    int nseg;
+    long long ncell;
+    double inv_dx;
+    double inv_dx_all[3];
+    double gamma;
+    int positivity;
+    unsigned nblk;      // logical blocks of this problem in the launch
+    long long block0;   // its first logical block
+};
+
+template <typename Real>
+struct BatchArgs {
+    const ProbDesc* probs;
+    const unsigned short* owner;  // problem index of every logical block
+    int first;
+    int stage;
+    int step_start;
+    Tab<Real> tab;
+};
+
+struct BatchStatus {
+    double t;
+    double dt;
+    long long nsteps;
+    int err;
+    int pad;
+};
+
 // Launchers (defined in gpweno_kernels.hip). fin: the sweep finishes an RK
 // stage (last direction of stages 1..3); otherwise it accumulates into dU.
 hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, const void* args, hipStream_t s);
 hipError_t launch_set_run(Ctl* ctl, double t_final, long long step_limit, hipStream_t s);
+long long sweep_blocks(int ndim, int dir, const int n[3], int nseg);
+hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, const void* args, long long blocks,
+                              hipStream_t s);
+hipError_t launch_gather_status(Ctl* const* ctls, int nprob, BatchStatus* out, hipStream_t s);
 hipError_t launch_set_time(Ctl* ctl, double t, long long nsteps, double cfl, double fixed_dt, hipStream_t s);
 hipError_t launch_speed(int ndim, const double* U, long long ncell, const int n[3], const double inv_dx[3],
                         double gamma, Ctl* ctl, hipStream_t s);

@@ -392,13 +392,24 @@ __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long 
     }
 }
 
+// XCD-aware block order. Workgroups are dealt to the 8 XCDs round-robin by
+// index; renumber them so that each XCD gets one contiguous range of logical
+// blocks. Logical order is "band-major" in every direction (rows for x sweeps,
+// runs along y / z for y / z sweeps), so an XCD keeps working on roughly the
+// same slab of the grid in every sweep, and the slab's stage states and
+// accumulator stay in that XCD's L2 between kernels.
+__device__ __forceinline__ long long xcd_logical_block() {
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned q8 = nb >> 3, r8 = nb & 7u, xcd = b & 7u;
+    return (long long)(xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3));
+}
+
+// One block of a sweep: logical block L of the problem's nblk blocks.
 template <int NDIM, int DIR, int R, typename Real, bool FIN>
-__global__ void __launch_bounds__(DIR == 0 ? 4 * WAVE : 8 * WAVE)
-sweep_kernel(const SweepArgs<Real> a) {
+__device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long long L, const unsigned nblk,
+                                            unsigned char* smem, unsigned long long* sred) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     constexpr int NV = C::NV, WPB = C::WPB, PITCH = C::PITCH, SLEN = C::SLEN, THREADS = C::THREADS;
-    __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
-    __shared__ unsigned long long sred[WPB];
     Real* sV = reinterpret_cast<Real*>(smem);
     double* sO = reinterpret_cast<double*>(smem);
 
@@ -406,22 +417,13 @@ sweep_kernel(const SweepArgs<Real> a) {
     int par = 0;
     if (a.stage > 0) {
         if (!step_go(a.ctl, t0, dt, par)) return;
-        if (a.step_start && blockIdx.x == 0 && threadIdx.x == 0) a.ctl->speed[1 - par] = 0ull;
+        if (a.step_start && L == 0 && threadIdx.x == 0) a.ctl->speed[1 - par] = 0ull;
     }
 
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
     const int w = tid / WAVE;
     const int N = a.n[DIR];
-    // XCD-aware block order. Workgroups are dealt to the 8 XCDs round-robin by
-    // index; renumber them so that each XCD gets one contiguous range of logical
-    // blocks. Logical order is "band-major" in every direction (rows for x
-    // sweeps, runs along y / z for y / z sweeps), so an XCD keeps working on
-    // roughly the same slab of the grid in every sweep, and the slab's stage
-    // states and accumulator stay in that XCD's L2 between kernels.
-    const unsigned nb = gridDim.x, b = blockIdx.x;
-    const unsigned q8 = nb >> 3, r8 = nb & 7u, xcd = b & 7u;
-    const long long L = (long long)(xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3));
     int seg;
     long long grp;       // DIR 0: row group; else x group
     long long other = 0; // z for DIR 1, y for DIR 2
@@ -587,7 +589,7 @@ sweep_kernel(const SweepArgs<Real> a) {
             Ctl* c = a.ctl;
             atomicMax(&c->speed[1 - par], m);
             const unsigned int done = atomicAdd(&c->ticket, 1u);
-            if (done == gridDim.x - 1) {
+            if (done == nblk - 1) {
                 c->t = t0 + dt;
                 c->dt = dt;
                 c->nsteps = c->nsteps + 1;
@@ -596,6 +598,53 @@ sweep_kernel(const SweepArgs<Real> a) {
             }
         }
     }
+}
+
+template <int NDIM, int DIR, int R, typename Real, bool FIN>
+__global__ void __launch_bounds__(DIR == 0 ? 4 * WAVE : 8 * WAVE)
+sweep_kernel(const SweepArgs<Real> a) {
+    using C = SweepCfg<NDIM, DIR, R, Real>;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
+    __shared__ unsigned long long sred[C::WPB];
+    sweep_block<NDIM, DIR, R, Real, FIN>(a, xcd_logical_block(), gridDim.x, smem, sred);
+}
+
+// Batched sweep over many independent problems (same ndim, R, precision and
+// tables). Logical blocks are laid out problem after problem; owner[L] names
+// the problem of logical block L. Every block runs exactly the code of the
+// single-problem sweep on its own problem's data, so a problem's result does
+// not depend on what else is in the batch.
+template <int NDIM, int DIR, int R, typename Real, bool FIN>
+__global__ void __launch_bounds__(DIR == 0 ? 4 * WAVE : 8 * WAVE)
+sweep_batch_kernel(const BatchArgs<Real> ba) {
+    using C = SweepCfg<NDIM, DIR, R, Real>;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
+    __shared__ unsigned long long sred[C::WPB];
+    const long long Lg = xcd_logical_block();
+    const int p = ba.owner[Lg];
+    const ProbDesc& P = ba.probs[p];
+    SweepArgs<Real> a;
+    a.U = P.U;
+    a.Un = P.Un;
+    a.dU = P.dU;
+    a.Uout = P.Uout;
+    a.ctl = P.ctl;
+    a.n[0] = P.n[0];
+    a.n[1] = P.n[1];
+    a.n[2] = P.n[2];
+    a.nseg = P.nseg;
+    a.ncell = P.ncell;
+    a.inv_dx = P.inv_dx;
+    a.inv_dx_all[0] = P.inv_dx_all[0];
+    a.inv_dx_all[1] = P.inv_dx_all[1];
+    a.inv_dx_all[2] = P.inv_dx_all[2];
+    a.gamma = P.gamma;
+    a.positivity = P.positivity;
+    a.first = ba.first;
+    a.stage = ba.stage;
+    a.step_start = ba.step_start;
+    a.tab = ba.tab;
+    sweep_block<NDIM, DIR, R, Real, FIN>(a, Lg - P.block0, P.nblk, smem, sred);
 }
 
 // ---------------------------------------------------------------------------
@@ -748,6 +797,82 @@ hipError_t launch_nd(int ndim, int dir, int R, bool fin, const void* args, hipSt
 
 hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, const void* args, hipStream_t s) {
     return fp32 ? launch_nd<float>(ndim, dir, R, fin, args, s) : launch_nd<double>(ndim, dir, R, fin, args, s);
+}
+
+// ---- batched launches --------------------------------------------------------
+long long sweep_blocks(int ndim, int dir, const int n[3], int nseg) {
+    const int wpb = dir == 0 ? 4 : 8;
+    long long groups;
+    if (dir == 0) groups = ((long long)n[1] * n[2] + wpb - 1) / wpb;
+    else groups = (long long)((n[0] + wpb - 1) / wpb) * (dir == 1 ? n[2] : n[1]);
+    (void)ndim;
+    return groups * nseg;
+}
+
+template <int NDIM, int DIR, int R, typename Real, bool FIN>
+hipError_t launch_batch_one(const void* args, long long blocks, hipStream_t s) {
+    using C = SweepCfg<NDIM, DIR, R, Real>;
+    const BatchArgs<Real>& a = *static_cast<const BatchArgs<Real>*>(args);
+    if (blocks <= 0 || blocks > INT_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep_batch_kernel<NDIM, DIR, R, Real, FIN>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
+                       a);
+    return hipGetLastError();
+}
+
+template <int NDIM, int R, typename Real>
+hipError_t launch_batch_dir(int dir, bool fin, const void* args, long long blocks, hipStream_t s) {
+    if (fin) {
+        if (dir != NDIM - 1) return hipErrorInvalidValue;
+        return launch_batch_one<NDIM, NDIM - 1, R, Real, true>(args, blocks, s);
+    }
+    if (dir == 0) return launch_batch_one<NDIM, 0, R, Real, false>(args, blocks, s);
+    if (NDIM >= 2 && dir == 1) return launch_batch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false>(args, blocks, s);
+    if (NDIM == 3 && dir == 2) return launch_batch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false>(args, blocks, s);
+    return hipErrorInvalidValue;
+}
+
+template <int NDIM, typename Real>
+hipError_t launch_batch_r(int dir, int R, bool fin, const void* args, long long blocks, hipStream_t s) {
+    switch (R) {
+        case 1: return launch_batch_dir<NDIM, 1, Real>(dir, fin, args, blocks, s);
+        case 2: return launch_batch_dir<NDIM, 2, Real>(dir, fin, args, blocks, s);
+        case 3: return launch_batch_dir<NDIM, 3, Real>(dir, fin, args, blocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename Real>
+hipError_t launch_batch_nd(int ndim, int dir, int R, bool fin, const void* args, long long blocks, hipStream_t s) {
+    switch (ndim) {
+        case 1: return launch_batch_r<1, Real>(dir, R, fin, args, blocks, s);
+        case 2: return launch_batch_r<2, Real>(dir, R, fin, args, blocks, s);
+        case 3: return launch_batch_r<3, Real>(dir, R, fin, args, blocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, const void* args, long long blocks,
+                              hipStream_t s) {
+    return fp32 ? launch_batch_nd<float>(ndim, dir, R, fin, args, blocks, s)
+                : launch_batch_nd<double>(ndim, dir, R, fin, args, blocks, s);
+}
+
+// Copies the step state of every problem of a batch into a compact array.
+__global__ void gather_status_kernel(Ctl* const* ctls, int nprob, BatchStatus* out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob) return;
+    const Ctl* c = ctls[p];
+    out[p].t = c->t;
+    out[p].dt = c->dt;
+    out[p].nsteps = c->nsteps;
+    out[p].err = c->err;
+    out[p].pad = 0;
+}
+
+hipError_t launch_gather_status(Ctl* const* ctls, int nprob, BatchStatus* out, hipStream_t s) {
+    if (nprob <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_status_kernel, dim3((nprob + 63) / 64), dim3(64), 0, s, ctls, nprob, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_set_run(Ctl* ctl, double t_final, long long step_limit, hipStream_t s) {

@@ -1,0 +1,254 @@
+"""Continuous batching of independent Euler problems on one GPU.
+
+Requests arrive over time and are replayed against a clock. A request is admitted
+when a slot is free and its HBM footprint (state plus stage workspace) fits the
+budget. Admitted problems stay resident on the device. The scheduler advances all
+of them together, a few steps per tick: each step is one batched launch per sweep
+and per group of equal R (``gpweno_batch_run``, replayed from a captured graph).
+A problem that reaches its step count is copied back and its memory released,
+which lets the next waiting requests in while the others keep running.
+
+Admission is first-in first-out: a request that does not fit blocks the ones
+behind it (no starvation of large problems). A request larger than the whole
+budget is rejected.
+
+Executors:
+  ``GpuExecutor`` -- the device path (``Solver`` + ``Batch``);
+  ``SimExecutor`` -- a modelled executor on a virtual clock, used to test the
+                     scheduling logic without a GPU.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+
+PARTIAL_SUMS = 1024  # partial sums of the conservation reduction in the workspace
+
+
+def footprint_bytes(grid) -> int:
+    """Device bytes one problem holds: float64 state, two RK stage states, the
+    direction accumulator (ndim > 1) and the reduction partials."""
+    nv = 2 + grid.ndim
+    one = -(-8 * nv * grid.ncells // 256) * 256
+    arrays = 3 + (1 if grid.ndim > 1 else 0)
+    return arrays * one + -(-8 * nv * PARTIAL_SUMS // 256) * 256
+
+
+@dataclasses.dataclass
+class Job:
+    req: object
+    footprint: int
+    status: str = "waiting"  # waiting, active, done, failed, rejected
+    admitted: float = float("nan")
+    finished: float = float("nan")
+    steps_done: int = 0
+    handle: object = None
+    result: object = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.req.arrival
+
+
+@dataclasses.dataclass
+class Report:
+    jobs: list
+    makespan: float
+    cell_updates: float
+    peak_bytes: int
+    peak_active: int
+    ticks: int
+
+    def latencies(self):
+        return np.array([j.latency for j in self.jobs if j.status == "done"])
+
+    def summary(self):
+        lat = self.latencies()
+        done = [j for j in self.jobs if j.status == "done"]
+        return {
+            "requests": len(self.jobs),
+            "completed": len(done),
+            "failed": sum(j.status == "failed" for j in self.jobs),
+            "rejected": sum(j.status == "rejected" for j in self.jobs),
+            "p50_ms": float(np.percentile(lat, 50) * 1e3) if len(lat) else None,
+            "p99_ms": float(np.percentile(lat, 99) * 1e3) if len(lat) else None,
+            "makespan_s": self.makespan,
+            "cell_updates_per_s": self.cell_updates / self.makespan if self.makespan > 0 else None,
+            "peak_resident_bytes": self.peak_bytes,
+            "peak_active": self.peak_active,
+            "ticks": self.ticks,
+        }
+
+
+class Server:
+    def __init__(self, executor, hbm_budget: int, max_slots: int = 64, steps_per_tick: int = 8):
+        self.ex = executor
+        self.budget = int(hbm_budget)
+        self.max_slots = int(max_slots)
+        self.k = int(steps_per_tick)
+
+    def run(self, requests, keep_results=False):
+        ex = self.ex
+        jobs = [Job(r, ex.footprint(r)) for r in sorted(requests, key=lambda r: (r.arrival, r.rid))]
+        pending = list(jobs)
+        waiting = []
+        active = []
+        used = 0
+        peak_bytes = 0
+        peak_active = 0
+        ticks = 0
+        cell_updates = 0.0
+        t0 = ex.now()
+        first_arrival = jobs[0].req.arrival if jobs else 0.0
+        while pending or waiting or active:
+            now = ex.now() - t0
+            while pending and pending[0].req.arrival <= now:
+                j = pending.pop(0)
+                if j.footprint > self.budget:
+                    j.status = "rejected"
+                    j.finished = now
+                else:
+                    waiting.append(j)
+            changed = False
+            while waiting and len(active) < self.max_slots and used + waiting[0].footprint <= self.budget:
+                j = waiting.pop(0)
+                j.handle = ex.admit(j.req)
+                j.status = "active"
+                j.admitted = ex.now() - t0
+                used += j.footprint
+                active.append(j)
+                changed = True
+            peak_bytes = max(peak_bytes, used)
+            peak_active = max(peak_active, len(active))
+            if changed:
+                ex.set_active([j.handle for j in active])
+            if not active:
+                if pending:
+                    ex.idle_until(t0 + pending[0].req.arrival)
+                continue
+            ex.advance(self.k)
+            ticks += 1
+            nsteps, err = ex.progress()
+            retired = []
+            for j, n, e in zip(active, nsteps, err):
+                cell_updates += (int(n) - j.steps_done) * 3.0 * j.req.cells
+                j.steps_done = int(n)
+                if e or n >= j.req.steps:
+                    j.result = ex.retire(j.handle, keep_results and not e)
+                    j.handle = None
+                    j.status = "failed" if e else "done"
+                    j.finished = ex.now() - t0
+                    used -= j.footprint
+                    retired.append(j)
+            if retired:
+                active = [j for j in active if j.handle is not None]
+                ex.set_active([j.handle for j in active])
+        makespan = max((j.finished for j in jobs), default=0.0) - first_arrival
+        return Report(jobs, makespan, cell_updates, peak_bytes, peak_active, ticks)
+
+
+class GpuExecutor:
+    """Problems resident on the GPU, advanced by one ``Batch`` on one stream."""
+
+    def __init__(self, precision="fp32", device=None):
+        import torch
+
+        from . import Batch
+
+        self.torch = torch
+        self.precision = precision
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.stream = torch.cuda.Stream(self.device)
+        self.batch = Batch(self.stream)
+
+    def now(self):
+        return time.perf_counter()
+
+    def idle_until(self, t):
+        dt = t - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+
+    def footprint(self, req):
+        return footprint_bytes(req.grid)
+
+    def admit(self, req):
+        from . import Solver
+
+        dx = req.grid.dx[0]
+        s = Solver(req.grid, req.R, 12 * dx, 3 * dx, gamma=req.gamma, precision=self.precision,
+                   positivity_fallback=(req.kind == "quadrant"), U0=req.state(), device=self.device.index,
+                   stream=self.stream)
+        s.set_end(1e30, req.steps)
+        return s
+
+    def set_active(self, handles):
+        self.batch.set(handles)
+
+    def advance(self, k):
+        self.batch.run(k)
+
+    def progress(self):
+        _, _, ns, err = self.batch.status()
+        return ns, err
+
+    def retire(self, handle, keep):
+        out = handle.get_state() if keep else None
+        handle.close()
+        handle.state = None
+        handle.workspace = None
+        return out
+
+    def close(self):
+        self.batch.close()
+
+
+class SimExecutor:
+    """Modelled executor: problems progress at a fixed aggregate rate of
+    cell-updates per second on a virtual clock (scheduler tests, no GPU)."""
+
+    @dataclasses.dataclass
+    class Handle:
+        req: object
+        steps: int = 0
+
+    def __init__(self, rate=5e9, fail_rids=()):
+        self.t = 0.0
+        self.rate = float(rate)
+        self.active = []
+        self.fail_rids = set(fail_rids)
+        self.admitted = []
+
+    def now(self):
+        return self.t
+
+    def idle_until(self, t):
+        self.t = max(self.t, t)
+
+    def footprint(self, req):
+        return footprint_bytes(req.grid)
+
+    def admit(self, req):
+        self.admitted.append(req.rid)
+        return SimExecutor.Handle(req)
+
+    def set_active(self, handles):
+        self.active = list(handles)
+
+    def advance(self, k):
+        work = 0.0
+        for h in self.active:
+            take = min(k, h.req.steps - h.steps)
+            work += take * 3.0 * h.req.cells
+            h.steps += take
+        self.t += work / self.rate
+
+    def progress(self):
+        ns = np.array([h.steps for h in self.active], dtype=np.int64)
+        err = np.array([1 if (h.req.rid in self.fail_rids and h.steps > 0) else 0 for h in self.active])
+        return ns, err
+
+    def retire(self, handle, keep):
+        return None

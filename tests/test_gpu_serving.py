@@ -1,0 +1,108 @@
+"""Batched execution and the continuous-batching server on the GPU.
+
+* A batch of problems of mixed size, R and initial data gives, for each problem,
+  bitwise the state the single-problem path gives: every block of the batched
+  kernel runs the single-problem sweep on its own problem's data.
+* Through the server, a request's result is bitwise the same alone and in a mix
+  of other requests arriving while it runs.
+* Batched results agree with the CPU oracle (1e-12 fp64, 1e-5 fp32).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1808_04960_amd as gw  # noqa: E402
+from paper_1808_04960_amd.serve import GpuExecutor, Server  # noqa: E402
+
+
+def announce(msg):
+    print(f"[gpu-serving] {msg}", file=sys.stderr, flush=True)
+
+
+def make_req(rid, n, R, steps, kind, arrival=0.0, seed=None):
+    if kind == "vortex":
+        g = inputs.grid2d(n, n, (-5.0, -5.0), (5.0, 5.0))
+    else:
+        g = inputs.grid2d(n, n)
+    return inputs.Request(rid, arrival, n, R, steps, kind, g, seed if seed is not None else 1000 + rid)
+
+
+MIX = [(64, 1, 23, "vortex"), (96, 2, 31, "quadrant"), (128, 3, 17, "vortex"), (80, 2, 40, "quadrant"),
+       (64, 3, 29, "quadrant"), (112, 1, 35, "vortex"), (128, 2, 26, "vortex"), (72, 3, 33, "vortex")]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_is_bitwise_the_single_problem_path(prec):
+    announce(f"batch vs single, {prec}")
+    stream = torch.cuda.Stream()
+    reqs = [make_req(i, *m) for i, m in enumerate(MIX)]
+    solvers = []
+    for r in reqs:
+        dx = r.grid.dx[0]
+        s = gw.Solver(r.grid, r.R, 12 * dx, 3 * dx, precision=prec, positivity_fallback=(r.kind == "quadrant"),
+                      U0=r.state(), stream=stream)
+        s.set_end(1e30, r.steps)
+        solvers.append(s)
+    b = gw.Batch(stream)
+    b.set(solvers)
+    b.run(max(r.steps for r in reqs) + 3)   # extra steps must be no-ops for finished problems
+    t, dt, ns, err = b.status()
+    assert list(ns) == [r.steps for r in reqs] and not err.any()
+    for r, s, ti in zip(reqs, solvers, t):
+        dx = r.grid.dx[0]
+        ref = gw.Solver(r.grid, r.R, 12 * dx, 3 * dx, precision=prec, positivity_fallback=(r.kind == "quadrant"),
+                        U0=r.state())
+        n, tr = ref.run(1e30, max_steps=r.steps)
+        assert n == r.steps and tr == ti
+        assert np.array_equal(s.get_state(), ref.get_state()), r
+    b.close()
+
+
+def test_server_alone_equals_mix_bitwise():
+    announce("server alone vs mix")
+    # arrivals closer together than a job lasts: later requests join while earlier
+    # ones run, and wait for slots when all 5 are taken
+    reqs = [make_req(i, *m, arrival=0.0002 * i) for i, m in enumerate(MIX)]
+    budget = 1 << 30
+    mix = Server(GpuExecutor("fp32"), hbm_budget=budget, max_slots=5, steps_per_tick=4).run(reqs, keep_results=True)
+    assert all(j.status == "done" for j in mix.jobs)
+    assert mix.peak_active >= 3      # requests really overlapped on the device
+    for j in mix.jobs:
+        alone = Server(GpuExecutor("fp32"), hbm_budget=budget, max_slots=5, steps_per_tick=7).run(
+            [make_req(j.req.rid, *MIX[j.req.rid], arrival=0.0)], keep_results=True)
+        assert np.array_equal(alone.jobs[0].result, j.result), j.req.rid
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_batched_results_match_oracle(prec, tol):
+    announce(f"batched vs oracle, {prec}")
+    reqs = [make_req(0, 96, 2, 30, "vortex"), make_req(1, 64, 3, 25, "quadrant"), make_req(2, 80, 1, 40, "vortex")]
+    rep = Server(GpuExecutor(prec), hbm_budget=1 << 30, max_slots=8, steps_per_tick=8).run(reqs, keep_results=True)
+    for j in rep.jobs:
+        r = j.req
+        dx = r.grid.dx[0]
+        U = r.state()
+        oracle.OracleSolver(r.grid, r.R, 12 * dx, 3 * dx, positivity_fallback=(r.kind == "quadrant")).run(
+            U, 1e30, max_steps=r.steps)
+        err = np.abs(j.result - U).sum() / np.abs(U).sum()
+        assert err < tol, (r.rid, err)
+
+
+def test_poisson_stream_small():
+    announce("small Poisson stream")
+    reqs = inputs.serving_stream(count=40, rate=200.0, seed=5, sizes=(64, 128, 256), steps=(20, 60))
+    rep = Server(GpuExecutor("fp32"), hbm_budget=256 << 20, max_slots=16, steps_per_tick=8).run(reqs)
+    s = rep.summary()
+    assert s["completed"] == 40 and s["failed"] == 0
+    assert rep.peak_bytes <= 256 << 20
+    assert s["p99_ms"] >= s["p50_ms"] > 0
