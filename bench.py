@@ -54,21 +54,51 @@ def flops_per_cell_sweep(ndim: int, R: int) -> int:
 WORKLOADS = {
     "vortex2d": dict(desc="2D isentropic vortex, 512x512 periodic on [-5,5]^2, strength 5, gamma 1.4, "
                           "GP-R2 (ell=12dx, sigma=3dx), SSP-RK3 CFL 0.4, t=10",
-                     make=lambda: inputs.isentropic_vortex_2d(512), R=2, t_final=10.0),
+                     make=lambda: inputs.isentropic_vortex_2d(512), R=2, t_final=10.0, tag="vortex2d_512_R2"),
     "sine1d": dict(desc="1D sine density wave, N=128 periodic on [0,1], GP-R2, CFL 0.4, t=1",
-                   make=lambda: inputs.sine_wave_1d(128), R=2, t_final=1.0),
+                   make=lambda: inputs.sine_wave_1d(128), R=2, t_final=1.0, tag="sine1d_128_R2"),
     "kh2d": dict(desc="2D Kelvin-Helmholtz, 2048x1024 periodic on [0,2]x[0,1], GP-R3, CFL 0.4",
-                 make=lambda: inputs.kelvin_helmholtz_2d(2048, 1024), R=3, t_final=None),
+                 make=lambda: inputs.kelvin_helmholtz_2d(2048, 1024), R=3, t_final=None, tag="kh2d_2048x1024_R3"),
     "wave3d": dict(desc="3D density wave, 256^3 periodic on [0,1]^3, GP-R2, CFL 0.4",
-                   make=lambda: inputs.density_wave_3d(256), R=2, t_final=None),
+                   make=lambda: inputs.density_wave_3d(256), R=2, t_final=None, tag="wave3d_256_R2"),
     "vortex3d": dict(desc="3D isentropic vortex (w=0), 256^3 periodic on [-5,5]^3, GP-R2, CFL 0.4",
-                     make=lambda: inputs.isentropic_vortex_3d(256), R=2, t_final=None),
+                     make=lambda: inputs.isentropic_vortex_3d(256), R=2, t_final=None, tag="vortex3d_256_R2"),
 }
 
+SERVING_DESC = ("Poisson stream (seed 0, mean 20 req/s) of independent 2D Euler problems, grids uniform from "
+                "{64^2..1024^2}, R in {1,2,3}, 100-500 steps, half isentropic vortex / half random four-quadrant "
+                "Riemann data, FIFO admission by HBM footprint (budget 2 GiB, 64 slots), fp32 sweep arithmetic")
 
-def traffic_from_profiles(kernel_name):
-    """HBM bytes per launch of the kernel from a committed rocprofv3 counter summary,
-    valid only while the kernel source is unchanged (else None)."""
+
+def run_serving(count, budget, slots, steps_per_tick, log):
+    """Replays the serving stream through the continuous-batching server."""
+    from paper_1808_04960_amd.serve import GpuExecutor, Server
+
+    reqs = inputs.serving_stream(count=count, rate=20.0, seed=0)
+    for r in reqs:
+        r.cache_state()
+    offered = sum(3.0 * r.steps * r.cells for r in reqs)
+    ex = GpuExecutor("fp32")
+    # warm the kernels and the allocator on a short private stream of the same mix
+    warm = inputs.serving_stream(count=12, rate=1e6, seed=99, steps=(2, 4))
+    Server(ex, hbm_budget=budget, max_slots=slots, steps_per_tick=steps_per_tick).run(warm)
+    rep = Server(ex, hbm_budget=budget, max_slots=slots, steps_per_tick=steps_per_tick).run(reqs, keep_results=True)
+    s = rep.summary()
+    s["offered_cell_updates"] = offered
+    s["arrival_span_s"] = reqs[-1].arrival - reqs[0].arrival
+    s["what"] = "latency = arrival to result on the host; cell_updates_per_s = work / (last completion - first arrival)"
+    for j in rep.jobs:
+        j.result = None
+    ex.close()
+    log(f"serving: {s['completed']}/{s['requests']} done, p50 {s['p50_ms']:.1f} ms, p99 {s['p99_ms']:.1f} ms, "
+        f"{s['cell_updates_per_s']:.3e} cell-updates/s over {s['makespan_s']:.2f} s, peak {s['peak_active']} active")
+    return s
+
+
+def traffic_from_profiles(kernel_name, tag):
+    """HBM bytes per launch (fetched + written) of the kernel on the workload, from
+    the committed rocprofv3 counter summary; None if there is none or the kernel
+    source changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
@@ -81,9 +111,9 @@ def traffic_from_profiles(kernel_name):
             if not line or line.startswith("#"):
                 continue
             parts = line.split()
-            if len(parts) >= 4:
-                entries[(parts[0], parts[1])] = float(parts[2]) + float(parts[3])
-    return entries.get((kernel_name, sha))
+            if len(parts) >= 5:
+                entries[(parts[0], parts[1], parts[4])] = float(parts[2]) + float(parts[3])
+    return entries.get((kernel_name.replace(" ", ""), sha, tag))
 
 
 def main():
@@ -91,11 +121,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="vortex2d", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="vortex2d", choices=sorted(WORKLOADS) + ["serving"])
     ap.add_argument("--solves", type=int, default=5, help="full solves for latency and exact-solution error")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=100, help="back-to-back launches per timed kernel")
+    ap.add_argument("--serving-requests", type=int, default=200, help="requests of the serving stream (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -112,6 +143,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     W = WORKLOADS[args.workload]
+    if args.workload == "serving":
+        W = dict(desc=SERVING_DESC)
+        s = run_serving(args.serving_requests or 200, 2 << 30, 64, 8, lambda m: print(f"[bench] {m}", file=sys.stderr))
+        print(json.dumps({"metric": METRIC, "value": s["cell_updates_per_s"], "unit": "cell-updates/s", "n_gpus": 1,
+                          "steps": s["ticks"], "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": SERVING_DESC}, "serving": s, "roofline": None,
+                          "cpu_baseline": None}), flush=True)
+        return
     grid, U0 = W["make"]()
     R = W["R"]
     dx = grid.dx[0]
@@ -230,6 +270,11 @@ def main():
             acc[f"{prec}_rel_l1_vs_oracle"] = float(np.abs(Ug - Uo).sum() / np.abs(Uo).sum())
         acc["oracle_steps_compared"] = steps
 
+    serving = None
+    if args.workload == "vortex2d" and args.serving_requests > 0:
+        serving = run_serving(args.serving_requests, 2 << 30, 64, 8, log)
+        serving["workload"] = SERVING_DESC
+
     cu32 = ncell * 3 * args.steps / timing["fp32"]
     cu64 = ncell * 3 * args.steps / timing["fp64"]
     def dominant(prec):
@@ -241,12 +286,12 @@ def main():
     t32, t64 = kern[("fp32", sym32)][0], kern[("fp64", sym64)][0]
     achieved = fl / t32 / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
-            "frac": achieved / PEAK_TFLOPS["fp32"], "traffic": traffic_from_profiles(sym32), "kernel": sym32,
+            "frac": achieved / PEAK_TFLOPS["fp32"], "traffic": traffic_from_profiles(sym32, W["tag"]), "kernel": sym32,
             "avg_launch_us": t32 * 1e6, "flops_per_launch": fl,
             "kernels_us": {k[1]: v[0] * 1e6 for k, v in kern.items()},
             "fp64": {"kernel": sym64, "avg_launch_us": t64 * 1e6, "achieved": fl / t64 / 1e12,
                      "peak": PEAK_TFLOPS["fp64"], "frac": fl / t64 / 1e12 / PEAK_TFLOPS["fp64"],
-                     "traffic": traffic_from_profiles(sym64)}}
+                     "traffic": traffic_from_profiles(sym64, W["tag"])}}
     out = {
         "metric": METRIC,
         "value": cu32,
@@ -266,6 +311,7 @@ def main():
         "accuracy": acc,
         "latency": ({"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
                      "solves": len(lat), "what": "upload + run to t_final + download, fp32 path"} if lat else None),
+        "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
