@@ -206,7 +206,9 @@ def main():
             d = k % grid.ndim
             fin = d == grid.ndim - 1
             sym = f"sweep_kernel<{grid.ndim}, {d}, {R}, {real}, {'true' if fin else 'false'}>"
-            per_sym.setdefault(sym, []).append(e0.elapsed_time(e1) / args.kernel_reps * 1e-3)
+            tk = e0.elapsed_time(e1) / args.kernel_reps * 1e-3
+            per_sym.setdefault(sym, []).append(tk)
+            log(f"  launch {k} (stage {k // grid.ndim + 1}, dir {d}): {tk * 1e6:.1f} us")
         for sym, ts in per_sym.items():
             kern[(prec, sym)] = (float(np.mean(ts)), len(ts))
             log(f"{sym}: {np.mean(ts) * 1e6:.1f} us per launch, {len(ts)} per step")

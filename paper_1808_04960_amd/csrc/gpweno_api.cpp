@@ -300,7 +300,8 @@ int gpweno_set_options(gpweno_ctx* c, const gpweno_options* o) {
     if (changes_rule && c->state) {
         // the CFL number and fixed dt live in the control block
         if (read_ctl(c, user_stream(c))) return GPWENO_EHIP;
-        hipError_t e = gpw::launch_set_time(c->d_ctl, c->h_ctl->t, c->h_ctl->nsteps, c->opt.cfl, c->opt.fixed_dt,
+        hipError_t e = gpw::launch_set_time(c->d_ctl, gpw::current_rec(*c->h_ctl).t,
+                                            gpw::current_rec(*c->h_ctl).nsteps, c->opt.cfl, c->opt.fixed_dt,
                                             user_stream(c));
         if (e != hipSuccess) return fail(c, GPWENO_EHIP, "set_time launch: %s", hipGetErrorString(e));
         const int n[3] = {c->grid.n[0], c->grid.n[1], c->grid.n[2]};
@@ -380,18 +381,18 @@ int gpweno_run(gpweno_ctx* c, double t_final, long max_steps, long* nsteps_out, 
     int st = read_ctl(c, s);
     if (st) return st;
     if ((st = check_err(c))) return st;
-    const long long start = c->h_ctl->nsteps;
+    const long long start = gpw::current_rec(*c->h_ctl).nsteps;
     const long long limit = max_steps < 0 ? LLONG_MAX : start + max_steps;
     hipError_t e = gpw::launch_set_run(c->d_ctl, t_final, limit, s);
     if (e != hipSuccess) return fail(c, GPWENO_EHIP, "set_run launch: %s", hipGetErrorString(e));
-    while (c->h_ctl->t < t_final && c->h_ctl->nsteps < limit) {
+    while (gpw::current_rec(*c->h_ctl).t < t_final && gpw::current_rec(*c->h_ctl).nsteps < limit) {
         if ((st = ensure_graph(c))) return st;
         HIP_TRY(c, hipGraphLaunch(c->graph, s));
         if ((st = read_ctl(c, s))) return st;
         if ((st = check_err(c))) break;
     }
-    if (nsteps_out) *nsteps_out = (long)(c->h_ctl->nsteps - start);
-    if (t_out) *t_out = c->h_ctl->t;
+    if (nsteps_out) *nsteps_out = (long)(gpw::current_rec(*c->h_ctl).nsteps - start);
+    if (t_out) *t_out = gpw::current_rec(*c->h_ctl).t;
     return st;
 }
 
@@ -399,9 +400,10 @@ int gpweno_get_time(gpweno_ctx* c, double* t, double* dt, long* nsteps) {
     if (!c) return fail(nullptr, GPWENO_EINVAL, "NULL context");
     int st = read_ctl(c, user_stream(c));
     if (st) return st;
-    if (t) *t = c->h_ctl->t;
-    if (dt) *dt = c->h_ctl->dt;
-    if (nsteps) *nsteps = (long)c->h_ctl->nsteps;
+    const gpw::StepRec& r = gpw::current_rec(*c->h_ctl);
+    if (t) *t = r.t;
+    if (dt) *dt = r.dt;
+    if (nsteps) *nsteps = (long)r.nsteps;
     return check_err(c);
 }
 

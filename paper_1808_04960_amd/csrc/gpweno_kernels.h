@@ -7,28 +7,48 @@
 namespace gpw {
 
 // Control block in device memory. Every sweep of a step derives the step's dt
-// and its go/no-go decision from these fields, which change only at the end of
-// a step (by the last block of the step's final sweep), so a captured sequence
-// of steps needs no host involvement and no separate time-step kernel.
+// and its go/no-go decision from it, so a captured sequence of steps needs no
+// host involvement and no separate time-step kernel, and closing a step needs
+// no inter-block synchronisation:
+//   * rec[0], rec[1] hold the two most recent step states; the one with the
+//     larger step count is current.
+//   * The first sweep of a step records the running step's count in `started`
+//     (-1 when the step does not run).
+//   * Block 0 of the step's final sweep writes the next step state into the
+//     older record with plain stores. Every other sweep of the step reads the
+//     newer record, which the final sweep never writes; the final sweep itself
+//     reads the record whose count equals `started`. Once the final sweep has
+//     completed, the new record is the newer one.
+//   * The CFL speed of the state with step count n is reduced (atomic max of
+//     the bit images of non-negative doubles) into xcd[.].speed[n & 1], one
+//     cache line per XCD; the first sweep of step n clears slot (n + 1) & 1.
+struct StepRec {
+    double t;          // time of the state
+    double dt;         // time step that produced it (0 for an initial state)
+    long long nsteps;  // steps taken to reach it
+    long long pad;
+};
+
+struct alignas(128) XcdSlot {
+    unsigned long long speed[2];
+};
+
 struct Ctl {
-    double t;               // time at the start of the next step
-    double dt;              // time step of the last completed step
+    StepRec rec[2];
+    long long started;      // step count of the step in flight, -1 if none
     double t_final;         // stop time of the current run
     double cfl;             // CFL number
     double fixed_dt;        // > 0: fixed time step
-    unsigned long long speed[2];  // max_i sum_d (|u_d|+c)/dx_d, bit image of a non-negative
-                                  // double (atomic max); speed[parity] belongs to the state
-                                  // at the start of the next step, the other slot is filled
-                                  // by the step in flight
-    long long nsteps;       // steps taken so far
     long long step_limit;   // a step starts only while nsteps < step_limit
-    int parity;             // which speed slot is current
     int err;                // 1: a stage produced rho <= 0, p <= 0 or NaN
+    int pad;
     long long bad_cell;     // smallest cell index of such a failure
-    unsigned int ticket;    // blocks of the step's final sweep that have finished
-    unsigned int pad;
     double sums[8];         // conserved sums (reduction output)
+    XcdSlot xcd[8];
 };
+
+// The current step state, as the host reads it.
+inline const StepRec& current_rec(const Ctl& c) { return c.rec[0].nsteps > c.rec[1].nsteps ? c.rec[0] : c.rec[1]; }
 
 template <typename Real>
 struct Tab {

@@ -92,14 +92,27 @@ __device__ __forceinline__ int wrap(int x, int n) {
     return r < 0 ? r + n : r;
 }
 
-// Time step of the step in flight and whether it runs. Every sweep of a step
-// reads the same control-block values (they change only when the step ends),
-// so all of them take the same decision and the same dt.
-__device__ __forceinline__ bool step_go(const Ctl* c, double& t0, double& dt, int& par) {
-    t0 = c->t;
-    par = c->parity;
-    if (c->err || !(t0 < c->t_final) || c->nsteps >= c->step_limit) return false;
-    const double speed = __longlong_as_double((long long)c->speed[par]);
+// Time step of the step in flight and whether it runs. final_sweep: the
+// sweep that closes the step (its block 0 writes the next step state).
+__device__ __forceinline__ bool step_go(const Ctl* c, bool final_sweep, double& t0, double& dt, long long& n) {
+    const bool newer0 = c->rec[0].nsteps > c->rec[1].nsteps;
+    int r;
+    if (final_sweep) {
+        const long long st = c->started;
+        if (st < 0) return false;
+        r = (c->rec[0].nsteps == st) ? 0 : 1;
+        if (c->rec[r].nsteps != st) return false;
+    } else {
+        r = newer0 ? 0 : 1;
+    }
+    t0 = c->rec[r].t;
+    n = c->rec[r].nsteps;
+    if (c->err || !(t0 < c->t_final) || n >= c->step_limit) return false;
+    const int par = (int)(n & 1);
+    unsigned long long sb = c->xcd[0].speed[par];
+#pragma unroll
+    for (int x = 1; x < 8; ++x) sb = c->xcd[x].speed[par] > sb ? c->xcd[x].speed[par] : sb;
+    const double speed = __longlong_as_double((long long)sb);
     double d = c->fixed_dt > 0.0 ? c->fixed_dt : c->cfl / speed;
     if (t0 + d > c->t_final) d = c->t_final - t0;
     dt = d;
@@ -108,20 +121,18 @@ __device__ __forceinline__ bool step_go(const Ctl* c, double& t0, double& dt, in
 
 // Conserved -> primitive in the frame rotated to DIR: (rho, u_n[, u_t1[, u_t2]], p).
 template <int NDIM, int DIR>
-__device__ __forceinline__ void cons_to_rot(const double* __restrict__ U, long long ncell, long long cell,
-                                            double gamma, double q[2 + NDIM]) {
+__device__ __forceinline__ void cons_to_rot(const double (&u)[2 + NDIM], double gamma, double q[2 + NDIM]) {
     constexpr int NV = 2 + NDIM;
-    const double rho = U[cell];
+    const double rho = u[0];
     const double irho = frcp(rho);
-    double mom[3] = {0.0, 0.0, 0.0}, vel[3] = {0.0, 0.0, 0.0};
+    double vel[3] = {0.0, 0.0, 0.0};
     double ke = 0.0;
 #pragma unroll
     for (int d = 0; d < NDIM; ++d) {
-        mom[d] = U[(1 + d) * ncell + cell];
-        vel[d] = mom[d] * irho;
-        ke += vel[d] * mom[d];
+        vel[d] = u[1 + d] * irho;
+        ke += vel[d] * u[1 + d];
     }
-    const double E = U[(NV - 1) * ncell + cell];
+    const double E = u[NV - 1];
     q[0] = rho;
     q[1] = vel[DIR];
     if (NDIM >= 2) q[2] = vel[t1_axis(DIR)];
@@ -404,20 +415,28 @@ __device__ __forceinline__ long long xcd_logical_block() {
     return (long long)(xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3));
 }
 
-// One block of a sweep: logical block L of the problem's nblk blocks.
+// One block of a sweep: logical block L of the problem's blocks.
 template <int NDIM, int DIR, int R, typename Real, bool FIN>
-__device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long long L, const unsigned nblk,
-                                            unsigned char* smem, unsigned long long* sred) {
+__device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long long L, unsigned char* smem,
+                                            unsigned long long* sred) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     constexpr int NV = C::NV, WPB = C::WPB, PITCH = C::PITCH, SLEN = C::SLEN, THREADS = C::THREADS;
     Real* sV = reinterpret_cast<Real*>(smem);
     double* sO = reinterpret_cast<double*>(smem);
 
     double t0 = 0.0, dt = 0.0;
-    int par = 0;
+    long long nstep = 0;
     if (a.stage > 0) {
-        if (!step_go(a.ctl, t0, dt, par)) return;
-        if (a.step_start && L == 0 && threadIdx.x == 0) a.ctl->speed[1 - par] = 0ull;
+        const bool go = step_go(a.ctl, FIN && a.stage == 3, t0, dt, nstep);
+        if (a.step_start && L == 0 && threadIdx.x == 0) {
+            // mark the step as running (or not) and clear the next speed slot
+            a.ctl->started = go ? nstep : -1;
+            if (go) {
+#pragma unroll
+                for (int x = 0; x < 8; ++x) a.ctl->xcd[x].speed[(nstep + 1) & 1] = 0ull;
+            }
+        }
+        if (!go) return;
     }
 
     const int tid = threadIdx.x;
@@ -486,7 +505,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             if (!a.first) pd[k] = a.dU[k * nc + ecell];
-            if (FIN) pu[k] = a.U[k * nc + ecell];
+            if (FIN && DIR == 0) pu[k] = a.U[k * nc + ecell];
             if (FIN && a.stage >= 2) pn[k] = a.Un[k * nc + ecell];
         }
     }
@@ -502,7 +521,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
                 double q[NV];
                 if (c < ncol_valid) {
                     const long long cell = blk_base + c * cstride + wrap(sbase + pos, N);
-                    cons_to_rot<NDIM, DIR>(a.U, nc, cell, gamma, q);
+                    double u[NV];
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) u[k] = a.U[k * nc + cell];
+                    cons_to_rot<NDIM, DIR>(u, gamma, q);
                 } else {
 #pragma unroll
                     for (int k = 0; k < NV; ++k) q[k] = (k == 0 || k == NV - 1) ? 1.0 : 0.0;
@@ -511,12 +533,24 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
                 for (int k = 0; k < NV; ++k) sV[k * FS + c * PITCH + pos] = (Real)q[k];
             }
         } else {
+            // rows are dealt rotated by LEFT + R, so that in the first round thread
+            // t loads the cell it finishes in the epilogue (row t / WPB of the
+            // output tile) and keeps its float64 conserved values
             const int c = tid % WPB;
-            for (int idx = tid / WPB; idx < SLEN; idx += THREADS / WPB) {
+            constexpr int ROWS = THREADS / WPB;
+            for (int p = tid / WPB; p < SLEN; p += ROWS) {
+                const int idx = (p + LEFT + R) % SLEN;
                 double q[NV];
                 if (c < ncol_valid) {
                     const long long cell = blk_base + c * cstride + (long long)wrap(sbase + idx, N) * stride;
-                    cons_to_rot<NDIM, DIR>(a.U, nc, cell, gamma, q);
+                    double u[NV];
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) u[k] = a.U[k * nc + cell];
+                    if (FIN && p == tid / WPB && ecell >= 0) {
+#pragma unroll
+                        for (int k = 0; k < NV; ++k) pu[k] = u[k];
+                    }
+                    cons_to_rot<NDIM, DIR>(u, gamma, q);
                 } else {
 #pragma unroll
                     for (int k = 0; k < NV; ++k) q[k] = (k == 0 || k == NV - 1) ? 1.0 : 0.0;
@@ -573,12 +607,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
         }
     }
     if (FIN && a.stage == 3) {
-        // CFL speed of the new state into the next step's slot; then the last
-        // block to take a ticket closes the step. It writes only values every
-        // block derived at its start from the unchanged control block, and the
-        // next kernel on the stream sees them (and every speed update) after
-        // this kernel completes, so no fence is needed: an agent-scope fence
-        // would write back and invalidate the L2 of the XCD once per block.
+        // CFL speed of the new state into the next step's slot (one atomic per
+        // block, no return value), and block 0 closes the step by writing the
+        // next step state into the older record (see Ctl).
         smax = wave_max_u64(smax);
         if (lane == 0) sred[w] = smax;
         __syncthreads();
@@ -587,14 +618,12 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
 #pragma unroll
             for (int i = 1; i < WPB; ++i) m = sred[i] > m ? sred[i] : m;
             Ctl* c = a.ctl;
-            atomicMax(&c->speed[1 - par], m);
-            const unsigned int done = atomicAdd(&c->ticket, 1u);
-            if (done == nblk - 1) {
-                c->t = t0 + dt;
-                c->dt = dt;
-                c->nsteps = c->nsteps + 1;
-                c->parity = 1 - par;
-                c->ticket = 0u;
+            atomicMax(&c->xcd[blockIdx.x & 7u].speed[(nstep + 1) & 1], m);
+            if (L == 0) {
+                const int older = (c->rec[0].nsteps == nstep) ? 1 : 0;
+                c->rec[older].t = t0 + dt;
+                c->rec[older].dt = dt;
+                c->rec[older].nsteps = nstep + 1;
             }
         }
     }
@@ -606,7 +635,7 @@ sweep_kernel(const SweepArgs<Real> a) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
     __shared__ unsigned long long sred[C::WPB];
-    sweep_block<NDIM, DIR, R, Real, FIN>(a, xcd_logical_block(), gridDim.x, smem, sred);
+    sweep_block<NDIM, DIR, R, Real, FIN>(a, xcd_logical_block(), smem, sred);
 }
 
 // Batched sweep over many independent problems (same ndim, R, precision and
@@ -644,7 +673,7 @@ sweep_batch_kernel(const BatchArgs<Real> ba) {
     a.stage = ba.stage;
     a.step_start = ba.step_start;
     a.tab = ba.tab;
-    sweep_block<NDIM, DIR, R, Real, FIN>(a, Lg - P.block0, P.nblk, smem, sred);
+    sweep_block<NDIM, DIR, R, Real, FIN>(a, Lg - P.block0, smem, sred);
 }
 
 // ---------------------------------------------------------------------------
@@ -655,22 +684,25 @@ __global__ void set_run_kernel(Ctl* c, double t_final, long long step_limit) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     c->t_final = t_final;
     c->step_limit = step_limit;
-    c->ticket = 0u;
 }
 
 __global__ void set_time_kernel(Ctl* c, double t, long long nsteps, double cfl, double fixed_dt) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    c->t = t;
-    c->dt = 0.0;
-    c->nsteps = nsteps;
+    c->rec[0].t = t;
+    c->rec[0].dt = 0.0;
+    c->rec[0].nsteps = nsteps;
+    c->rec[1].t = t;
+    c->rec[1].dt = 0.0;
+    c->rec[1].nsteps = nsteps - 1;
+    c->started = -1;
     c->cfl = cfl;
     c->fixed_dt = fixed_dt;
     c->err = 0;
     c->bad_cell = LLONG_MAX;
-    c->speed[0] = 0ull;
-    c->speed[1] = 0ull;
-    c->parity = 0;
-    c->ticket = 0u;
+    for (int x = 0; x < 8; ++x) {
+        c->xcd[x].speed[0] = 0ull;
+        c->xcd[x].speed[1] = 0ull;
+    }
 }
 
 // CFL speed max_i sum_d (|u_d| + c)/dx_d of a state, with the physical check.
@@ -708,7 +740,8 @@ __global__ void __launch_bounds__(256) speed_kernel(const double* __restrict__ U
     if (threadIdx.x == 0) {
         unsigned long long m = sred[0];
         for (int i = 1; i < 4; ++i) m = sred[i] > m ? sred[i] : m;
-        atomicMax(&ctl->speed[ctl->parity], m);
+        const long long n = ctl->rec[0].nsteps > ctl->rec[1].nsteps ? ctl->rec[0].nsteps : ctl->rec[1].nsteps;
+        atomicMax(&ctl->xcd[blockIdx.x & 7u].speed[n & 1], m);
     }
     (void)n0;
     (void)n1;
@@ -862,9 +895,10 @@ __global__ void gather_status_kernel(Ctl* const* ctls, int nprob, BatchStatus* o
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nprob) return;
     const Ctl* c = ctls[p];
-    out[p].t = c->t;
-    out[p].dt = c->dt;
-    out[p].nsteps = c->nsteps;
+    const StepRec& r = c->rec[0].nsteps > c->rec[1].nsteps ? c->rec[0] : c->rec[1];
+    out[p].t = r.t;
+    out[p].dt = r.dt;
+    out[p].nsteps = r.nsteps;
     out[p].err = c->err;
     out[p].pad = 0;
 }

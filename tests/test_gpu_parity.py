@@ -228,3 +228,33 @@ def test_step_kernels_compose_a_step():
     b.run(10.0, max_steps=2)
     assert a.time() == b.time()
     assert np.array_equal(a.get_state(), b.get_state())
+
+
+@pytest.mark.parametrize("R,Ns,expect", [(1, (32, 64, 128, 256), 3.0), (2, (32, 64, 128, 256), 5.0),
+                                         (3, (32, 64, 128), 7.0)])
+def test_gpu_convergence_orders(R, Ns, expect):
+    """The GPU path (float64) reaches the design order 2R+1 on the advected sine
+    wave with ell fixed in physical units (0.1) and dt reduced as dx^((2R+1)/3);
+    at every resolution it also matches the oracle run."""
+    announce(f"convergence R={R}")
+    errs = []
+    for N in Ns:
+        g, U = inputs.sine_wave_1d(N)
+        _, Ue = inputs.sine_wave_1d(N, t=1.0)
+        dx = g.dx[0]
+        o = oracle.OracleSolver(g, R, 0.1, 3 * dx)
+        smax = o.max_speed(U) * dx
+        dt = 0.4 * (1 / 32) / smax * (dx * 32) ** ((2 * R + 1) / 3)
+        n = math.ceil(1.0 / dt)
+        s = gw.Solver(g, R, 0.1, 3 * dx, fixed_dt=1.0 / n, U0=U)
+        steps, _ = s.run(1e9, max_steps=n)
+        assert steps == n
+        Ug = s.get_state()
+        Uo = U.copy()
+        o.run_fixed(Uo, 1.0 / n, n)
+        assert rel_l1(Ug, Uo) < 1e-11
+        errs.append(float(np.mean(np.abs(Ug[0] - Ue[0]))))
+    orders = [math.log(errs[i] / errs[i + 1]) / math.log(2) for i in range(len(errs) - 1)]
+    announce(f"  L1 {errs} orders {orders}")
+    assert orders[-1] == pytest.approx(expect, abs=0.15), (errs, orders)
+    assert min(orders) > expect - 0.4
