@@ -17,7 +17,7 @@ import subprocess
 
 import numpy as np
 
-from .tables import gp_tables  # noqa: F401
+from .tables import SCHEMES, gp_tables, scheme_tables  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gpweno_oracle.c")
@@ -48,6 +48,8 @@ class Cfg(ctypes.Structure):
         ("gp", ctypes.c_double * 12),
         ("gm", ctypes.c_double * 12),
         ("P", ctypes.c_double * 48),
+        ("beta_form", ctypes.c_int),
+        ("B", ctypes.c_double * 192),
     ]
 
 
@@ -77,7 +79,7 @@ def lib():
         L.oracle_run_fixed.restype = ctypes.c_long
         L.oracle_run_fixed.argtypes = [ctypes.POINTER(Cfg), _dp, ctypes.c_double, ctypes.c_long]
         L.oracle_gp_weno.restype = None
-        L.oracle_gp_weno.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_gp_weno.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         L.oracle_hllc.restype = None
         L.oracle_hllc.argtypes = [_dp, _dp, ctypes.c_double, _dp]
         L.oracle_flux_hat.restype = ctypes.c_double
@@ -107,8 +109,9 @@ def _ptr(a: np.ndarray):
 # Thin wrappers over the per-step building blocks (used by the pin tests).
 # ----------------------------------------------------------------------------
 def gp_weno(f, tab):
-    """GP-WENO interpolation of one variable; ``f`` has 2R+1 entries.
-    Returns (q+, q-, beta, omega+, omega-)."""
+    """WENO interpolation of one variable; ``f`` has 2R+1 entries. ``tab`` is a
+    table dict (``gp_tables`` or ``scheme_tables``); a 'B' beta form selects the
+    polynomial smoothness indicator. Returns (q+, q-, beta, omega+, omega-)."""
     f = np.ascontiguousarray(f, dtype=np.float64)
     R = (len(f) - 1) // 2
     qp = ctypes.c_double()
@@ -117,8 +120,11 @@ def gp_weno(f, tab):
     omp = np.zeros(4)
     omm = np.zeros(4)
     arrs = [np.ascontiguousarray(tab[k], dtype=np.float64) for k in ("w+", "w-", "gamma+", "gamma-", "P")]
-    lib().oracle_gp_weno(R, _ptr(f), *[_ptr(a) for a in arrs], ctypes.byref(qp), ctypes.byref(qm),
-                         _ptr(beta), _ptr(omp), _ptr(omm))
+    B = None
+    if tab.get("beta_form") == "B":
+        B = np.ascontiguousarray(tab["B"], dtype=np.float64)
+    lib().oracle_gp_weno(R, _ptr(f), *[_ptr(a) for a in arrs], _ptr(B) if B is not None else None,
+                         ctypes.byref(qp), ctypes.byref(qm), _ptr(beta), _ptr(omp), _ptr(omm))
     return qp.value, qm.value, beta[: R + 1], omp[: R + 1], omm[: R + 1]
 
 
@@ -155,9 +161,10 @@ def rk3_combine(stage, Un, Uin, L, dt):
 # Whole-scheme driver.
 # ----------------------------------------------------------------------------
 class OracleSolver:
-    """FP64 CPU reference solver. ``ell`` and ``sigma`` are physical lengths."""
+    """FP64 CPU reference solver. ``ell`` and ``sigma`` are physical lengths.
+    ``scheme`` is one of ``SCHEMES`` (default: the paper's GP-WENO)."""
 
-    def __init__(self, grid, R, ell, sigma, gamma=1.4, cfl=0.4, positivity_fallback=False):
+    def __init__(self, grid, R, ell, sigma, gamma=1.4, cfl=0.4, positivity_fallback=False, scheme="gp-weno"):
         self.grid = grid
         self.R = R
         self.cfl = cfl
@@ -171,8 +178,11 @@ class OracleSolver:
         c.positivity_fallback = 1 if positivity_fallback else 0
         self.tables = []
         for d in range(grid.ndim):
-            t = gp_tables(R, ell / grid.dx[d], sigma / grid.dx[d])
+            t = scheme_tables(scheme, R, ell / grid.dx[d], sigma / grid.dx[d])
             self.tables.append(t)
+            c.beta_form = 1 if t["beta_form"] == "B" else 0
+            for idx, v in enumerate(np.asarray(t["B"]).ravel()):
+                c.B[64 * d + idx] = v
             for m in range(4):
                 c.gp[4 * d + m] = t["gamma+"][m]
                 c.gm[4 * d + m] = t["gamma-"][m]

@@ -59,6 +59,9 @@ typedef struct {
     double gp[3][4];        /* gamma_m for x_* = +1/2 */
     double gm[3][4];        /* gamma_m for x_* = -1/2 */
     double P[3][4][4];      /* rows P_i = v_i / sqrt(lambda_i) of K_m(sigma) */
+    int beta_form;          /* 0: beta_m = sum_i (P_i . f_m)^2 (GP, Eq. (beta-eigen));
+                               1: beta_m = f_m^T B_m f_m (polynomial, Jiang-Shu type) */
+    double B[3][4][4][4];   /* [d][m][i][j], used when beta_form = 1 */
 } oracle_cfg;
 
 /* Primitive vector in a frame rotated to direction d:
@@ -178,11 +181,19 @@ void oracle_char_vectors(const double *q, double gamma, double *Lm, double *Rm) 
  * Sub-stencil m = 0..R holds f[m .. m+R]. beta is shared by the two
  * prediction points because the sub-stencils are the same sets.
  * Optional outputs (may be NULL): beta[R+1], omega_p[R+1], omega_m[R+1].
+ *
+ * The same function serves the paper's comparison schemes (Sec. 6.2, Table
+ * (weno-vortex)) with other tables: polynomial (Lagrange) weights and linear
+ * weights in w and gamma, and, when B is given, the polynomial smoothness
+ * indicator beta_m = f_m^T B_m f_m of the Jiang-Shu type (sum over derivative
+ * orders of the squared derivatives of the interpolant, integrated over the
+ * centre cell) in place of the GP one. The weight formula is unchanged.
  * ------------------------------------------------------------------------- */
 void oracle_gp_weno(int R, const double *f,
                     const double *wp, const double *wm,   /* [4][4] */
                     const double *gp, const double *gm,   /* [4] */
                     const double *P,                      /* [4][4] */
+                    const double *B,                      /* [4][4][4] or NULL */
                     double *qplus, double *qminus,
                     double *beta_out, double *omp_out, double *omm_out) {
     double beta[RMAX + 1], qp[RMAX + 1], qm[RMAX + 1];
@@ -191,10 +202,16 @@ void oracle_gp_weno(int R, const double *f,
     for (int m = 0; m <= R; ++m) {
         const double *fm = f + m;
         double b = 0.0;
-        for (int i = 0; i <= R; ++i) {
-            double proj = 0.0;
-            for (int j = 0; j <= R; ++j) proj += P[4 * i + j] * fm[j];
-            b += proj * proj;
+        if (B) {
+            /* quadratic form of the polynomial smoothness indicator */
+            for (int i = 0; i <= R; ++i)
+                for (int j = 0; j <= R; ++j) b += B[16 * m + 4 * i + j] * fm[i] * fm[j];
+        } else {
+            for (int i = 0; i <= R; ++i) {
+                double proj = 0.0;
+                for (int j = 0; j <= R; ++j) proj += P[4 * i + j] * fm[j];
+                b += proj * proj;
+            }
         }
         beta[m] = b;
         double a = 0.0, z = 0.0;
@@ -288,7 +305,8 @@ static int reconstruct_cell(const oracle_cfg *c, int d, const double (*qs)[5],
             f[s] = w;
         }
         oracle_gp_weno(R, f, &c->wp[d][0][0], &c->wm[d][0][0], c->gp[d], c->gm[d],
-                       &c->P[d][0][0], &Wp[k], &Wm[k], NULL, NULL, NULL);
+                       &c->P[d][0][0], c->beta_form ? &c->B[d][0][0][0] : NULL,
+                       &Wp[k], &Wm[k], NULL, NULL, NULL);
     }
     for (int q = 0; q < 5; ++q) {
         double ap = 0.0, am = 0.0;

@@ -29,6 +29,7 @@ the nodes m-R .. m, i.e. entries m .. m+R of the 2R+1 stencil vector.
 from __future__ import annotations
 
 import functools
+from fractions import Fraction
 
 import mpmath as mp
 import numpy as np
@@ -93,14 +94,23 @@ def gp_tables_mp(R: int, ell: str, sigma: str, dps: int = DEFAULT_DPS):
             out["w" + key] = wsub
             out["gamma" + key] = list(gam)
         # step 1(d): one eigensystem of K_m(sigma), identical for every m on a uniform grid
-        Ks = _kernel_matrix(nodes[: R + 1], sigm)
-        lam, Q = mp.eigsy(Ks)
-        P = []
-        for i in range(R + 1):
-            P.append([Q[j, i] / mp.sqrt(lam[i]) for j in range(R + 1)])
+        P, lam = gp_beta_rows_mp(R, sigma, dps)
         out["P"] = P
-        out["lambda"] = list(lam)
+        out["lambda"] = lam
         return out
+
+
+@functools.lru_cache(maxsize=64)
+def gp_beta_rows_mp(R: int, sigma: str, dps: int = DEFAULT_DPS):
+    """Rows P_i = v_i / sqrt(lambda_i) of the eigensystem of K_m(sigma) (Sec. 3.4,
+    Eq. (beta-eigen)), so that beta_m = sum_i (P_i . f_m)^2. ``sigma`` is a decimal
+    string in units of dx. Returns (P as list [i][j], eigenvalues)."""
+    with mp.workdps(dps):
+        nodes = [mp.mpf(j) for j in range(R + 1)]
+        Ks = _kernel_matrix(nodes, mp.mpf(sigma))
+        lam, Q = mp.eigsy(Ks)
+        P = [[Q[j, i] / mp.sqrt(lam[i]) for j in range(R + 1)] for i in range(R + 1)]
+        return P, list(lam)
 
 
 def _dec(x) -> str:
@@ -126,3 +136,160 @@ def gp_tables(R: int, ell_over_dx: float, sigma_over_dx: float, dps: int = DEFAU
     return {"w+": wp, "w-": wm, "gamma+": gp, "gamma-": gm, "P": P,
             "wstar+": np.array([float(v) for v in t["wstar+"]]),
             "wstar-": np.array([float(v) for v in t["wstar-"]])}
+
+
+# ----------------------------------------------------------------------------
+# Polynomial WENO interpolation (the paper's comparison schemes, Sec. 6.2,
+# Table (weno-vortex)): exact rational arithmetic.
+# ----------------------------------------------------------------------------
+def _pmul(a, b):
+    out = [Fraction(0)] * (len(a) + len(b) - 1)
+    for i, x in enumerate(a):
+        for j, y in enumerate(b):
+            out[i + j] += x * y
+    return out
+
+
+def _pder(a):
+    return [k * a[k] for k in range(1, len(a))] or [Fraction(0)]
+
+
+def _peval(a, x):
+    return sum(c * x ** k for k, c in enumerate(a))
+
+
+def _pint(a, lo, hi):
+    return sum(c * (hi ** (k + 1) - lo ** (k + 1)) / (k + 1) for k, c in enumerate(a))
+
+
+def _lagrange_basis(nodes):
+    """Coefficients (ascending powers) of the Lagrange basis polynomials."""
+    basis = []
+    for j, xj in enumerate(nodes):
+        p = [Fraction(1)]
+        for k, xk in enumerate(nodes):
+            if k != j:
+                p = _pmul(p, [Fraction(-xk, xj - xk), Fraction(1, xj - xk)])
+        basis.append(p)
+    return basis
+
+
+def _solve_exact(A, b):
+    """Gauss-Jordan elimination on Fractions (A square, non-singular)."""
+    n = len(A)
+    M = [list(A[i]) + [b[i]] for i in range(n)]
+    for c in range(n):
+        piv = next(r for r in range(c, n) if M[r][c] != 0)
+        M[c], M[piv] = M[piv], M[c]
+        for r in range(n):
+            if r != c and M[r][c] != 0:
+                f = M[r][c] / M[c][c]
+                M[r] = [x - f * y for x, y in zip(M[r], M[c])]
+    return [M[i][n] / M[i][i] for i in range(n)]
+
+
+@functools.lru_cache(maxsize=8)
+def poly_weno_tables_exact(R: int):
+    """Tables of polynomial WENO interpolation of point values (FD-Prim), exact.
+
+    Nodes at the integers -R..R, sub-stencil m holding nodes m-R..m, prediction
+    points x_* = +1/2 and -1/2 (as for the GP tables).
+      'w+', 'w-'         : [m][j] Lagrange interpolation weights on S_m at x_*;
+      'wstar+', 'wstar-' : the same on the whole stencil;
+      'gamma+', 'gamma-' : linear weights, the exact solution of M gamma = w_*
+                           (the same system as Eq. (gamm-system), which is
+                           consistent for polynomial weights);
+      'B'                : [m][i][j] smoothness-indicator quadratic forms of the
+                           Jiang-Shu type, beta_m = f_m^T B_m f_m: the sum over
+                           derivative orders l = 1..R of the integral over the
+                           centre cell [-1/2, 1/2] of the squared l-th derivative
+                           of the interpolating polynomial on S_m (grid spacing 1,
+                           so the dx^(2l-1) scale factors are 1).
+    """
+    nodes = list(range(-R, R + 1))
+    out = {}
+    for sign, key in ((1, "+"), (-1, "-")):
+        xs = Fraction(sign, 2)
+        wstar = [_peval(p, xs) for p in _lagrange_basis(nodes)]
+        wsub = [[_peval(p, xs) for p in _lagrange_basis(nodes[m : m + R + 1])] for m in range(R + 1)]
+        M = [[Fraction(0)] * (R + 1) for _ in range(2 * R + 1)]
+        for n in range(R + 1):
+            for j in range(R + 1):
+                M[n + j][n] = wsub[n][j]
+        MtM = [[sum(M[r][a] * M[r][b] for r in range(2 * R + 1)) for b in range(R + 1)] for a in range(R + 1)]
+        Mtw = [sum(M[r][a] * wstar[r] for r in range(2 * R + 1)) for a in range(R + 1)]
+        gam = _solve_exact(MtM, Mtw)
+        for r in range(2 * R + 1):
+            if sum(M[r][a] * gam[a] for a in range(R + 1)) != wstar[r]:
+                raise ArithmeticError("polynomial linear-weight system is not consistent")
+        out["wstar" + key] = wstar
+        out["w" + key] = wsub
+        out["gamma" + key] = gam
+    B = []
+    half = Fraction(1, 2)
+    for m in range(R + 1):
+        basis = _lagrange_basis(nodes[m : m + R + 1])
+        Bm = [[Fraction(0)] * (R + 1) for _ in range(R + 1)]
+        ders = [basis]
+        for _ in range(R):
+            ders.append([_pder(p) for p in ders[-1]])
+        for l in range(1, R + 1):
+            for i in range(R + 1):
+                for j in range(R + 1):
+                    Bm[i][j] += _pint(_pmul(ders[l][i], ders[l][j]), -half, half)
+        B.append(Bm)
+    out["B"] = B
+    return out
+
+
+SCHEMES = ("gp-weno", "weno-js", "weno-gp")
+
+
+def scheme_tables(scheme: str, R: int, ell_over_dx: float, sigma_over_dx: float, dps: int = DEFAULT_DPS):
+    """Float64 tables for the C oracle, for one of three interpolation schemes:
+
+      'gp-weno' : GP weights and linear weights, GP smoothness indicators
+                  (the paper's method);
+      'weno-js' : polynomial weights and linear weights, Jiang-Shu smoothness
+                  indicators (the classical comparison scheme, R = 1, 2);
+      'weno-gp' : polynomial weights and linear weights, GP smoothness
+                  indicators (the hybrid of Sec. 6.2, Table (weno-vortex)).
+
+    All three use the nonlinear weights of Eq. (weights) with p = 2, eps = 1e-36.
+    'beta_form' is 'P' (beta = sum_i (P_i . f)^2) or 'B' (beta = f^T B_m f).
+    """
+    if scheme not in SCHEMES:
+        raise ValueError(scheme)
+    if scheme == "gp-weno":
+        t = gp_tables(R, ell_over_dx, sigma_over_dx, dps)
+        t["beta_form"] = "P"
+        t["B"] = np.zeros((4, 4, 4))
+        return t
+    if scheme == "weno-js" and R not in (1, 2):
+        raise ValueError("WENO-JS smoothness indicators are defined here for R = 1, 2")
+    e = poly_weno_tables_exact(R)
+    t = {k: np.zeros((4, 4)) for k in ("w+", "w-", "P")}
+    t["gamma+"] = np.zeros(4)
+    t["gamma-"] = np.zeros(4)
+    t["B"] = np.zeros((4, 4, 4))
+    for m in range(R + 1):
+        t["gamma+"][m] = float(e["gamma+"][m])
+        t["gamma-"][m] = float(e["gamma-"][m])
+        for j in range(R + 1):
+            t["w+"][m, j] = float(e["w+"][m][j])
+            t["w-"][m, j] = float(e["w-"][m][j])
+    t["wstar+"] = np.array([float(v) for v in e["wstar+"]])
+    t["wstar-"] = np.array([float(v) for v in e["wstar-"]])
+    if scheme == "weno-js":
+        t["beta_form"] = "B"
+        for m in range(R + 1):
+            for i in range(R + 1):
+                for j in range(R + 1):
+                    t["B"][m, i, j] = float(e["B"][m][i][j])
+    else:
+        t["beta_form"] = "P"
+        P, _ = gp_beta_rows_mp(R, _dec(sigma_over_dx), dps)
+        for i in range(R + 1):
+            for j in range(R + 1):
+                t["P"][i, j] = float(P[i][j])
+    return t
