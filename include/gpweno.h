@@ -66,6 +66,18 @@ typedef struct {
     double hi[3];          /* domain upper corner */
 } gpweno_grid;
 
+/* Interpolation scheme of the Riemann states. GP-WENO is the paper's method;
+ * the other two are its comparison schemes (Sec. 6.2, Table (weno-vortex)):
+ * polynomial WENO interpolation (Lagrange weights on the sub-stencils, their
+ * linear weights) with the classical Jiang-Shu smoothness indicators, or with
+ * the GP smoothness indicators of Eq. (beta-eigen). All three use the
+ * nonlinear weights of Eq. (weights) with p = 2, eps = 1e-36. */
+typedef enum {
+    GPWENO_GP_WENO = 0,    /* GP weights, GP linear weights, GP indicators (R = 1..3) */
+    GPWENO_WENO_JS = 1,    /* polynomial weights, Jiang-Shu indicators (R = 1, 2) */
+    GPWENO_WENO_GP = 2     /* polynomial weights, GP indicators with sigma (R = 1..3) */
+} gpweno_scheme;
+
 typedef struct {
     int precision;         /* gpweno_precision */
     double cfl;            /* CFL number of the time-step rule (default 0.4) */
@@ -90,6 +102,13 @@ typedef struct gpweno_ctx gpweno_ctx;
  * Host-side work plus one small device allocation (the control block). */
 int gpweno_init(const gpweno_grid *grid, int R, double ell, double sigma, double gamma,
                 gpweno_ctx **out);
+
+/* gpweno_init for any gpweno_scheme: the same context, with the scheme's tables
+ * in place of the GP ones. ell is used only by GPWENO_GP_WENO; sigma (> dx) by
+ * the two schemes with GP indicators, and validated for all. Errors: as
+ * gpweno_init, and EINVAL for an unknown scheme or WENO-JS with R = 3. */
+int gpweno_init_scheme(const gpweno_grid *grid, int scheme, int R, double ell, double sigma,
+                       double gamma, gpweno_ctx **out);
 
 /* Options (host pointer, copied). Changing the precision or positivity flag
  * drops any captured graph. Errors: EINVAL. */
@@ -162,13 +181,16 @@ int gpweno_rhs_dir(gpweno_ctx *ctx, int dir, const double *d_U, double *d_L, int
  * state, written to host out[nv], by a deterministic device reduction. */
 int gpweno_conserved_sums(gpweno_ctx *ctx, double *out);
 
-/* Host-only (no device needed): the pre-simulation tables of gpweno_init for
- * stencil radius R and length scales in units of dx (ell_over_dx, sigma_over_dx).
+/* Host-only (no device needed): the pre-simulation tables of gpweno_init_scheme
+ * for a scheme (gpweno_scheme), stencil radius R and length scales in units of
+ * dx (ell_over_dx, sigma_over_dx; ell is unused by the polynomial schemes).
  * Outputs are host arrays, row-major, padded to 4: w_plus[4][4], w_minus[4][4]
  * (sub-stencil m = 0..R, node j = 0..R; sub-stencil m holds nodes m-R..m
- * relative to the centre cell), gam_plus[4], gam_minus[4], P[4][4] (row i is
- * v_i / sqrt(lambda_i)); any output may be NULL. Errors: EINVAL. */
-int gpweno_compute_tables(int R, double ell_over_dx, double sigma_over_dx,
+ * relative to the centre cell), gam_plus[4], gam_minus[4], and P[4][4][4] with
+ * beta_m = sum_i (P[m][i] . f_m)^2 (GP: row i is v_i / sqrt(lambda_i) of
+ * K_m(sigma), Eq. (beta-eigen), the same for every m). Any output may be NULL.
+ * Errors: EINVAL (also WENO-JS with R = 3). */
+int gpweno_compute_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx,
                           double *w_plus, double *w_minus, double *gam_plus,
                           double *gam_minus, double *P);
 

@@ -56,6 +56,8 @@ def lib():
         vp = ctypes.c_void_p
         L.gpweno_init.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.POINTER(vp)]
+        L.gpweno_init_scheme.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_double, ctypes.POINTER(vp)]
         L.gpweno_set_options.argtypes = [vp, ctypes.POINTER(_Options)]
         L.gpweno_get_options.argtypes = [vp, ctypes.POINTER(_Options)]
         L.gpweno_state_count.argtypes = [vp]
@@ -71,7 +73,8 @@ def lib():
         L.gpweno_rhs_dir.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int]
         L.gpweno_step_kernel.argtypes = [vp, ctypes.c_int]
         L.gpweno_conserved_sums.argtypes = [vp, _dp]
-        L.gpweno_compute_tables.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp, _dp]
+        L.gpweno_compute_tables.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp,
+                                            _dp, _dp, _dp]
         L.gpweno_set_end.argtypes = [vp, ctypes.c_double, ctypes.c_long]
         L.gpweno_batch_create.argtypes = [ctypes.POINTER(vp)]
         L.gpweno_batch_set.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, vp]
@@ -104,12 +107,23 @@ def _check(code, ctx=None):
         raise GpwenoError(code, msg)
 
 
-def compute_tables(R, ell_over_dx, sigma_over_dx):
-    """Host-only pre-simulation tables (binary128 arithmetic rounded to float64)."""
-    wp, wm, P = np.zeros((4, 4)), np.zeros((4, 4)), np.zeros((4, 4))
+SCHEMES = {"gp-weno": 0, "weno-js": 1, "weno-gp": 2}   # gpweno_scheme
+
+
+def _scheme_id(scheme):
+    if scheme not in SCHEMES:
+        raise GpwenoError(EINVAL, f"unknown scheme {scheme!r}; one of {sorted(SCHEMES)}")
+    return SCHEMES[scheme]
+
+
+def compute_tables(R, ell_over_dx, sigma_over_dx, scheme="gp-weno"):
+    """Host-only pre-simulation tables (binary128 arithmetic rounded to float64).
+    'P' has shape (4, 4, 4): beta_m = sum_i (P[m, i] . f_m)^2."""
+    wp, wm, P = np.zeros((4, 4)), np.zeros((4, 4)), np.zeros((4, 4, 4))
     gp, gm = np.zeros(4), np.zeros(4)
     ptr = lambda a: a.ctypes.data_as(_dp)  # noqa: E731
-    _check(lib().gpweno_compute_tables(R, ell_over_dx, sigma_over_dx, ptr(wp), ptr(wm), ptr(gp), ptr(gm), ptr(P)))
+    _check(lib().gpweno_compute_tables(_scheme_id(scheme), R, ell_over_dx, sigma_over_dx, ptr(wp), ptr(wm),
+                                       ptr(gp), ptr(gm), ptr(P)))
     return {"w+": wp, "w-": wm, "gamma+": gp, "gamma-": gm, "P": P}
 
 
@@ -130,10 +144,12 @@ class Solver:
     ``ell`` and ``sigma`` are physical lengths; ``precision`` is "fp64" or
     "fp32" (float32 sweep arithmetic, float64 state). The state lives in a
     float64 torch tensor of shape ``(nv, *grid.shape)`` owned by this object.
+    ``scheme`` is one of ``SCHEMES``: the paper's GP-WENO (default) or one of
+    its polynomial-WENO comparison schemes.
     """
 
     def __init__(self, grid, R, ell, sigma, gamma=1.4, precision="fp64", cfl=0.4, fixed_dt=0.0,
-                 positivity_fallback=False, U0=None, device=None, stream=None):
+                 positivity_fallback=False, U0=None, device=None, stream=None, scheme="gp-weno"):
         import torch
 
         if not torch.cuda.is_available():
@@ -148,7 +164,8 @@ class Solver:
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
             g = make_grid(grid)
-            _check(lib().gpweno_init(ctypes.byref(g), R, ell, sigma, gamma, ctypes.byref(self._ctx)))
+            _check(lib().gpweno_init_scheme(ctypes.byref(g), _scheme_id(scheme), R, ell, sigma, gamma,
+                                            ctypes.byref(self._ctx)))
             count = lib().gpweno_state_count(self._ctx)
             assert count == int(np.prod(self.shape))
             self.state = torch.empty(self.shape, dtype=torch.float64, device=self.device)

@@ -8,6 +8,13 @@
 //   (d) eigensystem of K_m built with sigma (Sec. 3.4); rows P_i = v_i/sqrt(lambda_i)
 //       (Eq. (beta-eigen)).
 //
+// The same tables for the paper's comparison schemes (Sec. 6.2, Table
+// (weno-vortex)): polynomial WENO interpolation (Lagrange weights on the
+// sub-stencils and their linear weights) with either Jiang-Shu smoothness
+// indicators (WENO-JS) or the GP ones (WENO-GP). Every scheme stores its
+// smoothness indicator as beta_m = sum_i (P[m][i] . f_m)^2, so the sweep kernel
+// is the same for all of them.
+//
 // K is badly conditioned at the usual ell = 12 dx (about 1e5, 6e9, 8e13 for
 // R = 1, 2, 3, and far worse for larger ell/dx), so a float64 solve loses up to
 // four digits of w for R = 3. Everything here runs in IEEE binary128 (113-bit
@@ -167,26 +174,127 @@ bool weights_for_point(int R, q128 ell, q128 xstar, q128 w[4][4], q128 gam[4]) {
     return true;
 }
 
+// Lagrange interpolation weights of the nodes x[0..n-1] at the point xs.
+void lagrange_weights(int n, const q128 *x, q128 xs, q128 *w) {
+    for (int j = 0; j < n; ++j) {
+        q128 v = 1;
+        for (int k = 0; k < n; ++k)
+            if (k != j) v *= (xs - x[k]) / (x[j] - x[k]);
+        w[j] = v;
+    }
+}
+
+// Polynomial WENO interpolation weights and linear weights for one prediction
+// point: the Lagrange limit of weights_for_point.
+bool poly_weights_for_point(int R, q128 xstar, q128 w[4][4], q128 gam[4]) {
+    const int n = 2 * R + 1;
+    q128 nodes[NMAX], wstar[NMAX];
+    for (int j = 0; j < n; ++j) nodes[j] = (q128)(j - R);
+    lagrange_weights(n, nodes, xstar, wstar);
+    for (int m = 0; m <= R; ++m) lagrange_weights(R + 1, nodes + m, xstar, w[m]);
+    q128 M[NMAX][NMAX] = {};
+    for (int m = 0; m <= R; ++m)
+        for (int j = 0; j <= R; ++j) M[m + j][m] = w[m][j];
+    q128 rhs[NMAX], g[NMAX];
+    for (int i = 0; i < n; ++i) rhs[i] = wstar[i];
+    if (!householder_lsq(n, R + 1, M, rhs, g)) return false;
+    for (int m = 0; m <= R; ++m) gam[m] = g[m];
+    return true;
+}
+
+// Jiang-Shu smoothness indicator of sub-stencil m (nodes m-R..m) as a quadratic
+// form beta = f^T B f: B_ij = sum_{l=1..R} int_{-1/2}^{1/2} L_i^(l)(x) L_j^(l)(x) dx
+// with L_j the Lagrange basis of the sub-stencil, unit spacing. The integrands
+// have degree <= 2R-2 <= 4, so 3-point Gauss-Legendre quadrature is exact.
+void js_form(int R, int m, q128 B[4][4]) {
+    const int np = R + 1;
+    q128 coef[4][4] = {};  // coef[j][k]: x^k coefficient of L_j
+    for (int j = 0; j < np; ++j) {
+        q128 c[4] = {1, 0, 0, 0};
+        int deg = 0;
+        const q128 xj = (q128)(m - R + j);
+        for (int k = 0; k < np; ++k) {
+            if (k == j) continue;
+            const q128 xk = (q128)(m - R + k);
+            const q128 s = 1 / (xj - xk);
+            q128 nc[4] = {0, 0, 0, 0};  // c * (x - xk) * s
+            for (int a = 0; a <= deg; ++a) {
+                nc[a + 1] += c[a] * s;
+                nc[a] -= c[a] * xk * s;
+            }
+            ++deg;
+            for (int a = 0; a < 4; ++a) c[a] = nc[a];
+        }
+        for (int a = 0; a < 4; ++a) coef[j][a] = c[a];
+    }
+    const q128 g = sqrtq((q128)3 / 5) / 2;
+    const q128 qx[3] = {-g, 0, g};
+    const q128 qw[3] = {(q128)5 / 18, (q128)8 / 18, (q128)5 / 18};
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) B[i][j] = 0;
+    for (int l = 1; l <= R; ++l) {
+        for (int q = 0; q < 3; ++q) {
+            q128 d[4];
+            for (int j = 0; j < np; ++j) {  // l-th derivative of L_j at qx[q]
+                q128 v = 0;
+                for (int k = l; k < np; ++k) {
+                    q128 fall = 1;
+                    for (int t = 0; t < l; ++t) fall *= (q128)(k - t);
+                    v += coef[j][k] * fall * powq(qx[q], k - l);
+                }
+                d[j] = v;
+            }
+            for (int i = 0; i < np; ++i)
+                for (int j = 0; j < np; ++j) B[i][j] += qw[q] * d[i] * d[j];
+        }
+    }
+}
+
 }  // namespace
 
-int gpw_build_tables(int R, double ell_over_dx, double sigma_over_dx, GpTablesF64 *out) {
+int gpw_build_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx, GpTablesF64 *out) {
     if (R < 1 || R > 3 || !(ell_over_dx > 0) || !(sigma_over_dx > 0) || !out) return -1;
+    if (scheme != GPW_SCHEME_GP_WENO && scheme != GPW_SCHEME_WENO_JS && scheme != GPW_SCHEME_WENO_GP) return -1;
+    if (scheme == GPW_SCHEME_WENO_JS && R > 2) return -1;
     std::memset(out, 0, sizeof(*out));
-    q128 ell = (q128)ell_over_dx;
-    q128 sig = (q128)sigma_over_dx;
     q128 wp[4][4] = {}, wm[4][4] = {}, gp[4] = {}, gm[4] = {};
-    if (!weights_for_point(R, ell, (q128)0.5, wp, gp)) return -2;
-    if (!weights_for_point(R, ell, (q128)-0.5, wm, gm)) return -2;
-    // eigensystem of K_m(sigma) on nodes 0..R (identical for every sub-stencil)
-    q128 A[4][4] = {}, V[4][4] = {};
-    for (int i = 0; i <= R; ++i)
-        for (int j = 0; j <= R; ++j) A[i][j] = se_kernel((q128)i, (q128)j, sig);
-    jacobi_eigen(R + 1, A, V);
-    for (int i = 0; i <= R; ++i) {
-        q128 lam = A[i][i];
-        if (!(lam > 0)) return -3;
-        q128 inv = 1 / sqrtq(lam);
-        for (int j = 0; j <= R; ++j) out->P[i][j] = (double)(V[j][i] * inv);
+    if (scheme == GPW_SCHEME_GP_WENO) {
+        const q128 ell = (q128)ell_over_dx;
+        if (!weights_for_point(R, ell, (q128)0.5, wp, gp)) return -2;
+        if (!weights_for_point(R, ell, (q128)-0.5, wm, gm)) return -2;
+    } else {
+        if (!poly_weights_for_point(R, (q128)0.5, wp, gp)) return -2;
+        if (!poly_weights_for_point(R, (q128)-0.5, wm, gm)) return -2;
+    }
+    if (scheme == GPW_SCHEME_WENO_JS) {
+        // factor each B_m = V diag(lambda) V^T; rows sqrt(lambda_i) v_i (B is
+        // positive semi-definite of rank R: round-off negatives become 0)
+        for (int m = 0; m <= R; ++m) {
+            q128 A[4][4], V[4][4] = {};
+            js_form(R, m, A);
+            jacobi_eigen(R + 1, A, V);
+            for (int i = 0; i <= R; ++i) {
+                const q128 lam = A[i][i];
+                const q128 s = lam > 0 ? sqrtq(lam) : (q128)0;
+                for (int j = 0; j <= R; ++j) out->P[m][i][j] = (double)(V[j][i] * s);
+            }
+        }
+    } else {
+        // eigensystem of K_m(sigma) on nodes 0..R (identical for every sub-stencil)
+        const q128 sig = (q128)sigma_over_dx;
+        q128 A[4][4] = {}, V[4][4] = {};
+        for (int i = 0; i <= R; ++i)
+            for (int j = 0; j <= R; ++j) A[i][j] = se_kernel((q128)i, (q128)j, sig);
+        jacobi_eigen(R + 1, A, V);
+        for (int i = 0; i <= R; ++i) {
+            const q128 lam = A[i][i];
+            if (!(lam > 0)) return -3;
+            const q128 inv = 1 / sqrtq(lam);
+            for (int j = 0; j <= R; ++j) {
+                const double v = (double)(V[j][i] * inv);
+                for (int m = 0; m <= R; ++m) out->P[m][i][j] = v;
+            }
+        }
     }
     for (int m = 0; m <= R; ++m) {
         out->gam_plus[m] = (double)gp[m];

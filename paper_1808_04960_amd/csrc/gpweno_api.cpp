@@ -195,7 +195,7 @@ void fill_tab(gpw::Tab<Real>& t, const GpTablesF64& s) {
         for (int j = 0; j < 4; ++j) {
             t.wp[m][j] = (Real)s.w_plus[m][j];
             t.wm[m][j] = (Real)s.w_minus[m][j];
-            t.P[m][j] = (Real)s.P[m][j];
+            for (int i = 0; i < 4; ++i) t.P[m][i][j] = (Real)s.P[m][i][j];
         }
     }
 }
@@ -204,13 +204,16 @@ void fill_tab(gpw::Tab<Real>& t, const GpTablesF64& s) {
 
 extern "C" {
 
-int gpweno_compute_tables(int R, double ell_over_dx, double sigma_over_dx, double* w_plus, double* w_minus,
-                          double* gam_plus, double* gam_minus, double* P) {
+int gpweno_compute_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx, double* w_plus,
+                          double* w_minus, double* gam_plus, double* gam_minus, double* P) {
+    if (scheme != GPWENO_GP_WENO && scheme != GPWENO_WENO_JS && scheme != GPWENO_WENO_GP)
+        return fail(nullptr, GPWENO_EINVAL, "unknown scheme %d", scheme);
     if (R < 1 || R > 3) return fail(nullptr, GPWENO_EINVAL, "R must be 1, 2 or 3 (got %d)", R);
+    if (scheme == GPWENO_WENO_JS && R > 2) return fail(nullptr, GPWENO_EINVAL, "WENO-JS needs R = 1 or 2");
     if (!(ell_over_dx > 0) || !std::isfinite(ell_over_dx) || !(sigma_over_dx > 0) || !std::isfinite(sigma_over_dx))
         return fail(nullptr, GPWENO_EINVAL, "length scales must be positive and finite");
     GpTablesF64 t;
-    int st = gpw_build_tables(R, ell_over_dx, sigma_over_dx, &t);
+    int st = gpw_build_tables(scheme, R, ell_over_dx, sigma_over_dx, &t);
     if (st) return fail(nullptr, GPWENO_EINVAL, "table construction failed (%d)", st);
     if (w_plus) std::memcpy(w_plus, t.w_plus, sizeof t.w_plus);
     if (w_minus) std::memcpy(w_minus, t.w_minus, sizeof t.w_minus);
@@ -221,10 +224,18 @@ int gpweno_compute_tables(int R, double ell_over_dx, double sigma_over_dx, doubl
 }
 
 int gpweno_init(const gpweno_grid* grid, int R, double ell, double sigma, double gamma, gpweno_ctx** out) {
+    return gpweno_init_scheme(grid, GPWENO_GP_WENO, R, ell, sigma, gamma, out);
+}
+
+int gpweno_init_scheme(const gpweno_grid* grid, int scheme, int R, double ell, double sigma, double gamma,
+                       gpweno_ctx** out) {
     if (!grid || !out) return fail(nullptr, GPWENO_EINVAL, "NULL grid or output pointer");
     *out = nullptr;
     if (grid->ndim < 1 || grid->ndim > 3) return fail(nullptr, GPWENO_EINVAL, "ndim must be 1, 2 or 3");
+    if (scheme != GPWENO_GP_WENO && scheme != GPWENO_WENO_JS && scheme != GPWENO_WENO_GP)
+        return fail(nullptr, GPWENO_EINVAL, "unknown scheme %d", scheme);
     if (R < 1 || R > 3) return fail(nullptr, GPWENO_EINVAL, "R must be 1, 2 or 3 (got %d)", R);
+    if (scheme == GPWENO_WENO_JS && R > 2) return fail(nullptr, GPWENO_EINVAL, "WENO-JS needs R = 1 or 2");
     if (!(gamma > 1.0) || !std::isfinite(gamma)) return fail(nullptr, GPWENO_EINVAL, "gamma must be > 1");
     if (!(ell > 0) || !std::isfinite(ell)) return fail(nullptr, GPWENO_EINVAL, "ell must be positive");
     gpweno_ctx* c = new (std::nothrow) gpweno_ctx();
@@ -257,7 +268,7 @@ int gpweno_init(const gpweno_grid* grid, int R, double ell, double sigma, double
             delete c;
             return fail(nullptr, GPWENO_EINVAL, "sigma must exceed dx on every axis (sigma <= dx is unstable)");
         }
-        int st = gpw_build_tables(R, ell / c->dx[d], sigma / c->dx[d], &c->tab64[d]);
+        int st = gpw_build_tables(scheme, R, ell / c->dx[d], sigma / c->dx[d], &c->tab64[d]);
         if (st) {
             delete c;
             return fail(nullptr, GPWENO_EINVAL, "table construction failed on axis %d (%d)", d, st);

@@ -56,7 +56,9 @@ struct Tab {
     Real wm[4][4];  // w_m at x_* = -1/2
     Real gp[4];     // gamma_m for x_* = +1/2
     Real gm[4];     // gamma_m for x_* = -1/2
-    Real P[4][4];   // rows v_i / sqrt(lambda_i) of K_m(sigma)
+    Real P[4][4][4];  // [m][i][j]: beta_m = sum_i (P[m][i] . f_m)^2 (GP: rows v_i / sqrt(lambda_i)
+                      // of K_m(sigma), the same for every m; WENO-JS: a factor of the
+                      // Jiang-Shu quadratic form of sub-stencil m)
 };
 
 template <typename Real>

@@ -141,7 +141,9 @@ __device__ __forceinline__ void cons_to_rot(const double (&u)[2 + NDIM], double 
 }
 
 // GP-WENO interpolation of one characteristic field f[0..2R] to x_{i+1/2} (qp)
-// and x_{i-1/2} (qm). beta_m = sum_i (P_i . f_m)^2 is shared by both points.
+// and x_{i-1/2} (qm). beta_m = sum_i (P_m,i . f_m)^2 is shared by both points.
+// The comparison schemes (polynomial WENO with Jiang-Shu or GP smoothness
+// indicators) run through the same code with their own tables.
 // Nonlinear weights gamma_m / (eps + beta_m)^2 are evaluated in the equivalent
 // form gamma_m * ((eps + beta_min)/(eps + beta_m))^2, which cannot overflow or
 // underflow to 0/0 in float32 (eps = 1e-36 squared is below float range).
@@ -153,9 +155,9 @@ __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Re
         Real b = Real(0);
 #pragma unroll
         for (int i = 0; i <= R; ++i) {
-            Real pr = T.P[i][0] * f[m];
+            Real pr = T.P[m][i][0] * f[m];
 #pragma unroll
-            for (int j = 1; j <= R; ++j) pr = fma(T.P[i][j], f[m + j], pr);
+            for (int j = 1; j <= R; ++j) pr = fma(T.P[m][i][j], f[m + j], pr);
             b = fma(pr, pr, b);
         }
         e[m] = Real(1e-36) + b;

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import paper_1808_04960_amd as gw
-from oracle.tables import gp_tables
+from oracle.tables import gp_tables, scheme_tables
 
 
 @pytest.fixture(scope="module")
@@ -34,10 +34,31 @@ def test_binary128_tables_match_oracle(R, ell, sigma):
         np.testing.assert_allclose(got[key], ref[key], rtol=tol, atol=tol * np.abs(ref[key]).max())
     for key in ("gamma+", "gamma-"):
         np.testing.assert_allclose(got[key], ref[key], rtol=tol, atol=0)
-    # P is defined up to the sign and order of the eigenvectors; P^T P = K_m(sigma)^{-1} is unique
-    PtP_got = got["P"][: R + 1, : R + 1].T @ got["P"][: R + 1, : R + 1]
+    # P is defined up to the sign and order of the eigenvectors; P^T P = K_m(sigma)^{-1} is
+    # unique, and the same for every sub-stencil m on a uniform grid
     PtP_ref = ref["P"][: R + 1, : R + 1].T @ ref["P"][: R + 1, : R + 1]
-    np.testing.assert_allclose(PtP_got, PtP_ref, rtol=1e-13, atol=1e-13 * np.abs(PtP_ref).max())
+    for m in range(R + 1):
+        Pm = got["P"][m, : R + 1, : R + 1]
+        np.testing.assert_allclose(Pm.T @ Pm, PtP_ref, rtol=1e-13, atol=1e-13 * np.abs(PtP_ref).max())
+    assert not got["P"][R + 1:].any()
+
+
+@pytest.mark.parametrize("scheme,R", [("weno-js", 1), ("weno-js", 2), ("weno-gp", 1), ("weno-gp", 2),
+                                      ("weno-gp", 3)])
+def test_binary128_polynomial_scheme_tables_match_oracle(scheme, R):
+    """Lagrange weights, linear weights and smoothness-indicator forms of the
+    comparison schemes against the oracle's exact rational tables."""
+    got = gw.compute_tables(R, 12.0, 3.0, scheme=scheme)
+    ref = scheme_tables(scheme, R, 12.0, 3.0)
+    for key in ("w+", "w-", "gamma+", "gamma-"):
+        np.testing.assert_allclose(got[key], ref[key], rtol=2.3e-16, atol=0)
+    for m in range(R + 1):
+        Pm = got["P"][m, : R + 1, : R + 1]
+        if ref["beta_form"] == "B":
+            want = ref["B"][m, : R + 1, : R + 1]
+        else:
+            want = ref["P"][: R + 1, : R + 1].T @ ref["P"][: R + 1, : R + 1]
+        np.testing.assert_allclose(Pm.T @ Pm, want, rtol=1e-14, atol=1e-14 * np.abs(want).max())
 
 
 def test_tables_reject_invalid_arguments():
@@ -45,6 +66,10 @@ def test_tables_reject_invalid_arguments():
         with pytest.raises(gw.GpwenoError) as e:
             gw.compute_tables(*args)
         assert e.value.code == gw.EINVAL
+    with pytest.raises(gw.GpwenoError) as e:
+        gw.compute_tables(3, 12.0, 3.0, scheme="weno-js")   # Jiang-Shu indicators: R = 1, 2 only
+    assert e.value.code == gw.EINVAL
+    assert gw.lib().gpweno_compute_tables(7, 2, 12.0, 3.0, None, None, None, None, None) == gw.EINVAL
 
 
 class _G:
@@ -67,6 +92,14 @@ def test_init_validates_before_touching_a_device(L, grid, R, ell, sigma, gamma):
     assert rc == gw.EINVAL
     assert not ctx.value
     assert len(L.gpweno_last_error(None)) > 0
+
+
+def test_init_scheme_validates(L):
+    g = gw.make_grid(_G(1, (64, 1, 1)))
+    ctx = ctypes.c_void_p()
+    assert L.gpweno_init_scheme(ctypes.byref(g), 1, 3, 0.1, 0.05, 1.4, ctypes.byref(ctx)) == gw.EINVAL
+    assert L.gpweno_init_scheme(ctypes.byref(g), 9, 2, 0.1, 0.05, 1.4, ctypes.byref(ctx)) == gw.EINVAL
+    assert not ctx.value
 
 
 def test_null_context_is_rejected(L):
