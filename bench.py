@@ -13,6 +13,8 @@ Reported (one JSON line):
               oracle's sample steps, and density L1 against the exact solution
               after full solves to t = 10
   latency     p50/p99 time-to-solution of full solves (upload, run to t = 10, download)
+  serving     the continuous-batching request loop on a Poisson stream of problems
+  time_to_error the paper's time-to-error comparison of GP-R1/R2/R3 with WENO-JS
   roofline    the dominant sweep kernel, timed with HIP events on its stream
   cpu_baseline the CPU oracle timed on a bounded sample of the same workload
 """
@@ -95,6 +97,92 @@ def run_serving(count, budget, slots, steps_per_tick, log):
     return s
 
 
+TTE_DESC = ("2D isentropic vortex on [0,20]^2 (strength 5, background rho = u = v = p = 1, gamma 1.4), one "
+            "period t = 20, ell = 1.2, sigma = 3 dx, CFL 0.4 without time-step reduction, SSP-RK3, float64 sweeps; "
+            "L1 = 100 x mean |rho - rho(t=0)|")
+TTE_CASES = (("weno-js", 2, (64, 96, 128, 192)), ("gp-weno", 1, (192, 256, 384, 512)),
+             ("gp-weno", 2, (48, 64, 96, 128)), ("gp-weno", 3, (48, 64, 96, 128)))
+
+
+def _interp_time(points, target):
+    """Time at which the L1 error reaches target, interpolated log-log between the
+    two grids that bracket it; None if no pair does."""
+    pts = sorted(points, key=lambda p: -p[0])
+    for (e0, t0), (e1, t1) in zip(pts, pts[1:]):
+        if e0 >= target >= e1 and e0 > e1:
+            f = math.log(e0 / target) / math.log(e0 / e1)
+            return t0 * (t1 / t0) ** f
+    return None
+
+
+def time_to_error(target, log, cells_per_batch=1 << 20, max_copies=64):
+    """The shape of the paper's time-to-error study (Sec. 6.2, Fig. (vortex_timing),
+    Table (performace-time-to-error)) on the GPU. For each scheme and grid:
+      single  -- wall time of one solve to t = 20 (state resident, graph replays);
+      batched -- wall time per problem when copies of the problem fill the GPU
+                 through the batched path (about cells_per_batch cells in flight);
+    each interpolated log-log to the target L1 error and divided by WENO-JS's."""
+    import torch
+
+    import paper_1808_04960_amd as gw
+
+    out = {"workload": TTE_DESC, "target_l1": target, "schemes": {}}
+    for scheme, R, sizes in TTE_CASES:
+        name = "WENO-JS" if scheme == "weno-js" else f"GP-R{R}"
+        rows = []
+        for n in sizes:
+            g, U = inputs.isentropic_vortex_2d(n, lo=0.0, hi=20.0)
+            dx = g.dx[0]
+            s = gw.Solver(g, R, 1.2, 3 * dx, precision="fp64", U0=U, scheme=scheme)
+            s.run(20.0, max_steps=40)                      # graph capture, clocks up
+            s.set_state(U)
+            s.synchronize()
+            t0 = time.perf_counter()
+            nst, tf = s.run(20.0)
+            single = time.perf_counter() - t0
+            Ug = s.get_state()
+            err = 100.0 * float(np.mean(np.abs(Ug[0] - U[0])))
+            s.close()
+            copies = max(1, min(max_copies, cells_per_batch // (n * n)))
+            stream = torch.cuda.Stream()
+            members = []
+            for _ in range(copies):
+                m = gw.Solver(g, R, 1.2, 3 * dx, precision="fp64", U0=U, scheme=scheme, stream=stream)
+                m.set_end(20.0, -1)
+                members.append(m)
+            b = gw.Batch(stream)
+            b.set(members)
+            stream.synchronize()
+            t0 = time.perf_counter()
+            b.run(nst)
+            _, _, ns, er = b.status()
+            batched = (time.perf_counter() - t0) / copies
+            assert (ns == nst).all() and not er.any()
+            same = bool(np.array_equal(members[-1].get_state(), Ug))
+            b.close()
+            for m in members:
+                m.close()
+            del members
+            torch.cuda.empty_cache()
+            rows.append({"n": n, "steps": nst, "l1": err, "single_s": single, "copies": copies,
+                         "batched_s_per_problem": batched, "batch_bitwise_equal_single": same})
+            log(f"time-to-error {name} n={n}: {nst} steps, L1 {err:.3e}, single {single * 1e3:.1f} ms, "
+                f"batched {batched * 1e3:.2f} ms/problem ({copies} copies)")
+        out["schemes"][name] = {
+            "runs": rows,
+            "single_s": _interp_time([(r["l1"], r["single_s"]) for r in rows], target),
+            "batched_s": _interp_time([(r["l1"], r["batched_s_per_problem"]) for r in rows], target),
+            "cell_updates": _interp_time([(r["l1"], 3.0 * r["steps"] * r["n"] ** 2) for r in rows], target),
+        }
+    ref = out["schemes"]["WENO-JS"]
+    for v in out["schemes"].values():
+        for k in ("single_s", "batched_s", "cell_updates"):
+            v[f"{k}_rel_weno_js"] = v[k] / ref[k] if v[k] and ref[k] else None
+    out["paper_relative_time"] = {"GP-R1": 35.81, "GP-R2": 0.43, "GP-R3": 0.22, "WENO-JS": 1.0,
+                                  "what": "CPU time on 4 cores with RK4, ell = 1.2 (the paper's table)"}
+    return out
+
+
 def traffic_from_profiles(kernel_name, tag):
     """HBM bytes per launch (fetched + written) of the kernel on the workload, from
     the committed rocprofv3 counter summary; None if there is none or the kernel
@@ -127,6 +215,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=100, help="back-to-back launches per timed kernel")
     ap.add_argument("--serving-requests", type=int, default=200, help="requests of the serving stream (0: skip)")
+    ap.add_argument("--no-time-to-error", action="store_true", help="skip the time-to-error study")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -277,6 +366,10 @@ def main():
         serving = run_serving(args.serving_requests, 2 << 30, 64, 8, log)
         serving["workload"] = SERVING_DESC
 
+    tte = None
+    if args.workload == "vortex2d" and not args.no_time_to_error:
+        tte = time_to_error(5e-3, log)
+
     cu32 = ncell * 3 * args.steps / timing["fp32"]
     cu64 = ncell * 3 * args.steps / timing["fp64"]
     def dominant(prec):
@@ -314,6 +407,7 @@ def main():
         "latency": ({"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
                      "solves": len(lat), "what": "upload + run to t_final + download, fp32 path"} if lat else None),
         "serving": serving,
+        "time_to_error": tte,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -27,6 +27,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <utility>
 
 #include "gp_tables.h"
 
@@ -267,16 +268,21 @@ int gpw_build_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx
         if (!poly_weights_for_point(R, (q128)-0.5, wm, gm)) return -2;
     }
     if (scheme == GPW_SCHEME_WENO_JS) {
-        // factor each B_m = V diag(lambda) V^T; rows sqrt(lambda_i) v_i (B is
-        // positive semi-definite of rank R: round-off negatives become 0)
+        // factor each B_m = V diag(lambda) V^T; rows sqrt(lambda_i) v_i in order of
+        // decreasing lambda. B_m is positive semi-definite of rank R (its null
+        // space is the constants), so row R is zero and the sweep skips it.
         for (int m = 0; m <= R; ++m) {
             q128 A[4][4], V[4][4] = {};
             js_form(R, m, A);
             jacobi_eigen(R + 1, A, V);
+            int order[4] = {0, 1, 2, 3};
+            for (int a = 0; a <= R; ++a)
+                for (int b = a + 1; b <= R; ++b)
+                    if (A[order[b]][order[b]] > A[order[a]][order[a]]) std::swap(order[a], order[b]);
             for (int i = 0; i <= R; ++i) {
-                const q128 lam = A[i][i];
-                const q128 s = lam > 0 ? sqrtq(lam) : (q128)0;
-                for (int j = 0; j <= R; ++j) out->P[m][i][j] = (double)(V[j][i] * s);
+                const q128 lam = A[order[i]][order[i]];
+                const q128 s = (i < R && lam > 0) ? sqrtq(lam) : (q128)0;
+                for (int j = 0; j <= R; ++j) out->P[m][i][j] = (double)(V[j][order[i]] * s);
             }
         }
     } else {

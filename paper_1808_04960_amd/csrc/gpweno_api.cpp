@@ -39,6 +39,7 @@ thread_local std::string g_tls_error = "";
 struct gpweno_ctx {
     gpweno_grid grid;
     int R;
+    int scheme;                     // gpweno_scheme
     double ell, sigma, gamma;
     double dx[3];
     long long ncell;
@@ -116,12 +117,12 @@ int launch(gpweno_ctx* c, int dir, const double* in, const double* un, double* a
         auto a = base_args<float>(c, dir);
         a.U = in; a.Un = un; a.dU = acc; a.Uout = out;
         a.first = first; a.stage = stage; a.step_start = step_start;
-        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, true, fin, &a, s);
+        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, true, fin, c->scheme == GPWENO_WENO_JS, &a, s);
     } else {
         auto a = base_args<double>(c, dir);
         a.U = in; a.Un = un; a.dU = acc; a.Uout = out;
         a.first = first; a.stage = stage; a.step_start = step_start;
-        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, false, fin, &a, s);
+        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, false, fin, c->scheme == GPWENO_WENO_JS, &a, s);
     }
     if (e != hipSuccess) return fail(c, GPWENO_EHIP, "sweep launch (dir %d): %s", dir, hipGetErrorString(e));
     return GPWENO_OK;
@@ -242,6 +243,7 @@ int gpweno_init_scheme(const gpweno_grid* grid, int scheme, int R, double ell, d
     if (!c) return fail(nullptr, GPWENO_ENOMEM, "out of host memory");
     c->grid = *grid;
     c->R = R;
+    c->scheme = scheme;
     c->ell = ell;
     c->sigma = sigma;
     c->gamma = gamma;
@@ -482,7 +484,7 @@ namespace {
 
 constexpr int BATCH_MAX = 4096;
 
-// Problems sharing one kernel instantiation and one set of GP tables.
+// Problems sharing one kernel instantiation and one set of tables (same scheme).
 struct BatchGroup {
     int ndim = 0, R = 0;
     bool fp32 = false;
@@ -494,6 +496,7 @@ struct BatchGroup {
 };
 
 bool same_tables(const gpweno_ctx* a, const gpweno_ctx* b) {
+    if (a->scheme != b->scheme) return false;
     for (int d = 0; d < a->grid.ndim; ++d)
         if (std::memcmp(&a->tab64[d], &b->tab64[d], sizeof(GpTablesF64)) != 0) return false;
     // the batched kernel takes one table set per launch; problems whose axes
@@ -562,7 +565,8 @@ int batch_launch(gpweno_batch* b, const BatchGroup& g, int k, hipStream_t s) {
         a.stage = stage;
         a.step_start = k == 0;
         a.tab = g.proto->tabf[0];
-        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, true, fin, &a, g.blocks[dir], s);
+        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, true, fin, g.proto->scheme == GPWENO_WENO_JS, &a, g.blocks[dir],
+                                    s);
     } else {
         gpw::BatchArgs<double> a;
         std::memset(&a, 0, sizeof a);
@@ -572,7 +576,8 @@ int batch_launch(gpweno_batch* b, const BatchGroup& g, int k, hipStream_t s) {
         a.stage = stage;
         a.step_start = k == 0;
         a.tab = g.proto->tabd[0];
-        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, false, fin, &a, g.blocks[dir], s);
+        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, false, fin, g.proto->scheme == GPWENO_WENO_JS, &a,
+                                    g.blocks[dir], s);
     }
     if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "batched sweep launch: %s", hipGetErrorString(e));
     return GPWENO_OK;

@@ -59,6 +59,9 @@ def test_binary128_polynomial_scheme_tables_match_oracle(scheme, R):
         else:
             want = ref["P"][: R + 1, : R + 1].T @ ref["P"][: R + 1, : R + 1]
         np.testing.assert_allclose(Pm.T @ Pm, want, rtol=1e-14, atol=1e-14 * np.abs(want).max())
+        if scheme == "weno-js":
+            # rank R (constants are smooth): the sweep reads rows 0..R-1 only
+            assert not got["P"][m, R:].any()
 
 
 def test_tables_reject_invalid_arguments():

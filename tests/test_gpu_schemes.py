@@ -1,0 +1,172 @@
+"""The comparison schemes on the GPU, and the paper's vortex tables at every
+resolution the paper prints.
+
+* Right-hand sides of WENO-JS (R = 1, 2) and WENO-GP (R = 1..3) agree with the
+  oracle within the rounding bound of the flux difference (as for GP-WENO).
+* Whole runs on the paper's vortex set-up agree with the oracle (WENO-GP: 1e-12
+  fp64, 1e-5 fp32; WENO-JS: as closely as the oracle agrees with itself under a
+  rounding-size change of its input, see the test).
+* The paper's Table (vortex) (GP-R1, GP-R2, GP-R3) and the WENO-GP column of its
+  Table (weno-vortex) are reproduced by the GPU within 5 % at every printed
+  resolution, including those too large for the oracle (dx = 1/20, 1/40).
+* A batch that mixes schemes gives each problem bitwise its single-problem result.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from conftest import load_golden
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1808_04960_amd as gw  # noqa: E402
+from test_gpu_parity import EPS, GRIDS, flux_bound, rel_l1  # noqa: E402
+
+
+def announce(msg):
+    print(f"[gpu-schemes] {msg}", file=sys.stderr, flush=True)
+
+
+SCHEME_R = [("weno-js", 1), ("weno-js", 2), ("weno-gp", 1), ("weno-gp", 2), ("weno-gp", 3)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+@pytest.mark.parametrize("scheme,R", SCHEME_R)
+def test_scheme_rhs_matches_oracle(scheme, R, ndim, prec):
+    """Bound: the rounding bound of the flux difference (as for GP-WENO) plus the
+    oracle's own response to a rounding-size perturbation of its input. With
+    eps = 1e-36 the Jiang-Shu weights are ill-conditioned where a first difference
+    of a characteristic field vanishes (extrema): a relative change of size u in
+    the data moves the weights there by O(u / |first difference|). The GP
+    indicator of zero-mean data has no such points (f^T K^-1 f > 0 for f != 0)."""
+    g = GRIDS[ndim]()
+    announce(f"rhs {scheme} R={R} ndim={ndim} {prec} n={g.n}")
+    U = inputs.random_smooth(g, seed=100 + 10 * ndim + R)
+    dx = g.dx[0]
+    o = oracle.OracleSolver(g, R, 12 * dx, 3 * dx, scheme=scheme)
+    ref = o.rhs(U)
+    rng = np.random.default_rng(7)
+    pert = max(float(np.abs(o.rhs(U * (1.0 + EPS[prec] * rng.uniform(-1, 1, U.shape))) - ref).sum())
+               for _ in range(3))
+    s = gw.Solver(g, R, 12 * dx, 3 * dx, precision=prec, U0=U, scheme=scheme)
+    got = s.rhs(U)
+    err = float(np.abs(got - ref).sum())
+    bound = 16 * EPS[prec] * flux_bound(g, U)
+    announce(f"  abs L1 {err:.3e}  rounding bound {bound:.3e}  oracle perturbed {pert:.3e}  "
+             f"rel L1 {rel_l1(got, ref):.3e}")
+    assert err < bound + 4 * pert
+
+
+def _vortex_dt(g, U, R, dx):
+    """The reduced time step of the accuracy tests: CFL 0.4 at dx = 0.4, scaled by
+    (dx/0.4)^((2R+1)/3 - 1), rounded so that whole steps reach t = 20."""
+    rho, vel, p = inputs.cons_to_prim(g, U, 1.4)
+    c = np.sqrt(1.4 * p / rho)
+    smax = float(sum((np.abs(vel[d]) + c) / g.dx[d] for d in range(2)).max())
+    dt0 = 0.4 / smax * (dx / 0.4) ** ((2 * R + 1) / 3 - 1)
+    nst = math.ceil(20.0 / dt0)
+    return 20.0 / nst, nst
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("scheme", ["weno-js", "weno-gp"])
+def test_scheme_vortex_period_matches_oracle(scheme, prec, tol):
+    """One period of the vortex on [0,20]^2 at dx = 2/5 (the paper's coarsest entry).
+
+    WENO-GP: relative L1 against the oracle within the usual 1e-12 / 1e-5.
+    WENO-JS: with eps = 1e-36 its weights in the nearly flat far field of the
+    vortex are set by rounding-level differences, and one period amplifies a
+    one-ulp change of the initial data to ~3e-7 relative L1 in the oracle itself
+    (GP indicators: ~2e-15). No implementation can agree with the oracle more
+    closely than the oracle agrees with itself. The bound is a multiple of the
+    oracle's spread under a rounding-size perturbation of its input at the
+    precision under test: 4x for float64, 10x for float32, whose rounding enters
+    every stage and not only the initial data (measured: 1.3x and 5x). The
+    density error against the exact solution must agree to 2e-5 (float64) and
+    5e-4 (float32) relative (measured: 7e-6 and 1.2e-4)."""
+    announce(f"vortex period {scheme} {prec}")
+    g, U = inputs.isentropic_vortex_2d(50, lo=0.0, hi=20.0)
+    dx = g.dx[0]
+    dt, nst = _vortex_dt(g, U, 2, dx)
+    o = oracle.OracleSolver(g, 2, 1.0, 3 * dx, scheme=scheme)
+    Uo = U.copy()
+    o.run_fixed(Uo, dt, nst)
+    s = gw.Solver(g, 2, 1.0, 3 * dx, precision=prec, fixed_dt=dt, U0=U, scheme=scheme)
+    n, _ = s.run(20.0, max_steps=nst)
+    assert n == nst
+    Ug = s.get_state()
+    err = rel_l1(Ug, Uo)
+    if scheme == "weno-gp":
+        announce(f"  rel L1 vs oracle {err:.3e}")
+        assert err < tol
+        return
+    rng = np.random.default_rng(3)
+    spread = 0.0
+    for _ in range(2):
+        Up = U * (1.0 + EPS[prec] * rng.uniform(-1, 1, U.shape))
+        o.run_fixed(Up, dt, nst)
+        spread = max(spread, rel_l1(Up, Uo))
+    l1_g = float(np.mean(np.abs(Ug[0] - U[0])))
+    l1_o = float(np.mean(np.abs(Uo[0] - U[0])))
+    announce(f"  rel L1 vs oracle {err:.3e}, oracle spread {spread:.3e}, density L1 {l1_g:.6e} vs {l1_o:.6e}")
+    assert err < (4 if prec == "fp64" else 10) * spread
+    assert abs(l1_g / l1_o - 1.0) < (2e-5 if prec == "fp64" else 5e-4)
+
+
+TABLE2 = {round(r[0], 4): r[1:] for r in load_golden("table2_vortex_2d.txt")}
+TABLE3 = {round(r[0], 4): r[1:] for r in load_golden("table3_weno_vortex_2d.txt")}
+CASES = ([("gp-weno", R, n) for R in (1, 2) for n in (50, 100, 200, 400, 800)] +
+         [("gp-weno", 3, n) for n in (50, 100, 200, 400)] +
+         [("weno-gp", 2, n) for n in (50, 100, 200, 400, 800)])
+
+
+@pytest.mark.parametrize("scheme,R,n", CASES)
+def test_paper_vortex_tables_on_gpu(scheme, R, n):
+    """float64 path, the paper's set-up: ell = 1, sigma = 3 dx, one period, time step
+    reduced so the temporal error stays below the spatial one (L1 read as 100 x the
+    mean absolute density error, the reading that matches the oracle's runs)."""
+    g, U = inputs.isentropic_vortex_2d(n, lo=0.0, hi=20.0)
+    dx = g.dx[0]
+    dt, nst = _vortex_dt(g, U, R, dx)
+    announce(f"table {scheme} R={R} n={n} steps={nst}")
+    s = gw.Solver(g, R, 1.0, 3 * dx, precision="fp64", fixed_dt=dt, U0=U, scheme=scheme)
+    got_n, _ = s.run(20.0, max_steps=nst)
+    assert got_n == nst
+    err = 100.0 * float(np.mean(np.abs(s.get_state()[0] - U[0])))
+    paper = TABLE2[round(dx, 4)][R - 1] if scheme == "gp-weno" else TABLE3[round(dx, 4)][1]
+    announce(f"  L1 {err:.4e}  paper {paper:.3e}  ratio {err / paper:.4f}")
+    s.close()
+    assert abs(err / paper - 1.0) < 0.05
+
+
+def test_batch_mixing_schemes_is_bitwise_the_single_problem_path():
+    announce("batch with mixed schemes")
+    stream = torch.cuda.Stream()
+    probs = [("gp-weno", 2, 64), ("weno-js", 2, 64), ("weno-gp", 3, 80), ("weno-js", 1, 72), ("gp-weno", 2, 96)]
+    solvers, states = [], []
+    for scheme, R, n in probs:
+        g, U = inputs.isentropic_vortex_2d(n)
+        dx = g.dx[0]
+        s = gw.Solver(g, R, 12 * dx, 3 * dx, precision="fp32", U0=U, stream=stream, scheme=scheme)
+        s.set_end(1e30, 25)
+        solvers.append(s)
+        states.append((g, U, dx, scheme, R))
+    b = gw.Batch(stream)
+    b.set(solvers)
+    b.run(27)
+    _, _, ns, err = b.status()
+    assert list(ns) == [25] * len(probs) and not err.any()
+    for s, (g, U, dx, scheme, R) in zip(solvers, states):
+        ref = gw.Solver(g, R, 12 * dx, 3 * dx, precision="fp32", U0=U, scheme=scheme)
+        ref.run(1e30, max_steps=25)
+        assert np.array_equal(s.get_state(), ref.get_state()), (scheme, R)
+    b.close()
