@@ -18,14 +18,20 @@ import math
 import numpy as np
 
 
+PERIODIC, OUTFLOW, REFLECT = 0, 1, 2   # boundary kinds, per axis and side
+
+
 @dataclasses.dataclass(frozen=True)
 class Grid:
-    """Uniform periodic grid. ``n`` and ``lo``/``hi`` are given per axis (x, y, z)."""
+    """Uniform grid. ``n`` and ``lo``/``hi`` are given per axis (x, y, z).
+    ``bc[d] = (low side, high side)`` boundary kinds; periodic by default
+    (a periodic axis is periodic on both sides)."""
 
     ndim: int
     n: tuple
     lo: tuple
     hi: tuple
+    bc: tuple = ((PERIODIC, PERIODIC), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC))
 
     @property
     def nv(self) -> int:
@@ -54,16 +60,26 @@ class Grid:
         return tuple(reversed(grids))
 
 
-def grid1d(n, lo=0.0, hi=1.0) -> Grid:
-    return Grid(1, (n, 1, 1), (lo, 0.0, 0.0), (hi, 1.0, 1.0))
+def _bc(bc, ndim):
+    """None: periodic; an int: that kind on every side; else per-axis pairs."""
+    if bc is None:
+        bc = PERIODIC
+    if isinstance(bc, int):
+        bc = [(bc, bc)] * ndim
+    bc = [tuple(b) for b in bc] + [(PERIODIC, PERIODIC)] * (3 - len(bc))
+    return tuple(bc[:3])
 
 
-def grid2d(nx, ny, lo=(0.0, 0.0), hi=(1.0, 1.0)) -> Grid:
-    return Grid(2, (nx, ny, 1), (lo[0], lo[1], 0.0), (hi[0], hi[1], 1.0))
+def grid1d(n, lo=0.0, hi=1.0, bc=None) -> Grid:
+    return Grid(1, (n, 1, 1), (lo, 0.0, 0.0), (hi, 1.0, 1.0), _bc(bc, 1))
 
 
-def grid3d(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)) -> Grid:
-    return Grid(3, (nx, ny, nz), tuple(lo), tuple(hi))
+def grid2d(nx, ny, lo=(0.0, 0.0), hi=(1.0, 1.0), bc=None) -> Grid:
+    return Grid(2, (nx, ny, 1), (lo[0], lo[1], 0.0), (hi[0], hi[1], 1.0), _bc(bc, 2))
+
+
+def grid3d(nx, ny, nz, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), bc=None) -> Grid:
+    return Grid(3, (nx, ny, nz), tuple(lo), tuple(hi), _bc(bc, 3))
 
 
 def prim_to_cons(grid: Grid, rho, vel, p, gamma):
@@ -183,6 +199,42 @@ def four_quadrant_2d(n, rng, gamma=1.4):
     p = pq[q]
     zero = np.zeros_like(x)
     return g, prim_to_cons(g, rho, [zero, zero], p, gamma)
+
+
+# The paper's 3D explosion (Sec. 7, Eq. (3d-exp)): inside a sphere of radius 0.5
+# V = (rho, u, v, w, p) = (1, 0, 0, 0, 1), outside (0.125, 0, 0, 0, 0.1), on
+# [-1,1]^3 with outflow boundaries, gamma = 1.4, to t = 0.25.
+EXPLOSION_IN = (1.0, 1.0)      # (rho, p)
+EXPLOSION_OUT = (0.125, 0.1)
+
+
+def explosion(ndim, n, gamma=1.4, radius=0.5):
+    """The explosion data on [-1,1]^ndim with outflow boundaries: the paper's 3D
+    problem for ndim = 3, its plane and line sections for ndim = 2, 1 (ndim = 1
+    is a two-sided shock tube with the diaphragms at x = +-0.5)."""
+    make = {1: lambda: grid1d(n, -1.0, 1.0, OUTFLOW), 2: lambda: grid2d(n, n, (-1.0, -1.0), (1.0, 1.0), OUTFLOW),
+            3: lambda: grid3d(n, n, n, (-1.0,) * 3, (1.0,) * 3, OUTFLOW)}
+    g = make[ndim]()
+    X = g.mesh()
+    r2 = sum(x * x for x in X)
+    inside = r2 <= radius * radius
+    rho = np.where(inside, EXPLOSION_IN[0], EXPLOSION_OUT[0])
+    p = np.where(inside, EXPLOSION_IN[1], EXPLOSION_OUT[1])
+    vel = [np.zeros(g.shape) for _ in range(ndim)]
+    return g, prim_to_cons(g, rho, vel, p, gamma)
+
+
+def shock_tube_1d(n, x0=0.5, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1), lo=0.0, hi=1.0, gamma=1.4,
+                  bc=OUTFLOW):
+    """A 1D Riemann problem: (rho, u, p) = left for x < x0, right beyond. The
+    defaults are the two states of the paper's explosion data (Eq. (3d-exp))."""
+    g = grid1d(n, lo, hi, bc)
+    x = g.centres(0)
+    L = x < x0
+    rho = np.where(L, left[0], right[0])
+    u = np.where(L, left[1], right[1])
+    p = np.where(L, left[2], right[2])
+    return g, prim_to_cons(g, rho, [u], p, gamma)
 
 
 def uniform_state(grid: Grid, rho=1.3, vel=(0.7, -0.4, 0.25), p=0.9, gamma=1.4):

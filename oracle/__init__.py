@@ -50,6 +50,7 @@ class Cfg(ctypes.Structure):
         ("P", ctypes.c_double * 48),
         ("beta_form", ctypes.c_int),
         ("B", ctypes.c_double * 192),
+        ("bc", ctypes.c_int * 6),
     ]
 
 
@@ -176,6 +177,15 @@ class OracleSolver:
         c.R = R
         c.gamma = gamma
         c.positivity_fallback = 1 if positivity_fallback else 0
+        bc = getattr(grid, "bc", ((0, 0),) * 3)
+        for d in range(3):
+            lo_bc, hi_bc = bc[d] if d < grid.ndim else (0, 0)
+            if (lo_bc == 0) != (hi_bc == 0):
+                raise ValueError("a periodic axis must be periodic on both sides")
+            if 2 in (lo_bc, hi_bc) and grid.n[d] < R + 3:
+                raise ValueError("a reflecting side needs at least R + 3 cells on its axis")
+            c.bc[2 * d] = lo_bc
+            c.bc[2 * d + 1] = hi_bc
         self.tables = []
         for d in range(grid.ndim):
             t = scheme_tables(scheme, R, ell / grid.dx[d], sigma / grid.dx[d])

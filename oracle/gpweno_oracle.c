@@ -1,6 +1,7 @@
 /*
  * CPU oracle for the GP-WENO finite-difference (FD-Prim) scheme for the
- * compressible Euler equations on uniform periodic grids.
+ * compressible Euler equations on uniform grids (periodic, outflow or
+ * reflecting boundaries per axis side).
  *
  * TEST INFRASTRUCTURE ONLY. This file is the plain, slow reference that the
  * GPU library is checked against. Only the test suite, the smoke check and the
@@ -62,7 +63,11 @@ typedef struct {
     int beta_form;          /* 0: beta_m = sum_i (P_i . f_m)^2 (GP, Eq. (beta-eigen));
                                1: beta_m = f_m^T B_m f_m (polynomial, Jiang-Shu type) */
     double B[3][4][4][4];   /* [d][m][i][j], used when beta_form = 1 */
+    int bc[3][2];           /* boundary kind per axis and side (0 low, 1 high):
+                               0 periodic, 1 outflow, 2 reflecting wall */
 } oracle_cfg;
+
+enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
 
 /* Primitive vector in a frame rotated to direction d:
  * (rho, u_n, u_t1, u_t2, p); absent velocity components are zero. */
@@ -371,12 +376,26 @@ long oracle_rhs(const oracle_cfg *c, const double *U, double *Lout) {
             double (*qminus)[5] = malloc(sizeof(double) * 5 * len);
             double (*Ff)[5] = malloc(sizeof(double) * 5 * len);
             double *fh = malloc(sizeof(double) * 5 * len);
-            /* gather the pencil with periodic ghosts, rotated to direction d */
+            /* gather the pencil with G ghost cells per side, rotated to direction d.
+             * Ghosts: periodic images; outflow copies the boundary cell
+             * (zero gradient); a reflecting wall mirrors the cells about the
+             * boundary face with the normal velocity reversed. */
             for (int s = 0; s < len; ++s) {
-                int i = ((s - G) % N + N) % N;
+                int i = s - G, flip = 0;
+                if (i < 0 || i >= N) {
+                    int kind = c->bc[d][i < 0 ? 0 : 1];
+                    if (kind == BC_PERIODIC) {
+                        i = ((i % N) + N) % N;
+                    } else if (kind == BC_OUTFLOW) {
+                        i = i < 0 ? 0 : N - 1;
+                    } else {
+                        i = i < 0 ? -1 - i : 2 * N - 1 - i;
+                        flip = 1;
+                    }
+                }
                 size_t cell = base + (size_t)i * stride;
                 q[s][Q_RHO] = Vp[0 * ncell + cell];
-                q[s][Q_UN] = Vp[(size_t)(1 + ax[0]) * ncell + cell];
+                q[s][Q_UN] = (flip ? -1.0 : 1.0) * Vp[(size_t)(1 + ax[0]) * ncell + cell];
                 q[s][Q_UT1] = Vp[(size_t)(1 + ax[1]) * ncell + cell];
                 q[s][Q_UT2] = Vp[(size_t)(1 + ax[2]) * ncell + cell];
                 q[s][Q_P] = Vp[(size_t)4 * ncell + cell];
