@@ -59,11 +59,22 @@ typedef enum {
 } gpweno_precision;
 
 /* Uniform periodic grid. Axes beyond ndim are ignored. */
+typedef enum {
+    GPWENO_BC_PERIODIC = 0, /* periodic images (both sides of the axis) */
+    GPWENO_BC_OUTFLOW = 1,  /* zero-gradient ghosts: copies of the boundary cell */
+    GPWENO_BC_REFLECT = 2   /* reflecting wall: mirror image about the boundary face,
+                               normal velocity reversed; needs n >= R + 3 */
+} gpweno_bc;
+
 typedef struct {
     int ndim;              /* 1, 2 or 3 */
     int n[3];              /* cells per axis */
     double lo[3];          /* domain lower corner */
     double hi[3];          /* domain upper corner */
+    int bc[3][2];          /* gpweno_bc per axis, [axis][0 = low side, 1 = high side];
+                              all zero = periodic everywhere. A periodic axis must be
+                              periodic on both sides. The paper's shock problems use
+                              outflow boundaries (Sec. 7). */
 } gpweno_grid;
 
 /* Interpolation scheme of the Riemann states. GP-WENO is the paper's method;

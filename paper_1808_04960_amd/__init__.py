@@ -34,7 +34,7 @@ class NonPhysicalState(GpwenoError):
 
 class _Grid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
-                ("hi", ctypes.c_double * 3)]
+                ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 6)]
 
 
 class _Options(ctypes.Structure):
@@ -128,13 +128,19 @@ def compute_tables(R, ell_over_dx, sigma_over_dx, scheme="gp-weno"):
 
 
 def make_grid(grid):
-    """Any object with ndim, n, lo, hi (per axis) -> C grid struct."""
+    """Any object with ndim, n, lo, hi (per axis) and optionally bc ((low, high)
+    boundary kinds per axis, gpweno_bc) -> C grid struct."""
     g = _Grid()
     g.ndim = grid.ndim
     for d in range(3):
         g.n[d] = int(grid.n[d]) if d < grid.ndim else 1
         g.lo[d] = float(grid.lo[d]) if d < grid.ndim else 0.0
         g.hi[d] = float(grid.hi[d]) if d < grid.ndim else 1.0
+    bc = getattr(grid, "bc", None)
+    for d in range(3):
+        lo_bc, hi_bc = bc[d] if (bc is not None and d < grid.ndim) else (0, 0)
+        g.bc[2 * d] = int(lo_bc)
+        g.bc[2 * d + 1] = int(hi_bc)
     return g
 
 

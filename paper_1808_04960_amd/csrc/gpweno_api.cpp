@@ -102,10 +102,18 @@ gpw::SweepArgs<Real> base_args(const gpweno_ctx* c, int dir) {
     for (int d = 0; d < 3; ++d) a.inv_dx_all[d] = d < c->grid.ndim ? 1.0 / c->dx[d] : 0.0;
     a.gamma = c->gamma;
     a.positivity = c->opt.positivity_fallback ? 1 : 0;
+    a.bc[0] = c->grid.bc[dir][0];
+    a.bc[1] = c->grid.bc[dir][1];
     a.ctl = c->d_ctl;
     if constexpr (sizeof(Real) == 8) a.tab = c->tabd[dir];
     else a.tab = c->tabf[dir];
     return a;
+}
+
+// True when an axis has a non-periodic side (its sweeps need the general
+// boundary kernels).
+bool general_bc(const gpweno_grid& g, int dir) {
+    return g.bc[dir][0] != GPWENO_BC_PERIODIC || g.bc[dir][1] != GPWENO_BC_PERIODIC;
 }
 
 // One sweep launch (direction dir) in the configured precision.
@@ -117,12 +125,14 @@ int launch(gpweno_ctx* c, int dir, const double* in, const double* un, double* a
         auto a = base_args<float>(c, dir);
         a.U = in; a.Un = un; a.dU = acc; a.Uout = out;
         a.first = first; a.stage = stage; a.step_start = step_start;
-        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, true, fin, c->scheme == GPWENO_WENO_JS, &a, s);
+        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, true, fin, c->scheme == GPWENO_WENO_JS,
+                              general_bc(c->grid, dir), &a, s);
     } else {
         auto a = base_args<double>(c, dir);
         a.U = in; a.Un = un; a.dU = acc; a.Uout = out;
         a.first = first; a.stage = stage; a.step_start = step_start;
-        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, false, fin, c->scheme == GPWENO_WENO_JS, &a, s);
+        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, false, fin, c->scheme == GPWENO_WENO_JS,
+                              general_bc(c->grid, dir), &a, s);
     }
     if (e != hipSuccess) return fail(c, GPWENO_EHIP, "sweep launch (dir %d): %s", dir, hipGetErrorString(e));
     return GPWENO_OK;
@@ -252,8 +262,19 @@ int gpweno_init_scheme(const gpweno_grid* grid, int scheme, int R, double ell, d
     for (int d = 0; d < 3; ++d) {
         if (d >= grid->ndim) {
             c->grid.n[d] = 1;
+            c->grid.bc[d][0] = c->grid.bc[d][1] = GPWENO_BC_PERIODIC;
             c->dx[d] = 1.0;
             continue;
+        }
+        const int blo = grid->bc[d][0], bhi = grid->bc[d][1];
+        if (blo < GPWENO_BC_PERIODIC || blo > GPWENO_BC_REFLECT || bhi < GPWENO_BC_PERIODIC ||
+            bhi > GPWENO_BC_REFLECT || ((blo == GPWENO_BC_PERIODIC) != (bhi == GPWENO_BC_PERIODIC))) {
+            delete c;
+            return fail(nullptr, GPWENO_EINVAL, "axis %d: invalid boundary kinds (%d, %d)", d, blo, bhi);
+        }
+        if ((blo == GPWENO_BC_REFLECT || bhi == GPWENO_BC_REFLECT) && grid->n[d] < R + 3) {
+            delete c;
+            return fail(nullptr, GPWENO_EINVAL, "axis %d: a reflecting side needs n >= R + 3", d);
         }
         if (grid->n[d] < 2 || grid->n[d] > (1 << 24)) {
             delete c;
@@ -491,9 +512,19 @@ struct BatchGroup {
     const gpweno_ctx* proto = nullptr;      // supplies the tables
     std::vector<int> members;               // indices into the set
     long long blocks[3] = {0, 0, 0};        // per direction
+    bool bcg[3] = {false, false, false};    // the members' axis has a non-periodic side
     size_t owner_off[3] = {0, 0, 0};        // element offsets into the owner table
     size_t desc_off[3][3] = {};             // [stage-1][dir] offsets into the descriptor table
 };
+
+// Same kernel instantiation per axis: periodic-only or general boundaries. A
+// problem runs the same kernels in a batch as alone, so its result is bitwise
+// the same.
+bool same_kernels(const gpweno_ctx* a, const gpweno_ctx* b) {
+    for (int d = 0; d < a->grid.ndim; ++d)
+        if (general_bc(a->grid, d) != general_bc(b->grid, d)) return false;
+    return true;
+}
 
 bool same_tables(const gpweno_ctx* a, const gpweno_ctx* b) {
     if (a->scheme != b->scheme) return false;
@@ -565,8 +596,8 @@ int batch_launch(gpweno_batch* b, const BatchGroup& g, int k, hipStream_t s) {
         a.stage = stage;
         a.step_start = k == 0;
         a.tab = g.proto->tabf[0];
-        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, true, fin, g.proto->scheme == GPWENO_WENO_JS, &a, g.blocks[dir],
-                                    s);
+        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, true, fin, g.proto->scheme == GPWENO_WENO_JS, g.bcg[dir], &a,
+                                    g.blocks[dir], s);
     } else {
         gpw::BatchArgs<double> a;
         std::memset(&a, 0, sizeof a);
@@ -576,7 +607,7 @@ int batch_launch(gpweno_batch* b, const BatchGroup& g, int k, hipStream_t s) {
         a.stage = stage;
         a.step_start = k == 0;
         a.tab = g.proto->tabd[0];
-        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, false, fin, g.proto->scheme == GPWENO_WENO_JS, &a,
+        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, false, fin, g.proto->scheme == GPWENO_WENO_JS, g.bcg[dir], &a,
                                     g.blocks[dir], s);
     }
     if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "batched sweep launch: %s", hipGetErrorString(e));
@@ -648,7 +679,9 @@ int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stre
         const bool fp32 = c->opt.precision == GPWENO_FP32;
         BatchGroup* g = nullptr;
         for (auto& h : b->groups)
-            if (h.ndim == c->grid.ndim && h.R == c->R && h.fp32 == fp32 && same_tables(h.proto, c)) g = &h;
+            if (h.ndim == c->grid.ndim && h.R == c->R && h.fp32 == fp32 && same_tables(h.proto, c) &&
+                same_kernels(h.proto, c))
+                g = &h;
         if (!g) {
             b->groups.emplace_back();
             g = &b->groups.back();
@@ -656,6 +689,7 @@ int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stre
             g->R = c->R;
             g->fp32 = fp32;
             g->proto = c;
+            for (int d = 0; d < c->grid.ndim; ++d) g->bcg[d] = general_bc(c->grid, d);
         }
         g->members.push_back(i);
     }
@@ -704,6 +738,8 @@ int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stre
                     for (int d = 0; d < 3; ++d) P.inv_dx_all[d] = d < c->grid.ndim ? 1.0 / c->dx[d] : 0.0;
                     P.gamma = c->gamma;
                     P.positivity = c->opt.positivity_fallback ? 1 : 0;
+                    P.bc[0] = c->grid.bc[dir][0];
+                    P.bc[1] = c->grid.bc[dir][1];
                     P.nblk = (unsigned)nblk[j];
                     P.block0 = b0[j];
                     desc.push_back(P);

@@ -78,6 +78,7 @@ struct SweepArgs {
     int stage;          // 0: right-hand side only; 1..3: SSP-RK3 stage
     int positivity;     // positivity fallback of the Riemann states
     int step_start;     // first sweep of a step: clears the next speed slot
+    int bc[2];          // boundary kinds of the sweep axis (low, high side)
     Tab<Real> tab;
 };
 
@@ -96,6 +97,7 @@ struct ProbDesc {
     double inv_dx_all[3];
     double gamma;
     int positivity;
+    int bc[2];          // boundary kinds of the sweep axis (low, high side)
     unsigned nblk;      // logical blocks of this problem in the launch
     long long block0;   // its first logical block
 };
@@ -122,10 +124,13 @@ struct BatchStatus {
 // stage (last direction of stages 1..3); otherwise it accumulates into dU.
 // pm: the smoothness-indicator factor differs per sub-stencil (Jiang-Shu
 // indicators, R = 1, 2); otherwise Tab::P[0] serves every sub-stencil.
-hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, bool pm, const void* args, hipStream_t s);
+// bcg: the sweep axis has a non-periodic side (the kernel reads bc[]); the
+// periodic-only kernels skip that logic and its registers.
+hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, bool pm, bool bcg, const void* args,
+                        hipStream_t s);
 hipError_t launch_set_run(Ctl* ctl, double t_final, long long step_limit, hipStream_t s);
 long long sweep_blocks(int ndim, int dir, const int n[3], int nseg);
-hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, bool pm, const void* args, long long blocks,
+hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, bool pm, bool bcg, const void* args, long long blocks,
                               hipStream_t s);
 hipError_t launch_gather_status(Ctl* const* ctls, int nprob, BatchStatus* out, hipStream_t s);
 hipError_t launch_set_time(Ctl* ctl, double t, long long nsteps, double cfl, double fixed_dt, hipStream_t s);

@@ -13,8 +13,8 @@
 //     yields 58 cells, and consecutive runs overlap by 6 cells.
 //   * A block holds several pencils (one wave each) and the same run segment.
 //     The input tile [2+ndim fields][pencils][64 + 2R cells] is loaded once
-//     from HBM with periodic wrap, converted to rotated primitive variables and
-//     staged in LDS.
+//     from HBM (ghost positions: periodic image, outflow copy or mirror image),
+//     converted to rotated primitive variables and staged in LDS.
 //   * x sweeps: each wave loads its own row (contiguous along x) and writes its
 //     outputs directly (contiguous). y/z sweeps: a block holds 8 adjacent
 //     x-columns, so every global access covers 8 consecutive doubles; the
@@ -90,6 +90,26 @@ __device__ __forceinline__ int wrap(int x, int n) {
     }
     int r = x % n;
     return r < 0 ? r + n : r;
+}
+
+// Source cell of stencil position x on an axis of n cells, for the boundary kinds
+// lo / hi of its two sides (gpweno_bc: 0 periodic, 1 outflow, 2 reflecting), and
+// whether the normal momentum changes sign (mirror image at a wall). Positions
+// beyond the ghost depth (unused lanes of a pencil's last run) are clamped into
+// the axis so every load stays in bounds.
+__device__ __forceinline__ int ghost_src(int x, int n, int lo, int hi, bool& flip) {
+    flip = false;
+    if (x >= 0 && x < n) return x;
+    const int kind = x < 0 ? lo : hi;
+    if (kind == 0) return wrap(x, n);
+    int j;
+    if (kind == 1) {
+        j = x < 0 ? 0 : n - 1;
+    } else {
+        j = x < 0 ? -1 - x : 2 * n - 1 - x;
+        flip = true;
+    }
+    return j < 0 ? 0 : (j >= n ? n - 1 : j);
 }
 
 // Time step of the step in flight and whether it runs. final_sweep: the
@@ -420,7 +440,7 @@ __device__ __forceinline__ long long xcd_logical_block() {
 }
 
 // One block of a sweep: logical block L of the problem's blocks.
-template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM>
+template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM, bool BCG>
 __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long long L, unsigned char* smem,
                                             unsigned long long* sred) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
@@ -524,10 +544,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
                 const int c = idx / SLEN, pos = idx - c * SLEN;
                 double q[NV];
                 if (c < ncol_valid) {
-                    const long long cell = blk_base + c * cstride + wrap(sbase + pos, N);
+                    bool flip = false;
+                    const long long cell = blk_base + c * cstride +
+                                           (BCG ? ghost_src(sbase + pos, N, a.bc[0], a.bc[1], flip) : wrap(sbase + pos, N));
                     double u[NV];
 #pragma unroll
                     for (int k = 0; k < NV; ++k) u[k] = a.U[k * nc + cell];
+                    if (BCG && flip) u[1 + DIR] = -u[1 + DIR];
                     cons_to_rot<NDIM, DIR>(u, gamma, q);
                 } else {
 #pragma unroll
@@ -546,7 +569,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
                 const int idx = (p + LEFT + R) % SLEN;
                 double q[NV];
                 if (c < ncol_valid) {
-                    const long long cell = blk_base + c * cstride + (long long)wrap(sbase + idx, N) * stride;
+                    bool flip = false;
+                    const long long cell =
+                        blk_base + c * cstride +
+                        (long long)(BCG ? ghost_src(sbase + idx, N, a.bc[0], a.bc[1], flip) : wrap(sbase + idx, N)) * stride;
                     double u[NV];
 #pragma unroll
                     for (int k = 0; k < NV; ++k) u[k] = a.U[k * nc + cell];
@@ -554,6 +580,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
 #pragma unroll
                         for (int k = 0; k < NV; ++k) pu[k] = u[k];
                     }
+                    if (BCG && flip) u[1 + DIR] = -u[1 + DIR];
                     cons_to_rot<NDIM, DIR>(u, gamma, q);
                 } else {
 #pragma unroll
@@ -579,13 +606,20 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
         for (int k = 0; k < NV; ++k) qR[k] = __shfl_down(qm[k], 1);
         hllc<NDIM, Real>(qp, qR, g, inv_gm1, F);
         const Real alpha = Real(-1.0 / 24.0), beta = Real(3.0 / 640.0);
+        // This lane's face is x_{i+1/2} of cell i. At a reflecting wall the mirror
+        // ghosts make the fluxes of mass, tangential momentum and energy vanish
+        // (and the correction terms with them, by antisymmetry) up to rounding;
+        // they are set to exactly zero so that float32 sweeps conserve mass and
+        // energy in a closed box to float64 rounding as well.
+        const int icell = s0 - LEFT + lane;
+        const bool wall = BCG && ((a.bc[0] == 2 && icell == -1) || (a.bc[1] == 2 && icell == N - 1));
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             const Real fm2 = __shfl_up(F[k], 2), fm1 = __shfl_up(F[k], 1);
             const Real fp1 = __shfl_down(F[k], 1), fp2 = __shfl_down(F[k], 2);
             const Real d2 = fm1 - Real(2) * F[k] + fp1;
             const Real d4 = fm2 - Real(4) * fm1 + Real(6) * F[k] - Real(4) * fp1 + fp2;
-            const Real fh = F[k] + alpha * d2 + beta * d4;
+            const Real fh = (wall && k != 1) ? Real(0) : F[k] + alpha * d2 + beta * d4;
             const Real fhm = __shfl_up(fh, 1);
             dcons[cons_slot<NDIM, DIR>(k)] = -((double)fh - (double)fhm) * a.inv_dx;
         }
@@ -633,13 +667,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     }
 }
 
-template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM>
+template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM, bool BCG>
 __global__ void __launch_bounds__(DIR == 0 ? 4 * WAVE : 8 * WAVE)
 sweep_kernel(const SweepArgs<Real> a) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
     __shared__ unsigned long long sred[C::WPB];
-    sweep_block<NDIM, DIR, R, Real, FIN, PM>(a, xcd_logical_block(), smem, sred);
+    sweep_block<NDIM, DIR, R, Real, FIN, PM, BCG>(a, xcd_logical_block(), smem, sred);
 }
 
 // Batched sweep over many independent problems (same ndim, R, precision and
@@ -647,7 +681,7 @@ sweep_kernel(const SweepArgs<Real> a) {
 // the problem of logical block L. Every block runs exactly the code of the
 // single-problem sweep on its own problem's data, so a problem's result does
 // not depend on what else is in the batch.
-template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM>
+template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM, bool BCG>
 __global__ void __launch_bounds__(DIR == 0 ? 4 * WAVE : 8 * WAVE)
 sweep_batch_kernel(const BatchArgs<Real> ba) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
@@ -673,11 +707,13 @@ sweep_batch_kernel(const BatchArgs<Real> ba) {
     a.inv_dx_all[2] = P.inv_dx_all[2];
     a.gamma = P.gamma;
     a.positivity = P.positivity;
+    a.bc[0] = P.bc[0];
+    a.bc[1] = P.bc[1];
     a.first = ba.first;
     a.stage = ba.stage;
     a.step_start = ba.step_start;
     a.tab = ba.tab;
-    sweep_block<NDIM, DIR, R, Real, FIN, PM>(a, Lg - P.block0, smem, sred);
+    sweep_block<NDIM, DIR, R, Real, FIN, PM, BCG>(a, Lg - P.block0, smem, sred);
 }
 
 // ---------------------------------------------------------------------------
@@ -782,7 +818,7 @@ __global__ void sums_final_kernel(const double* __restrict__ partials, int npart
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM>
+template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM, bool BCG>
 hipError_t launch_one(const void* args, hipStream_t s) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     const SweepArgs<Real>& a = *static_cast<const SweepArgs<Real>*>(args);
@@ -795,53 +831,61 @@ hipError_t launch_one(const void* args, hipStream_t s) {
     }
     const long long blocks = groups * a.nseg;
     if (blocks <= 0 || blocks > INT_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sweep_kernel<NDIM, DIR, R, Real, FIN, PM>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
+    hipLaunchKernelGGL((sweep_kernel<NDIM, DIR, R, Real, FIN, PM, BCG>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
 // A finishing kernel exists only for the last direction.
-template <int NDIM, int R, typename Real, bool PM>
+template <int NDIM, int R, typename Real, bool PM, bool BCG>
 hipError_t launch_dir(int dir, bool fin, const void* args, hipStream_t s) {
     if (fin) {
         if (dir != NDIM - 1) return hipErrorInvalidValue;
-        return launch_one<NDIM, NDIM - 1, R, Real, true, PM>(args, s);
+        return launch_one<NDIM, NDIM - 1, R, Real, true, PM, BCG>(args, s);
     }
-    if (dir == 0) return launch_one<NDIM, 0, R, Real, false, PM>(args, s);
-    if (NDIM >= 2 && dir == 1) return launch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false, PM>(args, s);
-    if (NDIM == 3 && dir == 2) return launch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false, PM>(args, s);
+    if (dir == 0) return launch_one<NDIM, 0, R, Real, false, PM, BCG>(args, s);
+    if (NDIM >= 2 && dir == 1) return launch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false, PM, BCG>(args, s);
+    if (NDIM == 3 && dir == 2) return launch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false, PM, BCG>(args, s);
     return hipErrorInvalidValue;
+}
+
+template <int NDIM, int R, typename Real, bool PM>
+hipError_t launch_bcg(int dir, bool fin, bool bcg, const void* args, hipStream_t s) {
+    return bcg ? launch_dir<NDIM, R, Real, PM, true>(dir, fin, args, s)
+               : launch_dir<NDIM, R, Real, PM, false>(dir, fin, args, s);
 }
 
 // Per-sub-stencil indicator factors (Jiang-Shu) exist for R = 1, 2 only.
 template <int NDIM, typename Real>
-hipError_t launch_r(int dir, int R, bool fin, bool pm, const void* args, hipStream_t s) {
+hipError_t launch_r(int dir, int R, bool fin, bool pm, bool bcg, const void* args, hipStream_t s) {
     if (pm) {
         switch (R) {
-            case 1: return launch_dir<NDIM, 1, Real, true>(dir, fin, args, s);
-            case 2: return launch_dir<NDIM, 2, Real, true>(dir, fin, args, s);
+            case 1: return launch_bcg<NDIM, 1, Real, true>(dir, fin, bcg, args, s);
+            case 2: return launch_bcg<NDIM, 2, Real, true>(dir, fin, bcg, args, s);
             default: return hipErrorInvalidValue;
         }
     }
     switch (R) {
-        case 1: return launch_dir<NDIM, 1, Real, false>(dir, fin, args, s);
-        case 2: return launch_dir<NDIM, 2, Real, false>(dir, fin, args, s);
-        case 3: return launch_dir<NDIM, 3, Real, false>(dir, fin, args, s);
+        case 1: return launch_bcg<NDIM, 1, Real, false>(dir, fin, bcg, args, s);
+        case 2: return launch_bcg<NDIM, 2, Real, false>(dir, fin, bcg, args, s);
+        case 3: return launch_bcg<NDIM, 3, Real, false>(dir, fin, bcg, args, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename Real>
-hipError_t launch_nd(int ndim, int dir, int R, bool fin, bool pm, const void* args, hipStream_t s) {
+hipError_t launch_nd(int ndim, int dir, int R, bool fin, bool pm, bool bcg, const void* args, hipStream_t s) {
     switch (ndim) {
-        case 1: return launch_r<1, Real>(dir, R, fin, pm, args, s);
-        case 2: return launch_r<2, Real>(dir, R, fin, pm, args, s);
-        case 3: return launch_r<3, Real>(dir, R, fin, pm, args, s);
+        case 1: return launch_r<1, Real>(dir, R, fin, pm, bcg, args, s);
+        case 2: return launch_r<2, Real>(dir, R, fin, pm, bcg, args, s);
+        case 3: return launch_r<3, Real>(dir, R, fin, pm, bcg, args, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, bool pm, const void* args, hipStream_t s) {
-    return fp32 ? launch_nd<float>(ndim, dir, R, fin, pm, args, s) : launch_nd<double>(ndim, dir, R, fin, pm, args, s);
+hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, bool pm, bool bcg, const void* args,
+                        hipStream_t s) {
+    return fp32 ? launch_nd<float>(ndim, dir, R, fin, pm, bcg, args, s)
+                : launch_nd<double>(ndim, dir, R, fin, pm, bcg, args, s);
 }
 
 // ---- batched launches --------------------------------------------------------
@@ -854,60 +898,69 @@ long long sweep_blocks(int ndim, int dir, const int n[3], int nseg) {
     return groups * nseg;
 }
 
-template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM>
+template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM, bool BCG>
 hipError_t launch_batch_one(const void* args, long long blocks, hipStream_t s) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     const BatchArgs<Real>& a = *static_cast<const BatchArgs<Real>*>(args);
     if (blocks <= 0 || blocks > INT_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sweep_batch_kernel<NDIM, DIR, R, Real, FIN, PM>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
+    hipLaunchKernelGGL((sweep_batch_kernel<NDIM, DIR, R, Real, FIN, PM, BCG>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
                        a);
     return hipGetLastError();
 }
 
-template <int NDIM, int R, typename Real, bool PM>
+template <int NDIM, int R, typename Real, bool PM, bool BCG>
 hipError_t launch_batch_dir(int dir, bool fin, const void* args, long long blocks, hipStream_t s) {
     if (fin) {
         if (dir != NDIM - 1) return hipErrorInvalidValue;
-        return launch_batch_one<NDIM, NDIM - 1, R, Real, true, PM>(args, blocks, s);
+        return launch_batch_one<NDIM, NDIM - 1, R, Real, true, PM, BCG>(args, blocks, s);
     }
-    if (dir == 0) return launch_batch_one<NDIM, 0, R, Real, false, PM>(args, blocks, s);
-    if (NDIM >= 2 && dir == 1) return launch_batch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false, PM>(args, blocks, s);
-    if (NDIM == 3 && dir == 2) return launch_batch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false, PM>(args, blocks, s);
+    if (dir == 0) return launch_batch_one<NDIM, 0, R, Real, false, PM, BCG>(args, blocks, s);
+    if (NDIM >= 2 && dir == 1)
+        return launch_batch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false, PM, BCG>(args, blocks, s);
+    if (NDIM == 3 && dir == 2)
+        return launch_batch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false, PM, BCG>(args, blocks, s);
     return hipErrorInvalidValue;
 }
 
+template <int NDIM, int R, typename Real, bool PM>
+hipError_t launch_batch_bcg(int dir, bool fin, bool bcg, const void* args, long long blocks, hipStream_t s) {
+    return bcg ? launch_batch_dir<NDIM, R, Real, PM, true>(dir, fin, args, blocks, s)
+               : launch_batch_dir<NDIM, R, Real, PM, false>(dir, fin, args, blocks, s);
+}
+
 template <int NDIM, typename Real>
-hipError_t launch_batch_r(int dir, int R, bool fin, bool pm, const void* args, long long blocks, hipStream_t s) {
+hipError_t launch_batch_r(int dir, int R, bool fin, bool pm, bool bcg, const void* args, long long blocks,
+                          hipStream_t s) {
     if (pm) {
         switch (R) {
-            case 1: return launch_batch_dir<NDIM, 1, Real, true>(dir, fin, args, blocks, s);
-            case 2: return launch_batch_dir<NDIM, 2, Real, true>(dir, fin, args, blocks, s);
+            case 1: return launch_batch_bcg<NDIM, 1, Real, true>(dir, fin, bcg, args, blocks, s);
+            case 2: return launch_batch_bcg<NDIM, 2, Real, true>(dir, fin, bcg, args, blocks, s);
             default: return hipErrorInvalidValue;
         }
     }
     switch (R) {
-        case 1: return launch_batch_dir<NDIM, 1, Real, false>(dir, fin, args, blocks, s);
-        case 2: return launch_batch_dir<NDIM, 2, Real, false>(dir, fin, args, blocks, s);
-        case 3: return launch_batch_dir<NDIM, 3, Real, false>(dir, fin, args, blocks, s);
+        case 1: return launch_batch_bcg<NDIM, 1, Real, false>(dir, fin, bcg, args, blocks, s);
+        case 2: return launch_batch_bcg<NDIM, 2, Real, false>(dir, fin, bcg, args, blocks, s);
+        case 3: return launch_batch_bcg<NDIM, 3, Real, false>(dir, fin, bcg, args, blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename Real>
-hipError_t launch_batch_nd(int ndim, int dir, int R, bool fin, bool pm, const void* args, long long blocks,
+hipError_t launch_batch_nd(int ndim, int dir, int R, bool fin, bool pm, bool bcg, const void* args, long long blocks,
                            hipStream_t s) {
     switch (ndim) {
-        case 1: return launch_batch_r<1, Real>(dir, R, fin, pm, args, blocks, s);
-        case 2: return launch_batch_r<2, Real>(dir, R, fin, pm, args, blocks, s);
-        case 3: return launch_batch_r<3, Real>(dir, R, fin, pm, args, blocks, s);
+        case 1: return launch_batch_r<1, Real>(dir, R, fin, pm, bcg, args, blocks, s);
+        case 2: return launch_batch_r<2, Real>(dir, R, fin, pm, bcg, args, blocks, s);
+        case 3: return launch_batch_r<3, Real>(dir, R, fin, pm, bcg, args, blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, bool pm, const void* args,
+hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, bool pm, bool bcg, const void* args,
                               long long blocks, hipStream_t s) {
-    return fp32 ? launch_batch_nd<float>(ndim, dir, R, fin, pm, args, blocks, s)
-                : launch_batch_nd<double>(ndim, dir, R, fin, pm, args, blocks, s);
+    return fp32 ? launch_batch_nd<float>(ndim, dir, R, fin, pm, bcg, args, blocks, s)
+                : launch_batch_nd<double>(ndim, dir, R, fin, pm, bcg, args, blocks, s);
 }
 
 // Copies the step state of every problem of a batch into a compact array.

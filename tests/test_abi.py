@@ -76,8 +76,8 @@ def test_tables_reject_invalid_arguments():
 
 
 class _G:
-    def __init__(self, ndim, n, lo=(0, 0, 0), hi=(1, 1, 1)):
-        self.ndim, self.n, self.lo, self.hi = ndim, n, lo, hi
+    def __init__(self, ndim, n, lo=(0, 0, 0), hi=(1, 1, 1), bc=((0, 0), (0, 0), (0, 0))):
+        self.ndim, self.n, self.lo, self.hi, self.bc = ndim, n, lo, hi, bc
 
 
 @pytest.mark.parametrize("grid,R,ell,sigma,gamma", [
@@ -87,6 +87,9 @@ class _G:
     (_G(1, (64, 1, 1)), 2, 0.1, 0.05, 1.0),     # gamma <= 1
     (_G(1, (1, 1, 1)), 2, 0.1, 2.0, 1.4),       # too few cells
     (_G(2, (64, 64, 1), hi=(1, 0, 1)), 2, 0.1, 0.05, 1.4),  # empty domain
+    (_G(1, (64, 1, 1), bc=((0, 1), (0, 0), (0, 0))), 2, 0.1, 0.05, 1.4),  # periodic on one side only
+    (_G(2, (64, 64, 1), bc=((1, 1), (3, 1), (0, 0))), 2, 0.1, 0.05, 1.4),  # unknown boundary kind
+    (_G(1, (5, 1, 1), bc=((2, 2), (0, 0), (0, 0))), 3, 1.0, 0.5, 1.4),     # reflecting axis shorter than R + 3
 ])
 def test_init_validates_before_touching_a_device(L, grid, R, ell, sigma, gamma):
     g = gw.make_grid(grid)
