@@ -51,6 +51,7 @@ class Cfg(ctypes.Structure):
         ("beta_form", ctypes.c_int),
         ("B", ctypes.c_double * 192),
         ("bc", ctypes.c_int * 6),
+        ("nonzero_mean", ctypes.c_int),
     ]
 
 
@@ -80,7 +81,8 @@ def lib():
         L.oracle_run_fixed.restype = ctypes.c_long
         L.oracle_run_fixed.argtypes = [ctypes.POINTER(Cfg), _dp, ctypes.c_double, ctypes.c_long]
         L.oracle_gp_weno.restype = None
-        L.oracle_gp_weno.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_gp_weno.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp,
+                                     _dp, _dp]
         L.oracle_hllc.restype = None
         L.oracle_hllc.argtypes = [_dp, _dp, ctypes.c_double, _dp]
         L.oracle_flux_hat.restype = ctypes.c_double
@@ -109,7 +111,7 @@ def _ptr(a: np.ndarray):
 # ----------------------------------------------------------------------------
 # Thin wrappers over the per-step building blocks (used by the pin tests).
 # ----------------------------------------------------------------------------
-def gp_weno(f, tab):
+def gp_weno(f, tab, nonzero_mean=False):
     """WENO interpolation of one variable; ``f`` has 2R+1 entries. ``tab`` is a
     table dict (``gp_tables`` or ``scheme_tables``); a 'B' beta form selects the
     polynomial smoothness indicator. Returns (q+, q-, beta, omega+, omega-)."""
@@ -125,7 +127,8 @@ def gp_weno(f, tab):
     if tab.get("beta_form") == "B":
         B = np.ascontiguousarray(tab["B"], dtype=np.float64)
     lib().oracle_gp_weno(R, _ptr(f), *[_ptr(a) for a in arrs], _ptr(B) if B is not None else None,
-                         ctypes.byref(qp), ctypes.byref(qm), _ptr(beta), _ptr(omp), _ptr(omm))
+                         1 if nonzero_mean else 0, ctypes.byref(qp), ctypes.byref(qm), _ptr(beta), _ptr(omp),
+                         _ptr(omm))
     return qp.value, qm.value, beta[: R + 1], omp[: R + 1], omm[: R + 1]
 
 
@@ -163,9 +166,11 @@ def rk3_combine(stage, Un, Uin, L, dt):
 # ----------------------------------------------------------------------------
 class OracleSolver:
     """FP64 CPU reference solver. ``ell`` and ``sigma`` are physical lengths.
-    ``scheme`` is one of ``SCHEMES`` (default: the paper's GP-WENO)."""
+    ``scheme`` is one of ``SCHEMES`` (default: the paper's GP-WENO).
+    ``nonzero_mean``: GP indicators of the data minus the centre cell's value."""
 
-    def __init__(self, grid, R, ell, sigma, gamma=1.4, cfl=0.4, positivity_fallback=False, scheme="gp-weno"):
+    def __init__(self, grid, R, ell, sigma, gamma=1.4, cfl=0.4, positivity_fallback=False, scheme="gp-weno",
+                 nonzero_mean=False):
         self.grid = grid
         self.R = R
         self.cfl = cfl
@@ -177,6 +182,7 @@ class OracleSolver:
         c.R = R
         c.gamma = gamma
         c.positivity_fallback = 1 if positivity_fallback else 0
+        c.nonzero_mean = 1 if nonzero_mean else 0
         bc = getattr(grid, "bc", ((0, 0),) * 3)
         for d in range(3):
             lo_bc, hi_bc = bc[d] if d < grid.ndim else (0, 0)

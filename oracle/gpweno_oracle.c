@@ -65,6 +65,7 @@ typedef struct {
     double B[3][4][4][4];   /* [d][m][i][j], used when beta_form = 1 */
     int bc[3][2];           /* boundary kind per axis and side (0 low, 1 high):
                                0 periodic, 1 outflow, 2 reflecting wall */
+    int nonzero_mean;       /* 1: GP indicators of f_m - f_i (centre-cell mean, Sec. 7) */
 } oracle_cfg;
 
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
@@ -186,6 +187,9 @@ void oracle_char_vectors(const double *q, double gamma, double *Lm, double *Rm) 
  * Sub-stencil m = 0..R holds f[m .. m+R]. beta is shared by the two
  * prediction points because the sub-stencils are the same sets.
  * Optional outputs (may be NULL): beta[R+1], omega_p[R+1], omega_m[R+1].
+ * nonzero_mean: the GP indicator of f_m - f_i instead of f_m, with f_i = f[R]
+ * the centre cell's value (Sec. 7, the non-zero-mean prior of the scalar
+ * advection test).
  *
  * The same function serves the paper's comparison schemes (Sec. 6.2, Table
  * (weno-vortex)) with other tables: polynomial (Lagrange) weights and linear
@@ -199,6 +203,7 @@ void oracle_gp_weno(int R, const double *f,
                     const double *gp, const double *gm,   /* [4] */
                     const double *P,                      /* [4][4] */
                     const double *B,                      /* [4][4][4] or NULL */
+                    int nonzero_mean,
                     double *qplus, double *qminus,
                     double *beta_out, double *omp_out, double *omm_out) {
     double beta[RMAX + 1], qp[RMAX + 1], qm[RMAX + 1];
@@ -212,9 +217,12 @@ void oracle_gp_weno(int R, const double *f,
             for (int i = 0; i <= R; ++i)
                 for (int j = 0; j <= R; ++j) b += B[16 * m + 4 * i + j] * fm[i] * fm[j];
         } else {
+            /* zero mean: the data itself; non-zero mean: its deviation from the
+             * centre cell's value f[R] */
+            double mean = nonzero_mean ? f[R] : 0.0;
             for (int i = 0; i <= R; ++i) {
                 double proj = 0.0;
-                for (int j = 0; j <= R; ++j) proj += P[4 * i + j] * fm[j];
+                for (int j = 0; j <= R; ++j) proj += P[4 * i + j] * (fm[j] - mean);
                 b += proj * proj;
             }
         }
@@ -310,7 +318,7 @@ static int reconstruct_cell(const oracle_cfg *c, int d, const double (*qs)[5],
             f[s] = w;
         }
         oracle_gp_weno(R, f, &c->wp[d][0][0], &c->wm[d][0][0], c->gp[d], c->gm[d],
-                       &c->P[d][0][0], c->beta_form ? &c->B[d][0][0][0] : NULL,
+                       &c->P[d][0][0], c->beta_form ? &c->B[d][0][0][0] : NULL, c->nonzero_mean,
                        &Wp[k], &Wm[k], NULL, NULL, NULL);
     }
     for (int q = 0; q < 5; ++q) {
