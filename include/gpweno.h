@@ -96,6 +96,12 @@ typedef struct {
     int positivity_fallback; /* 1: a Riemann state with rho <= 0 or p <= 0 is replaced
                                 by the cell-centre state (default 0) */
     void *stream;          /* hipStream_t, NULL = default stream */
+    int nonzero_mean;      /* 1: the GP smoothness indicators (GP-WENO, WENO-GP) see
+                              the sub-stencil data minus the centre cell's value,
+                              the non-zero-mean variant of Sec. 7 (scalar advection);
+                              0: zero mean, the paper's default (default 0). No
+                              effect on the Jiang-Shu indicators, which ignore
+                              constants. */
 } gpweno_options;
 
 typedef struct gpweno_ctx gpweno_ctx;

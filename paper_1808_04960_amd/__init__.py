@@ -39,7 +39,7 @@ class _Grid(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("cfl", ctypes.c_double), ("fixed_dt", ctypes.c_double),
-                ("positivity_fallback", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("positivity_fallback", ctypes.c_int), ("stream", ctypes.c_void_p), ("nonzero_mean", ctypes.c_int)]
 
 
 _lib = None
@@ -155,7 +155,7 @@ class Solver:
     """
 
     def __init__(self, grid, R, ell, sigma, gamma=1.4, precision="fp64", cfl=0.4, fixed_dt=0.0,
-                 positivity_fallback=False, U0=None, device=None, stream=None, scheme="gp-weno"):
+                 positivity_fallback=False, U0=None, device=None, stream=None, scheme="gp-weno", nonzero_mean=False):
         import torch
 
         if not torch.cuda.is_available():
@@ -178,18 +178,23 @@ class Solver:
             self.workspace = torch.empty(lib().gpweno_workspace_bytes(self._ctx), dtype=torch.uint8,
                                          device=self.device)
         self._bound = False
+        self.nonzero_mean = bool(nonzero_mean)
         self.set_options(precision, cfl, fixed_dt, positivity_fallback)
         if U0 is not None:
             self.set_state(U0)
 
     # -- configuration -------------------------------------------------------
-    def set_options(self, precision="fp64", cfl=0.4, fixed_dt=0.0, positivity_fallback=False):
+    def set_options(self, precision="fp64", cfl=0.4, fixed_dt=0.0, positivity_fallback=False, nonzero_mean=None):
+        """nonzero_mean: None keeps the current choice (see gpweno_options)."""
+        if nonzero_mean is not None:
+            self.nonzero_mean = bool(nonzero_mean)
         o = _Options()
         o.precision = {"fp64": FP64, "fp32": FP32}[precision]
         o.cfl = cfl
         o.fixed_dt = fixed_dt
         o.positivity_fallback = 1 if positivity_fallback else 0
         o.stream = self.stream.cuda_stream
+        o.nonzero_mean = 1 if self.nonzero_mean else 0
         self.precision = precision
         _check(lib().gpweno_set_options(self._ctx, ctypes.byref(o)), self._ctx)
 

@@ -110,6 +110,12 @@ gpw::SweepArgs<Real> base_args(const gpweno_ctx* c, int dir) {
     return a;
 }
 
+// Smoothness-indicator kind of the kernels (see launch_sweep).
+int indicator_kind(const gpweno_ctx* c) {
+    if (c->scheme == GPWENO_WENO_JS) return 1;
+    return c->opt.nonzero_mean ? 2 : 0;
+}
+
 // True when an axis has a non-periodic side (its sweeps need the general
 // boundary kernels).
 bool general_bc(const gpweno_grid& g, int dir) {
@@ -125,14 +131,13 @@ int launch(gpweno_ctx* c, int dir, const double* in, const double* un, double* a
         auto a = base_args<float>(c, dir);
         a.U = in; a.Un = un; a.dU = acc; a.Uout = out;
         a.first = first; a.stage = stage; a.step_start = step_start;
-        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, true, fin, c->scheme == GPWENO_WENO_JS,
-                              general_bc(c->grid, dir), &a, s);
+        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, true, fin, indicator_kind(c), general_bc(c->grid, dir), &a, s);
     } else {
         auto a = base_args<double>(c, dir);
         a.U = in; a.Un = un; a.dU = acc; a.Uout = out;
         a.first = first; a.stage = stage; a.step_start = step_start;
-        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, false, fin, c->scheme == GPWENO_WENO_JS,
-                              general_bc(c->grid, dir), &a, s);
+        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, false, fin, indicator_kind(c), general_bc(c->grid, dir), &a,
+                              s);
     }
     if (e != hipSuccess) return fail(c, GPWENO_EHIP, "sweep launch (dir %d): %s", dir, hipGetErrorString(e));
     return GPWENO_OK;
@@ -308,6 +313,7 @@ int gpweno_init_scheme(const gpweno_grid* grid, int scheme, int R, double ell, d
     c->opt.fixed_dt = 0.0;
     c->opt.positivity_fallback = 0;
     c->opt.stream = nullptr;
+    c->opt.nonzero_mean = 0;
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipMalloc(&c->d_ctl, sizeof(gpw::Ctl));
     if (e == hipSuccess) e = hipHostMalloc(&c->h_ctl, sizeof(gpw::Ctl), hipHostMallocDefault);
@@ -327,7 +333,8 @@ int gpweno_set_options(gpweno_ctx* c, const gpweno_options* o) {
     if (!c) return fail(nullptr, GPWENO_EINVAL, "NULL context");
     if (!valid_options(o)) return fail(c, GPWENO_EINVAL, "invalid options");
     const bool changes_graph = o->precision != c->opt.precision ||
-                               o->positivity_fallback != c->opt.positivity_fallback || o->stream != c->opt.stream;
+                               o->positivity_fallback != c->opt.positivity_fallback || o->stream != c->opt.stream ||
+                               (o->nonzero_mean != 0) != (c->opt.nonzero_mean != 0);
     const bool changes_rule = o->cfl != c->opt.cfl || o->fixed_dt != c->opt.fixed_dt;
     c->opt = *o;
     if (changes_graph) drop_graph(c);
@@ -521,6 +528,7 @@ struct BatchGroup {
 // problem runs the same kernels in a batch as alone, so its result is bitwise
 // the same.
 bool same_kernels(const gpweno_ctx* a, const gpweno_ctx* b) {
+    if (indicator_kind(a) != indicator_kind(b)) return false;
     for (int d = 0; d < a->grid.ndim; ++d)
         if (general_bc(a->grid, d) != general_bc(b->grid, d)) return false;
     return true;
@@ -596,7 +604,7 @@ int batch_launch(gpweno_batch* b, const BatchGroup& g, int k, hipStream_t s) {
         a.stage = stage;
         a.step_start = k == 0;
         a.tab = g.proto->tabf[0];
-        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, true, fin, g.proto->scheme == GPWENO_WENO_JS, g.bcg[dir], &a,
+        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, true, fin, indicator_kind(g.proto), g.bcg[dir], &a,
                                     g.blocks[dir], s);
     } else {
         gpw::BatchArgs<double> a;
@@ -607,7 +615,7 @@ int batch_launch(gpweno_batch* b, const BatchGroup& g, int k, hipStream_t s) {
         a.stage = stage;
         a.step_start = k == 0;
         a.tab = g.proto->tabd[0];
-        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, false, fin, g.proto->scheme == GPWENO_WENO_JS, g.bcg[dir], &a,
+        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, false, fin, indicator_kind(g.proto), g.bcg[dir], &a,
                                     g.blocks[dir], s);
     }
     if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "batched sweep launch: %s", hipGetErrorString(e));

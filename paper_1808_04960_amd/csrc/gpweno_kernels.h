@@ -122,15 +122,16 @@ struct BatchStatus {
 
 // Launchers (defined in gpweno_kernels.hip). fin: the sweep finishes an RK
 // stage (last direction of stages 1..3); otherwise it accumulates into dU.
-// pm: the smoothness-indicator factor differs per sub-stencil (Jiang-Shu
-// indicators, R = 1, 2); otherwise Tab::P[0] serves every sub-stencil.
+// ik: smoothness-indicator kind. 0: GP, Tab::P[0] serves every sub-stencil;
+// 1: a factor per sub-stencil (Jiang-Shu, R = 1, 2); 2: GP on the data minus the
+// centre cell's value (non-zero mean).
 // bcg: the sweep axis has a non-periodic side (the kernel reads bc[]); the
 // periodic-only kernels skip that logic and its registers.
-hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, bool pm, bool bcg, const void* args,
+hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, int ik, bool bcg, const void* args,
                         hipStream_t s);
 hipError_t launch_set_run(Ctl* ctl, double t_final, long long step_limit, hipStream_t s);
 long long sweep_blocks(int ndim, int dir, const int n[3], int nseg);
-hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, bool pm, bool bcg, const void* args, long long blocks,
+hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, int ik, bool bcg, const void* args, long long blocks,
                               hipStream_t s);
 hipError_t launch_gather_status(Ctl* const* ctls, int nprob, BatchStatus* out, hipStream_t s);
 hipError_t launch_set_time(Ctl* ctl, double t, long long nsteps, double cfl, double fixed_dt, hipStream_t s);

@@ -163,23 +163,30 @@ __device__ __forceinline__ void cons_to_rot(const double (&u)[2 + NDIM], double 
 // GP-WENO interpolation of one characteristic field f[0..2R] to x_{i+1/2} (qp)
 // and x_{i-1/2} (qm). beta_m = sum_i (P_m,i . f_m)^2 is shared by both points.
 // The comparison schemes (polynomial WENO with Jiang-Shu or GP smoothness
-// indicators) run through the same code with their own tables. PM selects a
-// factor per sub-stencil (Jiang-Shu); otherwise the one factor of K_m(sigma),
-// the same for every m, is read once (fewer scalar registers for the tables).
+// indicators) run through the same code with their own tables. IK, the kind of
+// smoothness indicator:
+//   0  GP, zero mean: the one factor of K_m(sigma), the same for every m, read
+//      once (fewer scalar registers for the tables);
+//   1  a factor per sub-stencil of rank R (Jiang-Shu quadratic forms);
+//   2  GP with the centre cell's value as the mean: the factor of K_m(sigma)
+//      applied to f_m - f_i (the paper's non-zero-mean variant, Sec. 7).
 // Nonlinear weights gamma_m / (eps + beta_m)^2 are evaluated in the equivalent
 // form gamma_m * ((eps + beta_min)/(eps + beta_m))^2, which cannot overflow or
 // underflow to 0/0 in float32 (eps = 1e-36 squared is below float range).
-template <int R, typename Real, bool PM>
+template <int R, typename Real, int IK>
 __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Real>& T, Real& qp, Real& qm) {
     Real e[R + 1], cp[R + 1], cm[R + 1];
+    Real g[2 * R + 1];  // the data the indicators see
+#pragma unroll
+    for (int j = 0; j <= 2 * R; ++j) g[j] = IK == 2 ? f[j] - f[R] : f[j];
 #pragma unroll
     for (int m = 0; m <= R; ++m) {
         Real b = Real(0);
 #pragma unroll
-        for (int i = 0; i < (PM ? R : R + 1); ++i) {  // Jiang-Shu forms have rank R
-            Real pr = T.P[PM ? m : 0][i][0] * f[m];
+        for (int i = 0; i < (IK == 1 ? R : R + 1); ++i) {  // Jiang-Shu forms have rank R
+            Real pr = T.P[IK == 1 ? m : 0][i][0] * g[m];
 #pragma unroll
-            for (int j = 1; j <= R; ++j) pr = fma(T.P[PM ? m : 0][i][j], f[m + j], pr);
+            for (int j = 1; j <= R; ++j) pr = fma(T.P[IK == 1 ? m : 0][i][j], g[m + j], pr);
             b = fma(pr, pr, b);
         }
         e[m] = Real(1e-36) + b;
@@ -222,7 +229,7 @@ __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Re
 //   entropy   :  rho - p/c^2                    r = (1, 0, 0, 0, 0)
 //   shear     :  u_t1, u_t2                     r = unit vectors
 //   acoustic +:   rho/(2c) u_n + p/(2c^2)       r = (1,  c/rho, 0, 0, c^2)
-template <int NDIM, int R, typename Real, bool PM>
+template <int NDIM, int R, typename Real, int IK>
 __device__ __forceinline__ void reconstruct(const Real* __restrict__ s, int fs, int l, const Tab<Real>& T,
                                             Real gamma, int positivity, Real (&qp)[2 + NDIM],
                                             Real (&qm)[2 + NDIM]) {
@@ -247,18 +254,18 @@ __device__ __forceinline__ void reconstruct(const Real* __restrict__ s, int fs, 
     Real acm_p, acm_m, ent_p, ent_m, acp_p, acp_m;
 #pragma unroll
     for (int j = 0; j < NS; ++j) f[j] = fma(-a, v[1][j], b * v[NV - 1][j]);
-    gp_weno<R, Real, PM>(f, T, acm_p, acm_m);
+    gp_weno<R, Real, IK>(f, T, acm_p, acm_m);
 #pragma unroll
     for (int j = 0; j < NS; ++j) f[j] = fma(-ic2, v[NV - 1][j], v[0][j]);
-    gp_weno<R, Real, PM>(f, T, ent_p, ent_m);
+    gp_weno<R, Real, IK>(f, T, ent_p, ent_m);
 #pragma unroll
     for (int j = 0; j < NS; ++j) f[j] = fma(a, v[1][j], b * v[NV - 1][j]);
-    gp_weno<R, Real, PM>(f, T, acp_p, acp_m);
+    gp_weno<R, Real, IK>(f, T, acp_p, acp_m);
 #pragma unroll
     for (int t = 0; t < NDIM - 1; ++t) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) f[j] = v[2 + t][j];
-        gp_weno<R, Real, PM>(f, T, qp[2 + t], qm[2 + t]);
+        gp_weno<R, Real, IK>(f, T, qp[2 + t], qm[2 + t]);
     }
     const Real cr = c * irho;
     qp[0] = acm_p + ent_p + acp_p;
@@ -440,7 +447,7 @@ __device__ __forceinline__ long long xcd_logical_block() {
 }
 
 // One block of a sweep: logical block L of the problem's blocks.
-template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM, bool BCG>
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
 __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long long L, unsigned char* smem,
                                             unsigned long long* sred) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
@@ -600,7 +607,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
         const Real g = (Real)gamma;
         const Real inv_gm1 = (Real)(1.0 / (gamma - 1.0));
         Real qp[NV], qm[NV];
-        reconstruct<NDIM, R, Real, PM>(sV + w * PITCH, FS, lane, a.tab, g, a.positivity, qp, qm);
+        reconstruct<NDIM, R, Real, IK>(sV + w * PITCH, FS, lane, a.tab, g, a.positivity, qp, qm);
         Real qR[NV], F[NV];
 #pragma unroll
         for (int k = 0; k < NV; ++k) qR[k] = __shfl_down(qm[k], 1);
@@ -667,13 +674,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     }
 }
 
-template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM, bool BCG>
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
 __global__ void __launch_bounds__(DIR == 0 ? 4 * WAVE : 8 * WAVE)
 sweep_kernel(const SweepArgs<Real> a) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
     __shared__ unsigned long long sred[C::WPB];
-    sweep_block<NDIM, DIR, R, Real, FIN, PM, BCG>(a, xcd_logical_block(), smem, sred);
+    sweep_block<NDIM, DIR, R, Real, FIN, IK, BCG>(a, xcd_logical_block(), smem, sred);
 }
 
 // Batched sweep over many independent problems (same ndim, R, precision and
@@ -681,7 +688,7 @@ sweep_kernel(const SweepArgs<Real> a) {
 // the problem of logical block L. Every block runs exactly the code of the
 // single-problem sweep on its own problem's data, so a problem's result does
 // not depend on what else is in the batch.
-template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM, bool BCG>
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
 __global__ void __launch_bounds__(DIR == 0 ? 4 * WAVE : 8 * WAVE)
 sweep_batch_kernel(const BatchArgs<Real> ba) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
@@ -713,7 +720,7 @@ sweep_batch_kernel(const BatchArgs<Real> ba) {
     a.stage = ba.stage;
     a.step_start = ba.step_start;
     a.tab = ba.tab;
-    sweep_block<NDIM, DIR, R, Real, FIN, PM, BCG>(a, Lg - P.block0, smem, sred);
+    sweep_block<NDIM, DIR, R, Real, FIN, IK, BCG>(a, Lg - P.block0, smem, sred);
 }
 
 // ---------------------------------------------------------------------------
@@ -818,7 +825,7 @@ __global__ void sums_final_kernel(const double* __restrict__ partials, int npart
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM, bool BCG>
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
 hipError_t launch_one(const void* args, hipStream_t s) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     const SweepArgs<Real>& a = *static_cast<const SweepArgs<Real>*>(args);
@@ -831,61 +838,66 @@ hipError_t launch_one(const void* args, hipStream_t s) {
     }
     const long long blocks = groups * a.nseg;
     if (blocks <= 0 || blocks > INT_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sweep_kernel<NDIM, DIR, R, Real, FIN, PM, BCG>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
+    hipLaunchKernelGGL((sweep_kernel<NDIM, DIR, R, Real, FIN, IK, BCG>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
     return hipGetLastError();
 }
 
 // A finishing kernel exists only for the last direction.
-template <int NDIM, int R, typename Real, bool PM, bool BCG>
+template <int NDIM, int R, typename Real, int IK, bool BCG>
 hipError_t launch_dir(int dir, bool fin, const void* args, hipStream_t s) {
     if (fin) {
         if (dir != NDIM - 1) return hipErrorInvalidValue;
-        return launch_one<NDIM, NDIM - 1, R, Real, true, PM, BCG>(args, s);
+        return launch_one<NDIM, NDIM - 1, R, Real, true, IK, BCG>(args, s);
     }
-    if (dir == 0) return launch_one<NDIM, 0, R, Real, false, PM, BCG>(args, s);
-    if (NDIM >= 2 && dir == 1) return launch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false, PM, BCG>(args, s);
-    if (NDIM == 3 && dir == 2) return launch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false, PM, BCG>(args, s);
+    if (dir == 0) return launch_one<NDIM, 0, R, Real, false, IK, BCG>(args, s);
+    if (NDIM >= 2 && dir == 1) return launch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false, IK, BCG>(args, s);
+    if (NDIM == 3 && dir == 2) return launch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false, IK, BCG>(args, s);
     return hipErrorInvalidValue;
 }
 
-template <int NDIM, int R, typename Real, bool PM>
+template <int NDIM, int R, typename Real, int IK>
 hipError_t launch_bcg(int dir, bool fin, bool bcg, const void* args, hipStream_t s) {
-    return bcg ? launch_dir<NDIM, R, Real, PM, true>(dir, fin, args, s)
-               : launch_dir<NDIM, R, Real, PM, false>(dir, fin, args, s);
+    return bcg ? launch_dir<NDIM, R, Real, IK, true>(dir, fin, args, s)
+               : launch_dir<NDIM, R, Real, IK, false>(dir, fin, args, s);
 }
 
-// Per-sub-stencil indicator factors (Jiang-Shu) exist for R = 1, 2 only.
-template <int NDIM, typename Real>
-hipError_t launch_r(int dir, int R, bool fin, bool pm, bool bcg, const void* args, hipStream_t s) {
-    if (pm) {
-        switch (R) {
-            case 1: return launch_bcg<NDIM, 1, Real, true>(dir, fin, bcg, args, s);
-            case 2: return launch_bcg<NDIM, 2, Real, true>(dir, fin, bcg, args, s);
-            default: return hipErrorInvalidValue;
-        }
-    }
+// Indicator kinds: 0 for R = 1..3, 1 (Jiang-Shu) for R = 1, 2, 2 for R = 1..3.
+template <int NDIM, typename Real, int IK>
+hipError_t launch_rk(int dir, int R, bool fin, bool bcg, const void* args, hipStream_t s) {
     switch (R) {
-        case 1: return launch_bcg<NDIM, 1, Real, false>(dir, fin, bcg, args, s);
-        case 2: return launch_bcg<NDIM, 2, Real, false>(dir, fin, bcg, args, s);
-        case 3: return launch_bcg<NDIM, 3, Real, false>(dir, fin, bcg, args, s);
+        case 1: return launch_bcg<NDIM, 1, Real, IK>(dir, fin, bcg, args, s);
+        case 2: return launch_bcg<NDIM, 2, Real, IK>(dir, fin, bcg, args, s);
+        case 3:
+            if constexpr (IK != 1) return launch_bcg<NDIM, 3, Real, IK>(dir, fin, bcg, args, s);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int NDIM, typename Real>
+hipError_t launch_r(int dir, int R, bool fin, int ik, bool bcg, const void* args, hipStream_t s) {
+    switch (ik) {
+        case 0: return launch_rk<NDIM, Real, 0>(dir, R, fin, bcg, args, s);
+        case 1: return launch_rk<NDIM, Real, 1>(dir, R, fin, bcg, args, s);
+        case 2: return launch_rk<NDIM, Real, 2>(dir, R, fin, bcg, args, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename Real>
-hipError_t launch_nd(int ndim, int dir, int R, bool fin, bool pm, bool bcg, const void* args, hipStream_t s) {
+hipError_t launch_nd(int ndim, int dir, int R, bool fin, int ik, bool bcg, const void* args, hipStream_t s) {
     switch (ndim) {
-        case 1: return launch_r<1, Real>(dir, R, fin, pm, bcg, args, s);
-        case 2: return launch_r<2, Real>(dir, R, fin, pm, bcg, args, s);
-        case 3: return launch_r<3, Real>(dir, R, fin, pm, bcg, args, s);
+        case 1: return launch_r<1, Real>(dir, R, fin, ik, bcg, args, s);
+        case 2: return launch_r<2, Real>(dir, R, fin, ik, bcg, args, s);
+        case 3: return launch_r<3, Real>(dir, R, fin, ik, bcg, args, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, bool pm, bool bcg, const void* args,
+hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, int ik, bool bcg, const void* args,
                         hipStream_t s) {
-    return fp32 ? launch_nd<float>(ndim, dir, R, fin, pm, bcg, args, s)
-                : launch_nd<double>(ndim, dir, R, fin, pm, bcg, args, s);
+    return fp32 ? launch_nd<float>(ndim, dir, R, fin, ik, bcg, args, s)
+                : launch_nd<double>(ndim, dir, R, fin, ik, bcg, args, s);
 }
 
 // ---- batched launches --------------------------------------------------------
@@ -898,69 +910,74 @@ long long sweep_blocks(int ndim, int dir, const int n[3], int nseg) {
     return groups * nseg;
 }
 
-template <int NDIM, int DIR, int R, typename Real, bool FIN, bool PM, bool BCG>
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
 hipError_t launch_batch_one(const void* args, long long blocks, hipStream_t s) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     const BatchArgs<Real>& a = *static_cast<const BatchArgs<Real>*>(args);
     if (blocks <= 0 || blocks > INT_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sweep_batch_kernel<NDIM, DIR, R, Real, FIN, PM, BCG>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
+    hipLaunchKernelGGL((sweep_batch_kernel<NDIM, DIR, R, Real, FIN, IK, BCG>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
                        a);
     return hipGetLastError();
 }
 
-template <int NDIM, int R, typename Real, bool PM, bool BCG>
+template <int NDIM, int R, typename Real, int IK, bool BCG>
 hipError_t launch_batch_dir(int dir, bool fin, const void* args, long long blocks, hipStream_t s) {
     if (fin) {
         if (dir != NDIM - 1) return hipErrorInvalidValue;
-        return launch_batch_one<NDIM, NDIM - 1, R, Real, true, PM, BCG>(args, blocks, s);
+        return launch_batch_one<NDIM, NDIM - 1, R, Real, true, IK, BCG>(args, blocks, s);
     }
-    if (dir == 0) return launch_batch_one<NDIM, 0, R, Real, false, PM, BCG>(args, blocks, s);
+    if (dir == 0) return launch_batch_one<NDIM, 0, R, Real, false, IK, BCG>(args, blocks, s);
     if (NDIM >= 2 && dir == 1)
-        return launch_batch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false, PM, BCG>(args, blocks, s);
+        return launch_batch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false, IK, BCG>(args, blocks, s);
     if (NDIM == 3 && dir == 2)
-        return launch_batch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false, PM, BCG>(args, blocks, s);
+        return launch_batch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false, IK, BCG>(args, blocks, s);
     return hipErrorInvalidValue;
 }
 
-template <int NDIM, int R, typename Real, bool PM>
+template <int NDIM, int R, typename Real, int IK>
 hipError_t launch_batch_bcg(int dir, bool fin, bool bcg, const void* args, long long blocks, hipStream_t s) {
-    return bcg ? launch_batch_dir<NDIM, R, Real, PM, true>(dir, fin, args, blocks, s)
-               : launch_batch_dir<NDIM, R, Real, PM, false>(dir, fin, args, blocks, s);
+    return bcg ? launch_batch_dir<NDIM, R, Real, IK, true>(dir, fin, args, blocks, s)
+               : launch_batch_dir<NDIM, R, Real, IK, false>(dir, fin, args, blocks, s);
+}
+
+template <int NDIM, typename Real, int IK>
+hipError_t launch_batch_rk(int dir, int R, bool fin, bool bcg, const void* args, long long blocks, hipStream_t s) {
+    switch (R) {
+        case 1: return launch_batch_bcg<NDIM, 1, Real, IK>(dir, fin, bcg, args, blocks, s);
+        case 2: return launch_batch_bcg<NDIM, 2, Real, IK>(dir, fin, bcg, args, blocks, s);
+        case 3:
+            if constexpr (IK != 1) return launch_batch_bcg<NDIM, 3, Real, IK>(dir, fin, bcg, args, blocks, s);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int NDIM, typename Real>
-hipError_t launch_batch_r(int dir, int R, bool fin, bool pm, bool bcg, const void* args, long long blocks,
+hipError_t launch_batch_r(int dir, int R, bool fin, int ik, bool bcg, const void* args, long long blocks,
                           hipStream_t s) {
-    if (pm) {
-        switch (R) {
-            case 1: return launch_batch_bcg<NDIM, 1, Real, true>(dir, fin, bcg, args, blocks, s);
-            case 2: return launch_batch_bcg<NDIM, 2, Real, true>(dir, fin, bcg, args, blocks, s);
-            default: return hipErrorInvalidValue;
-        }
-    }
-    switch (R) {
-        case 1: return launch_batch_bcg<NDIM, 1, Real, false>(dir, fin, bcg, args, blocks, s);
-        case 2: return launch_batch_bcg<NDIM, 2, Real, false>(dir, fin, bcg, args, blocks, s);
-        case 3: return launch_batch_bcg<NDIM, 3, Real, false>(dir, fin, bcg, args, blocks, s);
+    switch (ik) {
+        case 0: return launch_batch_rk<NDIM, Real, 0>(dir, R, fin, bcg, args, blocks, s);
+        case 1: return launch_batch_rk<NDIM, Real, 1>(dir, R, fin, bcg, args, blocks, s);
+        case 2: return launch_batch_rk<NDIM, Real, 2>(dir, R, fin, bcg, args, blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename Real>
-hipError_t launch_batch_nd(int ndim, int dir, int R, bool fin, bool pm, bool bcg, const void* args, long long blocks,
+hipError_t launch_batch_nd(int ndim, int dir, int R, bool fin, int ik, bool bcg, const void* args, long long blocks,
                            hipStream_t s) {
     switch (ndim) {
-        case 1: return launch_batch_r<1, Real>(dir, R, fin, pm, bcg, args, blocks, s);
-        case 2: return launch_batch_r<2, Real>(dir, R, fin, pm, bcg, args, blocks, s);
-        case 3: return launch_batch_r<3, Real>(dir, R, fin, pm, bcg, args, blocks, s);
+        case 1: return launch_batch_r<1, Real>(dir, R, fin, ik, bcg, args, blocks, s);
+        case 2: return launch_batch_r<2, Real>(dir, R, fin, ik, bcg, args, blocks, s);
+        case 3: return launch_batch_r<3, Real>(dir, R, fin, ik, bcg, args, blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, bool pm, bool bcg, const void* args,
+hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, int ik, bool bcg, const void* args,
                               long long blocks, hipStream_t s) {
-    return fp32 ? launch_batch_nd<float>(ndim, dir, R, fin, pm, bcg, args, blocks, s)
-                : launch_batch_nd<double>(ndim, dir, R, fin, pm, bcg, args, blocks, s);
+    return fp32 ? launch_batch_nd<float>(ndim, dir, R, fin, ik, bcg, args, blocks, s)
+                : launch_batch_nd<double>(ndim, dir, R, fin, ik, bcg, args, blocks, s);
 }
 
 // Copies the step state of every problem of a batch into a compact array.
