@@ -294,7 +294,9 @@ def main():
             e1.synchronize()
             d = k % grid.ndim
             fin = d == grid.ndim - 1
-            sym = f"sweep_kernel<{grid.ndim}, {d}, {R}, {real}, {'true' if fin else 'false'}>"
+            # template arguments: ndim, dir, R, real type, finishes the stage,
+            # indicator kind (0: GP), general boundaries (periodic: false)
+            sym = f"sweep_kernel<{grid.ndim}, {d}, {R}, {real}, {'true' if fin else 'false'}, 0, false>"
             tk = e0.elapsed_time(e1) / args.kernel_reps * 1e-3
             per_sym.setdefault(sym, []).append(tk)
             log(f"  launch {k} (stage {k // grid.ndim + 1}, dir {d}): {tk * 1e6:.1f} us")

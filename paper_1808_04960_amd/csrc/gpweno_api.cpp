@@ -427,10 +427,18 @@ int gpweno_run(gpweno_ctx* c, double t_final, long max_steps, long* nsteps_out, 
     hipError_t e = gpw::launch_set_run(c->d_ctl, t_final, limit, s);
     if (e != hipSuccess) return fail(c, GPWENO_EHIP, "set_run launch: %s", hipGetErrorString(e));
     while (gpw::current_rec(*c->h_ctl).t < t_final && gpw::current_rec(*c->h_ctl).nsteps < limit) {
+        const gpw::StepRec before = gpw::current_rec(*c->h_ctl);
         if ((st = ensure_graph(c))) return st;
         HIP_TRY(c, hipGraphLaunch(c->graph, s));
         if ((st = read_ctl(c, s))) return st;
         if ((st = check_err(c))) break;
+        // a replay that moves neither the step count nor the time cannot finish
+        const gpw::StepRec& after = gpw::current_rec(*c->h_ctl);
+        if (after.nsteps == before.nsteps || !(after.t > before.t)) {
+            st = fail(c, GPWENO_ESTATE, "run stalled at step %lld, t = %.17g (time step %.3g)", after.nsteps, after.t,
+                      after.dt);
+            break;
+        }
     }
     if (nsteps_out) *nsteps_out = (long)(gpw::current_rec(*c->h_ctl).nsteps - start);
     if (t_out) *t_out = gpw::current_rec(*c->h_ctl).t;

@@ -113,29 +113,47 @@ __device__ __forceinline__ int ghost_src(int x, int n, int lo, int hi, bool& fli
 }
 
 // Time step of the step in flight and whether it runs. final_sweep: the
-// sweep that closes the step (its block 0 writes the next step state).
+// sweep that closes the step (its block 0 writes the next step state). Only
+// sweeps that finish an RK stage need dt (NEED_DT); the others read no speeds.
+// Every field is read up front, with no address depending on another read, so
+// the control block costs one round trip of scalar loads.
+template <bool NEED_DT>
 __device__ __forceinline__ bool step_go(const Ctl* c, bool final_sweep, double& t0, double& dt, long long& n) {
-    const bool newer0 = c->rec[0].nsteps > c->rec[1].nsteps;
+    const long long n0 = c->rec[0].nsteps, n1 = c->rec[1].nsteps;
+    const double ta = c->rec[0].t, tb = c->rec[1].t;
+    const long long st = c->started;
+    const int err = c->err;
+    const double tf = c->t_final;
+    const long long lim = c->step_limit;
+    unsigned long long s0 = 0, s1 = 0;
+    double fixed = 0.0, cfl = 0.0;
+    if (NEED_DT) {
+        fixed = c->fixed_dt;
+        cfl = c->cfl;
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            const unsigned long long a0 = c->xcd[x].speed[0], a1 = c->xcd[x].speed[1];
+            s0 = a0 > s0 ? a0 : s0;
+            s1 = a1 > s1 ? a1 : s1;
+        }
+    }
     int r;
     if (final_sweep) {
-        const long long st = c->started;
         if (st < 0) return false;
-        r = (c->rec[0].nsteps == st) ? 0 : 1;
-        if (c->rec[r].nsteps != st) return false;
+        r = (n0 == st) ? 0 : 1;
+        if ((r ? n1 : n0) != st) return false;
     } else {
-        r = newer0 ? 0 : 1;
+        r = n0 > n1 ? 0 : 1;
     }
-    t0 = c->rec[r].t;
-    n = c->rec[r].nsteps;
-    if (c->err || !(t0 < c->t_final) || n >= c->step_limit) return false;
-    const int par = (int)(n & 1);
-    unsigned long long sb = c->xcd[0].speed[par];
-#pragma unroll
-    for (int x = 1; x < 8; ++x) sb = c->xcd[x].speed[par] > sb ? c->xcd[x].speed[par] : sb;
-    const double speed = __longlong_as_double((long long)sb);
-    double d = c->fixed_dt > 0.0 ? c->fixed_dt : c->cfl / speed;
-    if (t0 + d > c->t_final) d = c->t_final - t0;
-    dt = d;
+    t0 = r ? tb : ta;
+    n = r ? n1 : n0;
+    if (err || !(t0 < tf) || n >= lim) return false;
+    if (NEED_DT) {
+        const double speed = __longlong_as_double((long long)((n & 1) ? s1 : s0));
+        double d = fixed > 0.0 ? fixed : cfl / speed;
+        if (t0 + d > tf) d = tf - t0;
+        dt = d;
+    }
     return true;
 }
 
@@ -458,7 +476,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     double t0 = 0.0, dt = 0.0;
     long long nstep = 0;
     if (a.stage > 0) {
-        const bool go = step_go(a.ctl, FIN && a.stage == 3, t0, dt, nstep);
+        const bool go = step_go<FIN>(a.ctl, FIN && a.stage == 3, t0, dt, nstep);
         if (a.step_start && L == 0 && threadIdx.x == 0) {
             // mark the step as running (or not) and clear the next speed slot
             a.ctl->started = go ? nstep : -1;
@@ -598,6 +616,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
             }
         }
     }
+
     __syncthreads();
 
     // ---- per-lane reconstruction, face flux, correction, difference ----------
