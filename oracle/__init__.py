@@ -17,7 +17,7 @@ import subprocess
 
 import numpy as np
 
-from .tables import SCHEMES, gp_tables, scheme_tables  # noqa: F401
+from .tables import SCHEMES, gp_ao_tables, gp_tables, scheme_tables  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gpweno_oracle.c")
@@ -52,6 +52,15 @@ class Cfg(ctypes.Structure):
         ("B", ctypes.c_double * 192),
         ("bc", ctypes.c_int * 6),
         ("nonzero_mean", ctypes.c_int),
+        ("ao", ctypes.c_int),
+        ("ao_w7", ctypes.c_double * 42),
+        ("ao_w5", ctypes.c_double * 30),
+        ("ao_w3", ctypes.c_double * 54),
+        ("ao_P7", ctypes.c_double * 147),
+        ("ao_P5", ctypes.c_double * 75),
+        ("ao_P3", ctypes.c_double * 27),
+        ("ao_c", ctypes.c_double * 9),
+        ("ao_gam", ctypes.c_double * 4),
     ]
 
 
@@ -83,6 +92,12 @@ def lib():
         L.oracle_gp_weno.restype = None
         L.oracle_gp_weno.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int, _dp, _dp, _dp,
                                      _dp, _dp]
+        L.oracle_gp_ao.restype = None
+        L.oracle_gp_ao.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+        L.oracle_ao_hybrid.restype = ctypes.c_double
+        L.oracle_ao_hybrid.argtypes = [ctypes.c_double, ctypes.c_double, _dp, _dp, _dp]
+        L.oracle_ao_recursive.restype = ctypes.c_double
+        L.oracle_ao_recursive.argtypes = [ctypes.c_double] * 5
         L.oracle_hllc.restype = None
         L.oracle_hllc.argtypes = [_dp, _dp, ctypes.c_double, _dp]
         L.oracle_flux_hat.restype = ctypes.c_double
@@ -130,6 +145,35 @@ def gp_weno(f, tab, nonzero_mean=False):
                          1 if nonzero_mean else 0, ctypes.byref(qp), ctypes.byref(qm), _ptr(beta), _ptr(omp),
                          _ptr(omm))
     return qp.value, qm.value, beta[: R + 1], omp[: R + 1], omm[: R + 1]
+
+
+def gp_ao(f, tab, side):
+    """GP-AO interpolation of one variable (App. A): f has 7 entries (GP-AO(3,2,3))
+    or 5 (GP-AO(2,3)); side 0 is x_* = +1/2, side 1 is x_* = -1/2. ``tab`` is
+    ``gp_ao_tables``. Returns (q, beta) with beta = (beta^7, beta^5, beta_1..3)."""
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    R = (len(f) - 1) // 2
+    key = "+" if side == 0 else "-"
+    arrs = [np.ascontiguousarray(tab[k], dtype=np.float64) for k in
+            ("w7" + key, "w5" + key, "w3" + key, "P7", "P5", "P3")]
+    cN = np.array([tab["c7"], tab["c5"], tab["c3"]])
+    gam = np.array(list(tab["gamma"]) + [tab["gamma_hi"]])
+    q = ctypes.c_double()
+    beta = np.zeros(5)
+    lib().oracle_gp_ao(R, _ptr(f), *[_ptr(a) for a in arrs], _ptr(cN), _ptr(gam), ctypes.byref(q), _ptr(beta))
+    return q.value, beta
+
+
+def ao_hybrid(qR, bR, qm, bm, gam, g_hi):
+    """Eq. (GP-AO) with its weights (Eq. (nonlin-AO)) from given indicators."""
+    qm, bm = np.ascontiguousarray(qm, dtype=np.float64), np.ascontiguousarray(bm, dtype=np.float64)
+    g = np.array(list(gam) + [g_hi], dtype=np.float64)
+    return lib().oracle_ao_hybrid(qR, bR, _ptr(qm), _ptr(bm), _ptr(g))
+
+
+def ao_recursive(ao_hi, b_hi, ao_lo, b_lo, g_hi):
+    """Eq. (AO-recursive) with the weights of Eq. (recursive-weights)."""
+    return lib().oracle_ao_recursive(ao_hi, b_hi, ao_lo, b_lo, g_hi)
 
 
 def hllc(qL, qR, gamma):
@@ -193,7 +237,31 @@ class OracleSolver:
             c.bc[2 * d] = lo_bc
             c.bc[2 * d + 1] = hi_bc
         self.tables = []
-        for d in range(grid.ndim):
+        if scheme == "gp-ao":
+            if R not in (2, 3):
+                raise ValueError("GP-AO needs R = 2 (GP-AO(2,3)) or 3 (GP-AO(3,2,3))")
+            c.ao = 1
+            for d in range(grid.ndim):
+                t = gp_ao_tables(ell / grid.dx[d], sigma / grid.dx[d])
+                self.tables.append(t)
+                for side, key in enumerate("+-"):
+                    for j in range(7):
+                        c.ao_w7[14 * d + 7 * side + j] = t["w7" + key][j]
+                    for j in range(5):
+                        c.ao_w5[10 * d + 5 * side + j] = t["w5" + key][j]
+                    for m in range(3):
+                        for j in range(3):
+                            c.ao_w3[18 * d + 9 * side + 3 * m + j] = t["w3" + key][m, j]
+                for N, arr in ((7, c.ao_P7), (5, c.ao_P5), (3, c.ao_P3)):
+                    for i in range(N):
+                        for j in range(N):
+                            arr[N * N * d + N * i + j] = t[f"P{N}"][i, j]
+                for k, N in enumerate((7, 5, 3)):
+                    c.ao_c[3 * d + k] = t[f"c{N}"]
+            for m in range(3):
+                c.ao_gam[m] = t["gamma"][m]
+            c.ao_gam[3] = t["gamma_hi"]
+        for d in range(grid.ndim if scheme != "gp-ao" else 0):
             t = scheme_tables(scheme, R, ell / grid.dx[d], sigma / grid.dx[d])
             self.tables.append(t)
             c.beta_form = 1 if t["beta_form"] == "B" else 0

@@ -66,6 +66,17 @@ typedef struct {
     int bc[3][2];           /* boundary kind per axis and side (0 low, 1 high):
                                0 periodic, 1 outflow, 2 reflecting wall */
     int nonzero_mean;       /* 1: GP indicators of f_m - f_i (centre-cell mean, Sec. 7) */
+    /* adaptive-order GP (App. A); used when ao = 1: R = 3 gives GP-AO(3,2,3),
+     * R = 2 gives GP-AO(2,3). side 0 is x_* = +1/2, side 1 is x_* = -1/2. */
+    int ao;
+    double ao_w7[3][2][7];      /* GP weights, 7-point stencil */
+    double ao_w5[3][2][5];      /* GP weights, 5-point stencil */
+    double ao_w3[3][2][3][3];   /* GP weights of the 3-point sub-stencils [m][j] */
+    double ao_P7[3][7][7];      /* rows v_i / sqrt(lambda_i) of K_7(sigma) */
+    double ao_P5[3][5][5];
+    double ao_P3[3][3][3];
+    double ao_c[3][3];          /* N/2 log 2pi + 1/2 log det K_N(sigma), N = 7, 5, 3 */
+    double ao_gam[4];           /* CWENO linear weights gamma_1..3, then gamma_HI */
 } oracle_cfg;
 
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
@@ -139,6 +150,95 @@ static void phys_flux(const double *q, double gamma, double *F, double *Ucons) {
         Ucons[3] = rho * t2;
         Ucons[4] = E;
     }
+}
+
+/* ---------------------------------------------------------------------------
+ * Adaptive-order GP interpolation (App. A) of one variable to x_{i+1/2}
+ * (side 0) or x_{i-1/2} (side 1), data f[0..2Rhi] = q_{i-Rhi} .. q_{i+Rhi},
+ * Rhi = 3 (GP-AO(3,2,3)) or 2 (GP-AO(2,3)).
+ *   smoothness indicators: the negative log-likelihood of Eq. (log-like) with
+ *     zero mean, keeping its normalisation and complexity terms because the
+ *     stencils differ in size: beta = c_N + 1/2 f^T K_N(sigma)^-1 f,
+ *     with f^T K^-1 f = sum_i (P_i . f)^2 (Eq. (beta-eigen));
+ *   GP-CWENO on the three 3-point sub-stencils of the 5-point stencil with the
+ *     linear weights of Eq. (CWENO-lin);
+ *   GP-AO(R,3), Eqs. (nonlin-AO), (GP-AO): weights gamma_HI/(eps+beta^R)^2 and
+ *     gamma_m/(eps+beta_m)^2 normalised together, then
+ *     q = omega^R/gamma_HI q^R + sum_m (omega_m - omega^R gamma_m/gamma_HI) q^m;
+ *   GP-AO(R',R,3), Eqs. (recursive-weights), (AO-recursive): weights
+ *     gamma_HI/(eps+beta^R')^2 and (1-gamma_HI)/(eps+beta^R)^2, normalised, then
+ *     q = nu^R'/gamma_HI q^AO(R',3) + (nu^R - nu^R'(1-gamma_HI)/gamma_HI) q^AO(R,3).
+ * Reading: the weights of the sub-stencils use gamma_m (the printed formula
+ * repeats gamma_HI there, which would remove the bias towards the centred
+ * stencil that the text describes).
+ * ------------------------------------------------------------------------- */
+static double quad_rows(int N, const double *P, const double *f) {
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) {
+        double pr = 0.0;
+        for (int j = 0; j < N; ++j) pr += P[N * i + j] * f[j];
+        s += pr * pr;
+    }
+    return s;
+}
+
+static double dot(int N, const double *w, const double *f) {
+    double s = 0.0;
+    for (int j = 0; j < N; ++j) s += w[j] * f[j];
+    return s;
+}
+
+/* GP-AO(R,3) from the high-order interpolation qR with indicator bR, and the
+ * sub-stencil interpolations qm[3] with indicators bm[3]; gam = gamma_1..3,
+ * gamma_HI (Eqs. (nonlin-AO), (GP-AO)). */
+double oracle_ao_hybrid(double qR, double bR, const double *qm, const double *bm, const double *gam) {
+    double ghi = gam[3];
+    double wR = ghi / ((EPS_WENO + bR) * (EPS_WENO + bR));
+    double wm[3], sum = wR;
+    for (int m = 0; m < 3; ++m) {
+        wm[m] = gam[m] / ((EPS_WENO + bm[m]) * (EPS_WENO + bm[m]));
+        sum += wm[m];
+    }
+    double oR = wR / sum;
+    double q = oR / ghi * qR;
+    for (int m = 0; m < 3; ++m) q += (wm[m] / sum - oR / ghi * gam[m]) * qm[m];
+    return q;
+}
+
+/* GP-AO(R',R,3) from GP-AO(R',3) and GP-AO(R,3) with the indicators of the
+ * stencils S_R' and S_R (Eqs. (recursive-weights), (AO-recursive)). */
+double oracle_ao_recursive(double aoHi, double bHi, double aoLo, double bLo, double ghi) {
+    double nh = ghi / ((EPS_WENO + bHi) * (EPS_WENO + bHi));
+    double nl = (1.0 - ghi) / ((EPS_WENO + bLo) * (EPS_WENO + bLo));
+    double nuH = nh / (nh + nl), nuL = nl / (nh + nl);
+    return nuH / ghi * aoHi + (nuL - nuH * (1.0 - ghi) / ghi) * aoLo;
+}
+
+void oracle_gp_ao(int Rhi, const double *f, const double *w7, const double *w5, const double *w3,
+                  const double *P7, const double *P5, const double *P3, const double *cN,
+                  const double *gam, double *q_out, double *beta_out) {
+    const double *f5 = f + (Rhi - 2);           /* the 5-point stencil, nodes -2..2 */
+    double b5 = cN[1] + 0.5 * quad_rows(5, P5, f5);
+    double bm[3], qm[3];
+    for (int m = 0; m < 3; ++m) {
+        bm[m] = cN[2] + 0.5 * quad_rows(3, P3, f5 + m);
+        qm[m] = dot(3, w3 + 3 * m, f5 + m);
+    }
+    double q5 = dot(5, w5, f5);
+    double ao5 = oracle_ao_hybrid(q5, b5, qm, bm, gam);
+    if (beta_out) {
+        beta_out[1] = b5;
+        for (int m = 0; m < 3; ++m) beta_out[2 + m] = bm[m];
+    }
+    if (Rhi == 2) {
+        *q_out = ao5;
+        return;
+    }
+    double b7 = cN[0] + 0.5 * quad_rows(7, P7, f);
+    double q7 = dot(7, w7, f);
+    double ao7 = oracle_ao_hybrid(q7, b7, qm, bm, gam);
+    if (beta_out) beta_out[0] = b7;
+    *q_out = oracle_ao_recursive(ao7, b7, ao5, b5, gam[3]);
 }
 
 /* ---------------------------------------------------------------------------
@@ -317,9 +417,16 @@ static int reconstruct_cell(const oracle_cfg *c, int d, const double (*qs)[5],
             for (int q = 0; q < 5; ++q) w += L[k][q] * qs[s][q];
             f[s] = w;
         }
-        oracle_gp_weno(R, f, &c->wp[d][0][0], &c->wm[d][0][0], c->gp[d], c->gm[d],
-                       &c->P[d][0][0], c->beta_form ? &c->B[d][0][0][0] : NULL, c->nonzero_mean,
-                       &Wp[k], &Wm[k], NULL, NULL, NULL);
+        if (c->ao) {
+            for (int side = 0; side < 2; ++side)
+                oracle_gp_ao(R, f, c->ao_w7[d][side], c->ao_w5[d][side], &c->ao_w3[d][side][0][0],
+                             &c->ao_P7[d][0][0], &c->ao_P5[d][0][0], &c->ao_P3[d][0][0], c->ao_c[d],
+                             c->ao_gam, side == 0 ? &Wp[k] : &Wm[k], NULL);
+        } else {
+            oracle_gp_weno(R, f, &c->wp[d][0][0], &c->wm[d][0][0], c->gp[d], c->gm[d],
+                           &c->P[d][0][0], c->beta_form ? &c->B[d][0][0][0] : NULL, c->nonzero_mean,
+                           &Wp[k], &Wm[k], NULL, NULL, NULL);
+        }
     }
     for (int q = 0; q < 5; ++q) {
         double ap = 0.0, am = 0.0;

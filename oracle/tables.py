@@ -293,3 +293,63 @@ def scheme_tables(scheme: str, R: int, ell_over_dx: float, sigma_over_dx: float,
             for j in range(R + 1):
                 t["P"][i, j] = float(P[i][j])
     return t
+
+
+# ----------------------------------------------------------------------------
+# Adaptive-order GP (the paper's Appendix A): GP-AO(R,3) and GP-AO(R',R,3).
+# ----------------------------------------------------------------------------
+GAMMA_HI = 0.85   # the constants of Eq. (CWENO-lin), "typically" 0.85 (App. A)
+GAMMA_LO = 0.85
+
+
+def cweno_linear_weights(g_hi=GAMMA_HI, g_lo=GAMMA_LO):
+    """gamma_1 = gamma_3 = (1 - g_hi)(1 - g_lo)/2, gamma_2 = (1 - g_hi) g_lo (Eq. (CWENO-lin))."""
+    return [(1 - g_hi) * (1 - g_lo) / 2, (1 - g_hi) * g_lo, (1 - g_hi) * (1 - g_lo) / 2]
+
+
+@functools.lru_cache(maxsize=64)
+def gp_ao_tables_mp(ell: str, sigma: str, dps: int = DEFAULT_DPS):
+    """Tables of GP-AO, in units of dx, for the stencils of radius 3, 2 and the
+    three 3-point sub-stencils of the radius-2 stencil (App. A, Eq. (cweno_stencil)).
+
+      'w7+','w7-' : GP weights of the 7-point stencil (nodes -3..3) at x_* = +-1/2
+                    (Eq. (q-intrp), length scale ell);
+      'w5+','w5-' : the same on the 5-point stencil (nodes -2..2);
+      'w3+','w3-' : [m][j] GP weights of the sub-stencils m = 0, 1, 2 (nodes m-2..m);
+      'P7','P5','P3' : rows v_i / sqrt(lambda_i) of K_N(sigma), N = 7, 5, 3, so that
+                    f^T K_N^-1 f = sum_i (P_i . f)^2 (Eq. (beta-eigen));
+      'c7','c5','c3' : N/2 log(2 pi) + 1/2 log det K_N(sigma), the normalisation and
+                    complexity terms of the negative log-likelihood (Eq. (log-like)).
+    """
+    with mp.workdps(dps):
+        ellm, sigm = mp.mpf(ell), mp.mpf(sigma)
+        out = {}
+        for N, R in ((7, 3), (5, 2)):
+            nodes = [mp.mpf(j) for j in range(-R, R + 1)]
+            K = _kernel_matrix(nodes, ellm)
+            for sign, key in ((1, "+"), (-1, "-")):
+                out[f"w{N}{key}"] = list(mp.lu_solve(K, _kstar(nodes, mp.mpf(sign) / 2, ellm)))
+        nodes5 = [mp.mpf(j) for j in range(-2, 3)]
+        for sign, key in ((1, "+"), (-1, "-")):
+            xs = mp.mpf(sign) / 2
+            out["w3" + key] = [list(mp.lu_solve(_kernel_matrix(nodes5[m:m + 3], ellm), _kstar(nodes5[m:m + 3], xs, ellm)))
+                               for m in range(3)]
+        for N in (7, 5, 3):
+            nodes = [mp.mpf(j) for j in range(N)]
+            Ks = _kernel_matrix(nodes, sigm)
+            lam, Q = mp.eigsy(Ks)
+            out[f"P{N}"] = [[Q[j, i] / mp.sqrt(lam[i]) for j in range(N)] for i in range(N)]
+            out[f"c{N}"] = mp.mpf(N) / 2 * mp.log(2 * mp.pi) + sum(mp.log(l) for l in lam) / 2
+        return out
+
+
+def gp_ao_tables(ell_over_dx: float, sigma_over_dx: float, dps: int = DEFAULT_DPS):
+    """Float64 arrays of gp_ao_tables_mp, plus the CWENO linear weights and gamma_HI."""
+    t = gp_ao_tables_mp(_dec(ell_over_dx), _dec(sigma_over_dx), dps)
+    f = lambda v: np.array(v, dtype=float) if not isinstance(v, list) else np.array([[float(x) for x in r] if isinstance(r, list) else float(r) for r in v])  # noqa: E731
+    out = {k: f(v) for k, v in t.items() if not k.startswith("c")}
+    for N in (7, 5, 3):
+        out[f"c{N}"] = float(t[f"c{N}"])
+    out["gamma"] = np.array(cweno_linear_weights())
+    out["gamma_hi"] = GAMMA_HI
+    return out
