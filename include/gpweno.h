@@ -86,7 +86,14 @@ typedef struct {
 typedef enum {
     GPWENO_GP_WENO = 0,    /* GP weights, GP linear weights, GP indicators (R = 1..3) */
     GPWENO_WENO_JS = 1,    /* polynomial weights, Jiang-Shu indicators (R = 1, 2) */
-    GPWENO_WENO_GP = 2     /* polynomial weights, GP indicators with sigma (R = 1..3) */
+    GPWENO_WENO_GP = 2,    /* polynomial weights, GP indicators with sigma (R = 1..3) */
+    GPWENO_GP_AO = 3       /* adaptive-order GP of App. A: R = 3 is GP-AO(3,2,3), R = 2 is
+                              GP-AO(2,3). GP-CWENO on the 3-point sub-stencils (linear
+                              weights of Eq. (CWENO-lin), gamma_HI = gamma_LO = 0.85)
+                              hybridised with the 5- and 7-point GP interpolations
+                              (Eqs. (nonlin-AO), (GP-AO), (AO-recursive)); indicators
+                              are the full negative log-likelihood of Eq. (log-like)
+                              with K_N(sigma). The paper uses sigma/dx = 1.8 with it. */
 } gpweno_scheme;
 
 typedef struct {
@@ -210,6 +217,15 @@ int gpweno_conserved_sums(gpweno_ctx *ctx, double *out);
 int gpweno_compute_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx,
                           double *w_plus, double *w_minus, double *gam_plus,
                           double *gam_minus, double *P);
+
+/* Host-only: the extra tables of GPWENO_GP_AO for length scales in units of dx.
+ * w7[2][7] and w5[2][5]: GP weights of the 7- and 5-point stencils (nodes -3..3,
+ * -2..2) at x_* = +1/2 (row 0) and -1/2 (row 1), Eq. (q-intrp); P7[7][7],
+ * P5[5][5], P3[3][3]: rows v_i / sqrt(lambda_i) of K_N(sigma); c[3]: for N = 7,
+ * 5, 3, N/2 log(2 pi) + 1/2 log det K_N(sigma) (Eq. (log-like)). Any output may
+ * be NULL. Errors: EINVAL. */
+int gpweno_compute_ao_tables(double ell_over_dx, double sigma_over_dx, double *w7, double *w5,
+                             double *P7, double *P5, double *P3, double *c);
 
 /* Sets the end time and the absolute step limit (step_limit < 0: none) of the
  * context's runs without stepping (enqueued). gpweno_batch_run honours them;

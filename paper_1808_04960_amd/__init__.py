@@ -75,6 +75,7 @@ def lib():
         L.gpweno_conserved_sums.argtypes = [vp, _dp]
         L.gpweno_compute_tables.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp,
                                             _dp, _dp, _dp]
+        L.gpweno_compute_ao_tables.argtypes = [ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp]
         L.gpweno_set_end.argtypes = [vp, ctypes.c_double, ctypes.c_long]
         L.gpweno_batch_create.argtypes = [ctypes.POINTER(vp)]
         L.gpweno_batch_set.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, vp]
@@ -107,7 +108,7 @@ def _check(code, ctx=None):
         raise GpwenoError(code, msg)
 
 
-SCHEMES = {"gp-weno": 0, "weno-js": 1, "weno-gp": 2}   # gpweno_scheme
+SCHEMES = {"gp-weno": 0, "weno-js": 1, "weno-gp": 2, "gp-ao": 3}   # gpweno_scheme
 
 
 def _scheme_id(scheme):
@@ -125,6 +126,18 @@ def compute_tables(R, ell_over_dx, sigma_over_dx, scheme="gp-weno"):
     _check(lib().gpweno_compute_tables(_scheme_id(scheme), R, ell_over_dx, sigma_over_dx, ptr(wp), ptr(wm),
                                        ptr(gp), ptr(gm), ptr(P)))
     return {"w+": wp, "w-": wm, "gamma+": gp, "gamma-": gm, "P": P}
+
+
+def compute_ao_tables(ell_over_dx, sigma_over_dx):
+    """Host-only extra tables of the adaptive-order GP scheme (binary128 rounded
+    to float64): 'w7' (2, 7), 'w5' (2, 5) (rows: x_* = +1/2, -1/2), 'P7', 'P5',
+    'P3', and 'c' = (c7, c5, c3)."""
+    out = {"w7": np.zeros((2, 7)), "w5": np.zeros((2, 5)), "P7": np.zeros((7, 7)), "P5": np.zeros((5, 5)),
+           "P3": np.zeros((3, 3)), "c": np.zeros(3)}
+    ptr = lambda a: a.ctypes.data_as(_dp)  # noqa: E731
+    _check(lib().gpweno_compute_ao_tables(ell_over_dx, sigma_over_dx, *[ptr(out[k]) for k in
+                                                                         ("w7", "w5", "P7", "P5", "P3", "c")]))
+    return out
 
 
 def make_grid(grid):

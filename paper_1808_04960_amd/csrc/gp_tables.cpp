@@ -105,9 +105,10 @@ bool householder_lsq(int m, int n, q128 A[NMAX][NMAX], q128 *b, q128 *x) {
     return true;
 }
 
-// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (n <= 4).
+// Cyclic Jacobi eigen-decomposition of a symmetric n x n matrix (n <= M).
 // On return A's diagonal holds the eigenvalues and V's columns the eigenvectors.
-void jacobi_eigen(int n, q128 A[4][4], q128 V[4][4]) {
+template <int M>
+void jacobi_eigen(int n, q128 (&A)[M][M], q128 (&V)[M][M]) {
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) V[i][j] = (i == j) ? 1 : 0;
     for (int sweep = 0; sweep < 100; ++sweep) {
@@ -251,7 +252,59 @@ void js_form(int R, int m, q128 B[4][4]) {
     }
 }
 
+// GP weights of the whole stencil of radius R at x_* (Eq. (q-intrp)).
+bool full_weights(int R, q128 ell, q128 xstar, q128 *w) {
+    const int n = 2 * R + 1;
+    q128 K[NMAX][NMAX], ks[NMAX];
+    for (int i = 0; i < n; ++i) {
+        ks[i] = se_kernel(xstar, (q128)(i - R), ell);
+        for (int j = 0; j < n; ++j) K[i][j] = se_kernel((q128)(i - R), (q128)(j - R), ell);
+    }
+    return cholesky_solve(n, K, ks, w);
+}
+
+// Rows v_i / sqrt(lambda_i) of K_N(sigma) on N consecutive nodes, and
+// N/2 log(2 pi) + 1/2 log det K_N(sigma) (the sum of the log eigenvalues).
+bool kernel_rows(int N, q128 sig, double *P /* [N][N] */, double *cN) {
+    q128 A[NMAX][NMAX] = {}, V[NMAX][NMAX] = {};
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) A[i][j] = se_kernel((q128)i, (q128)j, sig);
+    jacobi_eigen(N, A, V);
+    q128 logdet = 0;
+    for (int i = 0; i < N; ++i) {
+        const q128 lam = A[i][i];
+        if (!(lam > 0)) return false;
+        logdet += logq(lam);
+        const q128 inv = 1 / sqrtq(lam);
+        for (int j = 0; j < N; ++j) P[N * i + j] = (double)(V[j][i] * inv);
+    }
+    const q128 pi = 4 * atanq((q128)1);
+    *cN = (double)((q128)N / 2 * logq(2 * pi) + logdet / 2);
+    return true;
+}
+
 }  // namespace
+
+int gpw_build_ao_tables(double ell_over_dx, double sigma_over_dx, GpAoTablesF64 *out) {
+    if (!(ell_over_dx > 0) || !(sigma_over_dx > 0) || !out) return -1;
+    std::memset(out, 0, sizeof(*out));
+    const q128 ell = (q128)ell_over_dx, sig = (q128)sigma_over_dx;
+    q128 w7p[NMAX], w7m[NMAX], w5p[NMAX], w5m[NMAX];
+    if (!full_weights(3, ell, (q128)0.5, w7p) || !full_weights(3, ell, (q128)-0.5, w7m)) return -2;
+    if (!full_weights(2, ell, (q128)0.5, w5p) || !full_weights(2, ell, (q128)-0.5, w5m)) return -2;
+    for (int j = 0; j < 7; ++j) {
+        out->w7_plus[j] = (double)w7p[j];
+        out->w7_minus[j] = (double)w7m[j];
+    }
+    for (int j = 0; j < 5; ++j) {
+        out->w5_plus[j] = (double)w5p[j];
+        out->w5_minus[j] = (double)w5m[j];
+    }
+    if (!kernel_rows(7, sig, &out->P7[0][0], &out->c[0])) return -3;
+    if (!kernel_rows(5, sig, &out->P5[0][0], &out->c[1])) return -3;
+    if (!kernel_rows(3, sig, &out->P3[0][0], &out->c[2])) return -3;
+    return 0;
+}
 
 int gpw_build_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx, GpTablesF64 *out) {
     if (R < 1 || R > 3 || !(ell_over_dx > 0) || !(sigma_over_dx > 0) || !out) return -1;

@@ -10,7 +10,20 @@ struct GpTablesF64 {
 };
 
 // Interpolation schemes (values of gpweno_scheme).
-enum { GPW_SCHEME_GP_WENO = 0, GPW_SCHEME_WENO_JS = 1, GPW_SCHEME_WENO_GP = 2 };
+enum { GPW_SCHEME_GP_WENO = 0, GPW_SCHEME_WENO_JS = 1, GPW_SCHEME_WENO_GP = 2, GPW_SCHEME_GP_AO = 3 };
+
+// Extra tables of the adaptive-order GP interpolation (App. A of the paper):
+// whole-stencil GP weights of radius 3 and 2, and for K_N(sigma), N = 7, 5, 3,
+// the rows v_i / sqrt(lambda_i) and the constant N/2 log(2 pi) + 1/2 log det.
+// The 3-point sub-stencil weights are GpTablesF64::w_plus / w_minus of R = 2.
+struct GpAoTablesF64 {
+    double w7_plus[7], w7_minus[7];
+    double w5_plus[5], w5_minus[5];
+    double P7[7][7], P5[5][5], P3[3][3];
+    double c[3];           // N = 7, 5, 3
+};
+
+int gpw_build_ao_tables(double ell_over_dx, double sigma_over_dx, GpAoTablesF64 *out);
 
 // Returns 0 on success, < 0 on invalid input or a failed factorisation.
 int gpw_build_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx, GpTablesF64 *out);

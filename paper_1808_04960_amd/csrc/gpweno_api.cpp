@@ -46,6 +46,7 @@ struct gpweno_ctx {
     int nv;
     gpweno_options opt;
     GpTablesF64 tab64[3];
+    GpAoTablesF64 ao64[3];          // adaptive-order GP only
     gpw::Tab<double> tabd[3];
     gpw::Tab<float> tabf[3];
     int device;
@@ -112,6 +113,7 @@ gpw::SweepArgs<Real> base_args(const gpweno_ctx* c, int dir) {
 
 // Smoothness-indicator kind of the kernels (see launch_sweep).
 int indicator_kind(const gpweno_ctx* c) {
+    if (c->scheme == GPWENO_GP_AO) return 3;
     if (c->scheme == GPWENO_WENO_JS) return 1;
     return c->opt.nonzero_mean ? 2 : 0;
 }
@@ -203,6 +205,42 @@ bool valid_options(const gpweno_options* o) {
            std::isfinite(o->cfl) && o->fixed_dt >= 0 && std::isfinite(o->fixed_dt);
 }
 
+bool valid_scheme(int scheme) {
+    return scheme == GPWENO_GP_WENO || scheme == GPWENO_WENO_JS || scheme == GPWENO_WENO_GP || scheme == GPWENO_GP_AO;
+}
+
+// The constants of the adaptive-order hybrid (App. A): gamma_HI = gamma_LO = 0.85
+// and the CWENO linear weights of Eq. (CWENO-lin).
+constexpr double AO_GAMMA_HI = 0.85, AO_GAMMA_LO = 0.85;
+
+// Adaptive-order tables: the GP-R2 sub-stencil weights and K_3(sigma) rows
+// (scheme GP-WENO, R = 2) with the CWENO linear weights in place of the
+// GP-WENO ones, and the 7- and 5-point tables.
+int build_ao(double ell_dx, double sigma_dx, GpTablesF64* t, GpAoTablesF64* ao) {
+    int st = gpw_build_tables(GPWENO_GP_WENO, 2, ell_dx, sigma_dx, t);
+    if (st) return st;
+    const double g[3] = {0.5 * (1 - AO_GAMMA_HI) * (1 - AO_GAMMA_LO), (1 - AO_GAMMA_HI) * AO_GAMMA_LO,
+                         0.5 * (1 - AO_GAMMA_HI) * (1 - AO_GAMMA_LO)};
+    for (int m = 0; m < 4; ++m) t->gam_plus[m] = t->gam_minus[m] = m < 3 ? g[m] : 0.0;
+    return gpw_build_ao_tables(ell_dx, sigma_dx, ao);
+}
+
+template <typename Real>
+void fill_ao(gpw::AoTab<Real>& t, const GpAoTablesF64& s) {
+    for (int j = 0; j < 7; ++j) {
+        t.w7p[j] = (Real)s.w7_plus[j];
+        t.w7m[j] = (Real)s.w7_minus[j];
+        for (int i = 0; i < 7; ++i) t.P7[i][j] = (Real)s.P7[i][j];
+    }
+    for (int j = 0; j < 5; ++j) {
+        t.w5p[j] = (Real)s.w5_plus[j];
+        t.w5m[j] = (Real)s.w5_minus[j];
+        for (int i = 0; i < 5; ++i) t.P5[i][j] = (Real)s.P5[i][j];
+    }
+    for (int k = 0; k < 3; ++k) t.c[k] = (Real)s.c[k];
+    t.ghi = (Real)AO_GAMMA_HI;
+}
+
 template <typename Real>
 void fill_tab(gpw::Tab<Real>& t, const GpTablesF64& s) {
     for (int m = 0; m < 4; ++m) {
@@ -222,20 +260,45 @@ extern "C" {
 
 int gpweno_compute_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx, double* w_plus,
                           double* w_minus, double* gam_plus, double* gam_minus, double* P) {
-    if (scheme != GPWENO_GP_WENO && scheme != GPWENO_WENO_JS && scheme != GPWENO_WENO_GP)
-        return fail(nullptr, GPWENO_EINVAL, "unknown scheme %d", scheme);
+    if (!valid_scheme(scheme)) return fail(nullptr, GPWENO_EINVAL, "unknown scheme %d", scheme);
     if (R < 1 || R > 3) return fail(nullptr, GPWENO_EINVAL, "R must be 1, 2 or 3 (got %d)", R);
     if (scheme == GPWENO_WENO_JS && R > 2) return fail(nullptr, GPWENO_EINVAL, "WENO-JS needs R = 1 or 2");
+    if (scheme == GPWENO_GP_AO && R < 2) return fail(nullptr, GPWENO_EINVAL, "GP-AO needs R = 2 or 3");
     if (!(ell_over_dx > 0) || !std::isfinite(ell_over_dx) || !(sigma_over_dx > 0) || !std::isfinite(sigma_over_dx))
         return fail(nullptr, GPWENO_EINVAL, "length scales must be positive and finite");
     GpTablesF64 t;
-    int st = gpw_build_tables(scheme, R, ell_over_dx, sigma_over_dx, &t);
+    GpAoTablesF64 ao;
+    int st = scheme == GPWENO_GP_AO ? build_ao(ell_over_dx, sigma_over_dx, &t, &ao)
+                                    : gpw_build_tables(scheme, R, ell_over_dx, sigma_over_dx, &t);
     if (st) return fail(nullptr, GPWENO_EINVAL, "table construction failed (%d)", st);
     if (w_plus) std::memcpy(w_plus, t.w_plus, sizeof t.w_plus);
     if (w_minus) std::memcpy(w_minus, t.w_minus, sizeof t.w_minus);
     if (gam_plus) std::memcpy(gam_plus, t.gam_plus, sizeof t.gam_plus);
     if (gam_minus) std::memcpy(gam_minus, t.gam_minus, sizeof t.gam_minus);
     if (P) std::memcpy(P, t.P, sizeof t.P);
+    return GPWENO_OK;
+}
+
+int gpweno_compute_ao_tables(double ell_over_dx, double sigma_over_dx, double* w7, double* w5, double* P7,
+                             double* P5, double* P3, double* c) {
+    if (!(ell_over_dx > 0) || !std::isfinite(ell_over_dx) || !(sigma_over_dx > 0) || !std::isfinite(sigma_over_dx))
+        return fail(nullptr, GPWENO_EINVAL, "length scales must be positive and finite");
+    GpTablesF64 t;
+    GpAoTablesF64 ao;
+    int st = build_ao(ell_over_dx, sigma_over_dx, &t, &ao);
+    if (st) return fail(nullptr, GPWENO_EINVAL, "table construction failed (%d)", st);
+    if (w7) {
+        std::memcpy(w7, ao.w7_plus, sizeof ao.w7_plus);
+        std::memcpy(w7 + 7, ao.w7_minus, sizeof ao.w7_minus);
+    }
+    if (w5) {
+        std::memcpy(w5, ao.w5_plus, sizeof ao.w5_plus);
+        std::memcpy(w5 + 5, ao.w5_minus, sizeof ao.w5_minus);
+    }
+    if (P7) std::memcpy(P7, ao.P7, sizeof ao.P7);
+    if (P5) std::memcpy(P5, ao.P5, sizeof ao.P5);
+    if (P3) std::memcpy(P3, ao.P3, sizeof ao.P3);
+    if (c) std::memcpy(c, ao.c, sizeof ao.c);
     return GPWENO_OK;
 }
 
@@ -248,10 +311,10 @@ int gpweno_init_scheme(const gpweno_grid* grid, int scheme, int R, double ell, d
     if (!grid || !out) return fail(nullptr, GPWENO_EINVAL, "NULL grid or output pointer");
     *out = nullptr;
     if (grid->ndim < 1 || grid->ndim > 3) return fail(nullptr, GPWENO_EINVAL, "ndim must be 1, 2 or 3");
-    if (scheme != GPWENO_GP_WENO && scheme != GPWENO_WENO_JS && scheme != GPWENO_WENO_GP)
-        return fail(nullptr, GPWENO_EINVAL, "unknown scheme %d", scheme);
+    if (!valid_scheme(scheme)) return fail(nullptr, GPWENO_EINVAL, "unknown scheme %d", scheme);
     if (R < 1 || R > 3) return fail(nullptr, GPWENO_EINVAL, "R must be 1, 2 or 3 (got %d)", R);
     if (scheme == GPWENO_WENO_JS && R > 2) return fail(nullptr, GPWENO_EINVAL, "WENO-JS needs R = 1 or 2");
+    if (scheme == GPWENO_GP_AO && R < 2) return fail(nullptr, GPWENO_EINVAL, "GP-AO needs R = 2 or 3");
     if (!(gamma > 1.0) || !std::isfinite(gamma)) return fail(nullptr, GPWENO_EINVAL, "gamma must be > 1");
     if (!(ell > 0) || !std::isfinite(ell)) return fail(nullptr, GPWENO_EINVAL, "ell must be positive");
     gpweno_ctx* c = new (std::nothrow) gpweno_ctx();
@@ -296,13 +359,18 @@ int gpweno_init_scheme(const gpweno_grid* grid, int scheme, int R, double ell, d
             delete c;
             return fail(nullptr, GPWENO_EINVAL, "sigma must exceed dx on every axis (sigma <= dx is unstable)");
         }
-        int st = gpw_build_tables(scheme, R, ell / c->dx[d], sigma / c->dx[d], &c->tab64[d]);
+        int st = scheme == GPWENO_GP_AO ? build_ao(ell / c->dx[d], sigma / c->dx[d], &c->tab64[d], &c->ao64[d])
+                                        : gpw_build_tables(scheme, R, ell / c->dx[d], sigma / c->dx[d], &c->tab64[d]);
         if (st) {
             delete c;
             return fail(nullptr, GPWENO_EINVAL, "table construction failed on axis %d (%d)", d, st);
         }
         fill_tab(c->tabd[d], c->tab64[d]);
         fill_tab(c->tabf[d], c->tab64[d]);
+        if (scheme == GPWENO_GP_AO) {
+            fill_ao(c->tabd[d].ao, c->ao64[d]);
+            fill_ao(c->tabf[d].ao, c->ao64[d]);
+        }
     }
     if (c->ncell > (1ll << 40)) {
         delete c;

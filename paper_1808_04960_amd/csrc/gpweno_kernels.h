@@ -50,6 +50,19 @@ struct Ctl {
 // The current step state, as the host reads it.
 inline const StepRec& current_rec(const Ctl& c) { return c.rec[0].nsteps > c.rec[1].nsteps ? c.rec[0] : c.rec[1]; }
 
+// Tables of the adaptive-order GP interpolation (indicator kind 3): whole-stencil
+// GP weights of radius 3 and 2 at x_{i+-1/2}, rows v_i / sqrt(lambda_i) of
+// K_7(sigma) and K_5(sigma), the constants N/2 log(2 pi) + 1/2 log det K_N(sigma)
+// for N = 7, 5, 3, and gamma_HI. The 3-point sub-stencils use Tab::wp / wm,
+// Tab::P[0] (K_3(sigma)) and Tab::gp (the CWENO linear weights).
+template <typename Real>
+struct AoTab {
+    Real w7p[7], w7m[7], w5p[5], w5m[5];
+    Real P7[7][7], P5[5][5];
+    Real c[3];
+    Real ghi;
+};
+
 template <typename Real>
 struct Tab {
     Real wp[4][4];  // w_m at x_* = +1/2, [m][j]
@@ -59,6 +72,7 @@ struct Tab {
     Real P[4][4][4];  // [m][i][j]: beta_m = sum_i (P[m][i] . f_m)^2 (GP: rows v_i / sqrt(lambda_i)
                       // of K_m(sigma), the same for every m; WENO-JS: a factor of the
                       // Jiang-Shu quadratic form of sub-stencil m)
+    AoTab<Real> ao;
 };
 
 template <typename Real>
@@ -124,7 +138,7 @@ struct BatchStatus {
 // stage (last direction of stages 1..3); otherwise it accumulates into dU.
 // ik: smoothness-indicator kind. 0: GP, Tab::P[0] serves every sub-stencil;
 // 1: a factor per sub-stencil (Jiang-Shu, R = 1, 2); 2: GP on the data minus the
-// centre cell's value (non-zero mean).
+// centre cell's value (non-zero mean); 3: adaptive-order GP (R = 2, 3).
 // bcg: the sweep axis has a non-periodic side (the kernel reads bc[]); the
 // periodic-only kernels skip that logic and its registers.
 hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, int ik, bool bcg, const void* args,

@@ -239,6 +239,136 @@ __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Re
     qm = accm * (sp * inv);
 }
 
+// Adaptive-order GP interpolation (the paper's App. A) of one characteristic
+// field f[0..2R] to x_{i+1/2} (qp) and x_{i-1/2} (qm); R = 3 gives GP-AO(3,2,3),
+// R = 2 gives GP-AO(2,3).
+//   indicators: the negative log-likelihood with its normalisation and
+//     complexity terms, beta_N = c_N + 1/2 sum_i (P_i . f_N)^2 (Eqs. (log-like),
+//     (beta-eigen)), for the 7- and 5-point stencils and the three 3-point
+//     sub-stencils of the 5-point one;
+//   GP-AO(R,3): omega^R and omega_m from gamma_HI/(eps+beta^R)^2 and
+//     gamma_m/(eps+beta_m)^2 normalised together (Eq. (nonlin-AO), with gamma_m
+//     for the sub-stencils), q = omega^R/gamma_HI q^R + sum_m (omega_m -
+//     omega^R gamma_m/gamma_HI) q^m (Eq. (GP-AO));
+//   GP-AO(3,2,3): weights gamma_HI/(eps+beta^7)^2 and (1-gamma_HI)/(eps+beta^5)^2
+//     normalised (Eq. (recursive-weights)) combine the two (Eq. (AO-recursive)).
+// The weights are evaluated as ratios to the smallest |eps + beta| (the
+// indicators can be negative: the log-det term of a 7-point K is), so no
+// intermediate overflows. Both faces share the indicators and weights.
+template <int N, typename Real>
+__device__ __forceinline__ Real half_quad(const Real (&P)[N][N], const Real* f) {
+    Real s = Real(0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        Real pr = P[i][0] * f[0];
+#pragma unroll
+        for (int j = 1; j < N; ++j) pr = fma(P[i][j], f[j], pr);
+        s = fma(pr, pr, s);
+    }
+    return Real(0.5) * s;
+}
+
+// Coefficients (a_hi, a_m) of q = a_hi q^hi + sum_m a_m q^m for GP-AO(R,3)
+// given e = eps + beta of the high-order stencil and of the sub-stencils.
+template <typename Real>
+__device__ __forceinline__ void ao_coeffs(Real eh, const Real (&em)[3], const Tab<Real>& T, Real& ah, Real (&am)[3]) {
+    Real mn = fabs(eh);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) mn = fmin(mn, fabs(em[m]));
+    const Real ghi = T.ao.ghi;
+    Real r = mn * frcp(eh);
+    const Real wh = ghi * r * r;
+    Real wm[3], sum = wh;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        r = mn * frcp(em[m]);
+        wm[m] = T.gp[m] * r * r;
+        sum += wm[m];
+    }
+    const Real inv = frcp(sum);
+    ah = wh * inv * frcp(ghi);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) am[m] = fma(-ah, T.gp[m], wm[m] * inv);
+}
+
+template <int R, typename Real>
+__device__ __forceinline__ void gp_ao(const Real (&f)[2 * R + 1], const Tab<Real>& T, Real& qp, Real& qm) {
+    static_assert(R == 2 || R == 3, "GP-AO uses stencils of radius 2 and 3");
+    const Real* f5 = f + (R - 2);
+    const Real e5 = Real(1e-36) + (T.ao.c[1] + half_quad<5, Real>(T.ao.P5, f5));
+    Real em[3], q3p[3], q3m[3];
+    Real P3[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) P3[i][j] = T.P[0][i][j];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        em[m] = Real(1e-36) + (T.ao.c[2] + half_quad<3, Real>(P3, f5 + m));
+        Real a = T.wp[m][0] * f5[m], b = T.wm[m][0] * f5[m];
+#pragma unroll
+        for (int j = 1; j < 3; ++j) {
+            a = fma(T.wp[m][j], f5[m + j], a);
+            b = fma(T.wm[m][j], f5[m + j], b);
+        }
+        q3p[m] = a;
+        q3m[m] = b;
+    }
+    Real q5p = T.ao.w5p[0] * f5[0], q5m = T.ao.w5m[0] * f5[0];
+#pragma unroll
+    for (int j = 1; j < 5; ++j) {
+        q5p = fma(T.ao.w5p[j], f5[j], q5p);
+        q5m = fma(T.ao.w5m[j], f5[j], q5m);
+    }
+    Real a5, c5[3];
+    ao_coeffs<Real>(e5, em, T, a5, c5);
+    Real ao5p = a5 * q5p, ao5m = a5 * q5m;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        ao5p = fma(c5[m], q3p[m], ao5p);
+        ao5m = fma(c5[m], q3m[m], ao5m);
+    }
+    if constexpr (R == 2) {
+        qp = ao5p;
+        qm = ao5m;
+    } else {
+        const Real e7 = Real(1e-36) + (T.ao.c[0] + half_quad<7, Real>(T.ao.P7, f));
+        Real q7p = T.ao.w7p[0] * f[0], q7m = T.ao.w7m[0] * f[0];
+#pragma unroll
+        for (int j = 1; j < 7; ++j) {
+            q7p = fma(T.ao.w7p[j], f[j], q7p);
+            q7m = fma(T.ao.w7m[j], f[j], q7m);
+        }
+        Real a7, c7[3];
+        ao_coeffs<Real>(e7, em, T, a7, c7);
+        Real ao7p = a7 * q7p, ao7m = a7 * q7m;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            ao7p = fma(c7[m], q3p[m], ao7p);
+            ao7m = fma(c7[m], q3m[m], ao7m);
+        }
+        // recursive weights of the 7- and 5-point stencils, as ratios
+        const Real ghi = T.ao.ghi;
+        const Real mn = fmin(fabs(e7), fabs(e5));
+        Real r = mn * frcp(e7);
+        const Real nh = ghi * r * r;
+        r = mn * frcp(e5);
+        const Real nl = (Real(1) - ghi) * r * r;
+        const Real inv = frcp(nh + nl);
+        const Real bh = nh * inv * frcp(ghi);
+        const Real bl = fma(-bh, Real(1) - ghi, nl * inv);
+        qp = fma(bh, ao7p, bl * ao5p);
+        qm = fma(bh, ao7m, bl * ao5m);
+    }
+}
+
+// The interpolation of one field for the indicator kind.
+template <int R, typename Real, int IK>
+__device__ __forceinline__ void interp(const Real (&f)[2 * R + 1], const Tab<Real>& T, Real& qp, Real& qm) {
+    if constexpr (IK == 3) gp_ao<R, Real>(f, T, qp, qm);
+    else gp_weno<R, Real, IK>(f, T, qp, qm);
+}
+
 // Riemann states of the cell at lane position l: stencil entries l .. l+2R of a
 // pencil in LDS (field k at s[k * fs + .]). Projects the primitive stencil on the
 // left eigenvectors of the primitive Jacobian at the centre cell, interpolates
@@ -272,18 +402,18 @@ __device__ __forceinline__ void reconstruct(const Real* __restrict__ s, int fs, 
     Real acm_p, acm_m, ent_p, ent_m, acp_p, acp_m;
 #pragma unroll
     for (int j = 0; j < NS; ++j) f[j] = fma(-a, v[1][j], b * v[NV - 1][j]);
-    gp_weno<R, Real, IK>(f, T, acm_p, acm_m);
+    interp<R, Real, IK>(f, T, acm_p, acm_m);
 #pragma unroll
     for (int j = 0; j < NS; ++j) f[j] = fma(-ic2, v[NV - 1][j], v[0][j]);
-    gp_weno<R, Real, IK>(f, T, ent_p, ent_m);
+    interp<R, Real, IK>(f, T, ent_p, ent_m);
 #pragma unroll
     for (int j = 0; j < NS; ++j) f[j] = fma(a, v[1][j], b * v[NV - 1][j]);
-    gp_weno<R, Real, IK>(f, T, acp_p, acp_m);
+    interp<R, Real, IK>(f, T, acp_p, acp_m);
 #pragma unroll
     for (int t = 0; t < NDIM - 1; ++t) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) f[j] = v[2 + t][j];
-        gp_weno<R, Real, IK>(f, T, qp[2 + t], qm[2 + t]);
+        interp<R, Real, IK>(f, T, qp[2 + t], qm[2 + t]);
     }
     const Real cr = c * irho;
     qp[0] = acm_p + ent_p + acp_p;
@@ -880,11 +1010,14 @@ hipError_t launch_bcg(int dir, bool fin, bool bcg, const void* args, hipStream_t
                : launch_dir<NDIM, R, Real, IK, false>(dir, fin, args, s);
 }
 
-// Indicator kinds: 0 for R = 1..3, 1 (Jiang-Shu) for R = 1, 2, 2 for R = 1..3.
+// Indicator kinds: 0 for R = 1..3, 1 (Jiang-Shu) for R = 1, 2, 2 for R = 1..3,
+// 3 (adaptive order) for R = 2, 3.
 template <int NDIM, typename Real, int IK>
 hipError_t launch_rk(int dir, int R, bool fin, bool bcg, const void* args, hipStream_t s) {
     switch (R) {
-        case 1: return launch_bcg<NDIM, 1, Real, IK>(dir, fin, bcg, args, s);
+        case 1:
+            if constexpr (IK != 3) return launch_bcg<NDIM, 1, Real, IK>(dir, fin, bcg, args, s);
+            return hipErrorInvalidValue;
         case 2: return launch_bcg<NDIM, 2, Real, IK>(dir, fin, bcg, args, s);
         case 3:
             if constexpr (IK != 1) return launch_bcg<NDIM, 3, Real, IK>(dir, fin, bcg, args, s);
@@ -899,6 +1032,7 @@ hipError_t launch_r(int dir, int R, bool fin, int ik, bool bcg, const void* args
         case 0: return launch_rk<NDIM, Real, 0>(dir, R, fin, bcg, args, s);
         case 1: return launch_rk<NDIM, Real, 1>(dir, R, fin, bcg, args, s);
         case 2: return launch_rk<NDIM, Real, 2>(dir, R, fin, bcg, args, s);
+        case 3: return launch_rk<NDIM, Real, 3>(dir, R, fin, bcg, args, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -962,7 +1096,9 @@ hipError_t launch_batch_bcg(int dir, bool fin, bool bcg, const void* args, long 
 template <int NDIM, typename Real, int IK>
 hipError_t launch_batch_rk(int dir, int R, bool fin, bool bcg, const void* args, long long blocks, hipStream_t s) {
     switch (R) {
-        case 1: return launch_batch_bcg<NDIM, 1, Real, IK>(dir, fin, bcg, args, blocks, s);
+        case 1:
+            if constexpr (IK != 3) return launch_batch_bcg<NDIM, 1, Real, IK>(dir, fin, bcg, args, blocks, s);
+            return hipErrorInvalidValue;
         case 2: return launch_batch_bcg<NDIM, 2, Real, IK>(dir, fin, bcg, args, blocks, s);
         case 3:
             if constexpr (IK != 1) return launch_batch_bcg<NDIM, 3, Real, IK>(dir, fin, bcg, args, blocks, s);
@@ -978,6 +1114,7 @@ hipError_t launch_batch_r(int dir, int R, bool fin, int ik, bool bcg, const void
         case 0: return launch_batch_rk<NDIM, Real, 0>(dir, R, fin, bcg, args, blocks, s);
         case 1: return launch_batch_rk<NDIM, Real, 1>(dir, R, fin, bcg, args, blocks, s);
         case 2: return launch_batch_rk<NDIM, Real, 2>(dir, R, fin, bcg, args, blocks, s);
+        case 3: return launch_batch_rk<NDIM, Real, 3>(dir, R, fin, bcg, args, blocks, s);
         default: return hipErrorInvalidValue;
     }
 }

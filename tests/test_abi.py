@@ -114,3 +114,24 @@ def test_null_context_is_rejected(L):
     assert L.gpweno_state_count(None) == 0
     assert L.gpweno_workspace_bytes(None) == 0
     L.gpweno_destroy(None)
+
+
+@pytest.mark.parametrize("ell,sigma", [(12.0, 1.8), (6.0, 1.5), (12.0, 3.0)])
+def test_binary128_ao_tables_match_oracle(ell, sigma):
+    from oracle.tables import gp_ao_tables
+    got = gw.compute_ao_tables(ell, sigma)
+    ref = gp_ao_tables(ell, sigma)
+    for N, key in ((7, "w7"), (5, "w5")):
+        np.testing.assert_allclose(got[key][0], ref[key + "+"], rtol=1e-15, atol=1e-16)
+        np.testing.assert_allclose(got[key][1], ref[key + "-"], rtol=1e-15, atol=1e-16)
+    for N in (7, 5, 3):
+        a, b = got[f"P{N}"], ref[f"P{N}"]
+        np.testing.assert_allclose(a.T @ a, b.T @ b, rtol=1e-13, atol=1e-13 * np.abs(b.T @ b).max())
+    np.testing.assert_allclose(got["c"], [ref["c7"], ref["c5"], ref["c3"]], rtol=1e-15, atol=1e-15)
+
+
+def test_gp_ao_needs_radius_two_or_three(L):
+    g = gw.make_grid(_G(1, (64, 1, 1)))
+    ctx = ctypes.c_void_p()
+    assert L.gpweno_init_scheme(ctypes.byref(g), 3, 1, 0.1, 0.05, 1.4, ctypes.byref(ctx)) == gw.EINVAL
+    assert not ctx.value

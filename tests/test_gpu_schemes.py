@@ -231,3 +231,52 @@ def test_nonzero_mean_square_pulse(prec):
     announce(f"square pulse {prec}: overshoot {over:.2e}, rel L1 vs oracle {err:.2e}, oracle spread {spread:.2e}")
     assert over < 1e-3
     assert err < (4 if prec == "fp64" else 10) * spread
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+@pytest.mark.parametrize("R", [2, 3])
+def test_gp_ao_rhs_matches_oracle(R, ndim, prec):
+    """Adaptive-order GP (App. A): GP-AO(2,3) and GP-AO(3,2,3), sigma = 1.8 dx as
+    the paper uses with it."""
+    g = GRIDS[ndim]()
+    announce(f"rhs gp-ao R={R} ndim={ndim} {prec}")
+    U = inputs.random_smooth(g, seed=400 + 10 * ndim + R)
+    dx = g.dx[0]
+    o = oracle.OracleSolver(g, R, 12 * dx, 1.8 * dx, scheme="gp-ao")
+    ref = o.rhs(U)
+    s = gw.Solver(g, R, 12 * dx, 1.8 * dx, precision=prec, U0=U, scheme="gp-ao")
+    got = s.rhs(U)
+    err = float(np.abs(got - ref).sum())
+    bound = 16 * EPS[prec] * flux_bound(g, U)
+    announce(f"  abs L1 {err:.3e}  bound {bound:.3e}  rel L1 {rel_l1(got, ref):.3e}")
+    assert err < bound
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("R", [2, 3])
+def test_gp_ao_shock_tube_matches_oracle(R, prec, tol):
+    g, U = inputs.shock_tube_1d(200)
+    dx = g.dx[0]
+    Uo = U.copy()
+    to, no = oracle.OracleSolver(g, R, 12 * dx, 1.8 * dx, scheme="gp-ao").run(Uo, 0.2)
+    s = gw.Solver(g, R, 12 * dx, 1.8 * dx, precision=prec, U0=U, scheme="gp-ao")
+    n, t = s.run(0.2)
+    assert n == no and t == to
+    err = rel_l1(s.get_state(), Uo)
+    announce(f"gp-ao shock tube R={R} {prec}: rel L1 vs oracle {err:.3e}")
+    assert err < tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_gp_ao_vortex_matches_oracle(prec, tol):
+    g, U = inputs.isentropic_vortex_2d(64)
+    dx = g.dx[0]
+    Uo = U.copy()
+    oracle.OracleSolver(g, 3, 12 * dx, 1.8 * dx, scheme="gp-ao").run(Uo, 10.0, max_steps=30)
+    s = gw.Solver(g, 3, 12 * dx, 1.8 * dx, precision=prec, U0=U, scheme="gp-ao")
+    n, _ = s.run(10.0, max_steps=30)
+    assert n == 30
+    err = rel_l1(s.get_state(), Uo)
+    announce(f"gp-ao vortex {prec}: rel L1 vs oracle {err:.3e}")
+    assert err < tol
