@@ -37,7 +37,17 @@ import inputs  # noqa: E402
 
 METRIC = "cell-updates/sec per RK stage (FP32 vs FP64 at stated L1 err); p50/p99 solve latency"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X published vector peaks
-KERNEL_SRC = os.path.join(ROOT, "paper_1808_04960_amd", "csrc", "gpweno_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1808_04960_amd", "csrc")
+
+
+def kernel_source_hash() -> str:
+    """sha256[:16] of the device sources (every .hip file and the kernel headers)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith(".hip") or name in ("gpweno_sweep.h", "gpweno_kernels.h"):
+            with open(os.path.join(CSRC, name), "rb") as fh:
+                h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
 
 
 def flops_per_cell_sweep(ndim: int, R: int) -> int:
@@ -190,8 +200,7 @@ def traffic_from_profiles(kernel_name, tag):
     path = os.path.join(ROOT, "profiles", "traffic.txt")
     if not os.path.exists(path):
         return None
-    with open(KERNEL_SRC, "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()[:16]
+    sha = kernel_source_hash()
     entries = {}
     with open(path) as fh:
         for line in fh:

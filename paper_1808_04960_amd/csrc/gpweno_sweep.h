@@ -1,0 +1,1001 @@
+// GP-WENO FD-Prim sweep kernels for gfx950 (CDNA4, wave64).
+//
+// One kernel launch evaluates one direction's contribution to the right-hand
+// side of Eq. (disc_fd) for every cell, and in the last direction of an RK
+// stage also finishes the stage. Work decomposition:
+//
+//   * A "run" is 64 consecutive cells of one pencil along the sweep axis,
+//     mapped one cell per lane of a wave. Each lane reconstructs the Riemann
+//     states of its cell (stencil of 2R+1 cells read from LDS), the wave then
+//     forms face fluxes, corrected fluxes and flux differences with cross-lane
+//     shuffles. The flux correction needs face fluxes two faces either side
+//     and the difference one more face, so lanes 3..60 produce output: a run
+//     yields 58 cells, and consecutive runs overlap by 6 cells.
+//   * A block holds several pencils (one wave each) and the same run segment.
+//     The input tile [2+ndim fields][pencils][64 + 2R cells] is loaded once
+//     from HBM (ghost positions: periodic image, outflow copy or mirror image),
+//     converted to rotated primitive variables and staged in LDS.
+//   * x sweeps: each wave loads its own row (contiguous along x) and writes its
+//     outputs directly (contiguous). y/z sweeps: a block holds 8 adjacent
+//     x-columns, so every global access covers 8 consecutive doubles; the
+//     outputs are transposed through LDS so the read-modify-write epilogue is
+//     also x-contiguous.
+//
+// Per cell (paper references):
+//   characteristic projection of the primitive stencil at the centre cell
+//     (Sec. 7 intro), GP-WENO per field (Sec. 3.3: Eqs. (candidate_interp),
+//     (beta-eigen), (weights), (weight_sum)), back-projection, HLLC at the face
+//     (Eq. (riemann_prob)), flux correction alpha = -1/24, beta = 3/640
+//     (Eqs. (numFlux_cor), (FD-ders)), flux difference (Eq. (disc_fd)), SSP-RK3.
+//
+// Precision: Real is the sweep arithmetic type (double or float). The state,
+// flux differences, accumulator, RK combination, CFL speeds and sums are
+// always float64; a float32 corrected flux is widened before its difference
+// is taken, so both neighbours of a face subtract the same value.
+#include <float.h>
+#include <limits.h>
+
+#pragma once
+
+#include "gpweno_kernels.h"
+
+namespace gpw {
+
+constexpr int WAVE = 64;
+constexpr int LEFT = 3;             // first output lane of a run
+constexpr int TOUT = WAVE - 6;      // outputs per run
+
+__host__ __device__ constexpr int t1_axis(int dir) { return dir == 0 ? 1 : 0; }
+__host__ __device__ constexpr int t2_axis(int dir) { return dir == 2 ? 1 : 2; }
+
+// Conserved slot of rotated component k (rho, u_n, u_t1, u_t2, p order).
+template <int NDIM, int DIR>
+__host__ __device__ constexpr int cons_slot(int k) {
+    return k == 0 ? 0
+         : k == 1 ? 1 + DIR
+         : k == 1 + NDIM ? 1 + NDIM
+         : k == 2 ? 1 + t1_axis(DIR)
+         : 1 + t2_axis(DIR);
+}
+
+// Reciprocal and reciprocal square root. float: the hardware approximations
+// (about 1 ulp). double: the hardware approximation refined by two Newton-Raphson
+// steps, r <- r + r (1 - x r) and y <- y + y (1 - x y^2)/2, each of which squares
+// the relative error, giving float64 accuracy to within an ulp or two; cheaper
+// than the IEEE division and square-root sequences. Arguments are positive and
+// normal wherever these are used on a selected value.
+template <typename Real> __device__ __forceinline__ Real frcp(Real x);
+template <> inline __device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> inline __device__ __forceinline__ double frcp<double>(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+template <typename Real> __device__ __forceinline__ Real frsq(Real x);
+template <> inline __device__ __forceinline__ float frsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> inline __device__ __forceinline__ double frsq<double>(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+// Periodic index. For n >= 64 every index a sweep forms lies in [-n, 2n), so a
+// compare-and-add suffices; shorter axes (tests) take the general modulo.
+inline __device__ __forceinline__ int wrap(int x, int n) {
+    if (n >= WAVE) {
+        x += (x < 0) ? n : 0;
+        return x - ((x >= n) ? n : 0);
+    }
+    int r = x % n;
+    return r < 0 ? r + n : r;
+}
+
+// Source cell of stencil position x on an axis of n cells, for the boundary kinds
+// lo / hi of its two sides (gpweno_bc: 0 periodic, 1 outflow, 2 reflecting), and
+// whether the normal momentum changes sign (mirror image at a wall). Positions
+// beyond the ghost depth (unused lanes of a pencil's last run) are clamped into
+// the axis so every load stays in bounds.
+inline __device__ __forceinline__ int ghost_src(int x, int n, int lo, int hi, bool& flip) {
+    flip = false;
+    if (x >= 0 && x < n) return x;
+    const int kind = x < 0 ? lo : hi;
+    if (kind == 0) return wrap(x, n);
+    int j;
+    if (kind == 1) {
+        j = x < 0 ? 0 : n - 1;
+    } else {
+        j = x < 0 ? -1 - x : 2 * n - 1 - x;
+        flip = true;
+    }
+    return j < 0 ? 0 : (j >= n ? n - 1 : j);
+}
+
+// Time step of the step in flight and whether it runs. final_sweep: the
+// sweep that closes the step (its block 0 writes the next step state). Only
+// sweeps that finish an RK stage need dt (NEED_DT); the others read no speeds.
+// Every field is read up front, with no address depending on another read, so
+// the control block costs one round trip of scalar loads.
+template <bool NEED_DT>
+__device__ __forceinline__ bool step_go(const Ctl* c, bool final_sweep, double& t0, double& dt, long long& n) {
+    const long long n0 = c->rec[0].nsteps, n1 = c->rec[1].nsteps;
+    const double ta = c->rec[0].t, tb = c->rec[1].t;
+    const long long st = c->started;
+    const int err = c->err;
+    const double tf = c->t_final;
+    const long long lim = c->step_limit;
+    unsigned long long s0 = 0, s1 = 0;
+    double fixed = 0.0, cfl = 0.0;
+    if (NEED_DT) {
+        fixed = c->fixed_dt;
+        cfl = c->cfl;
+#pragma unroll
+        for (int x = 0; x < 8; ++x) {
+            const unsigned long long a0 = c->xcd[x].speed[0], a1 = c->xcd[x].speed[1];
+            s0 = a0 > s0 ? a0 : s0;
+            s1 = a1 > s1 ? a1 : s1;
+        }
+    }
+    int r;
+    if (final_sweep) {
+        if (st < 0) return false;
+        r = (n0 == st) ? 0 : 1;
+        if ((r ? n1 : n0) != st) return false;
+    } else {
+        r = n0 > n1 ? 0 : 1;
+    }
+    t0 = r ? tb : ta;
+    n = r ? n1 : n0;
+    if (err || !(t0 < tf) || n >= lim) return false;
+    if (NEED_DT) {
+        const double speed = __longlong_as_double((long long)((n & 1) ? s1 : s0));
+        double d = fixed > 0.0 ? fixed : cfl / speed;
+        if (t0 + d > tf) d = tf - t0;
+        dt = d;
+    }
+    return true;
+}
+
+// Conserved -> primitive in the frame rotated to DIR: (rho, u_n[, u_t1[, u_t2]], p).
+template <int NDIM, int DIR>
+__device__ __forceinline__ void cons_to_rot(const double (&u)[2 + NDIM], double gamma, double q[2 + NDIM]) {
+    constexpr int NV = 2 + NDIM;
+    const double rho = u[0];
+    const double irho = frcp(rho);
+    double vel[3] = {0.0, 0.0, 0.0};
+    double ke = 0.0;
+#pragma unroll
+    for (int d = 0; d < NDIM; ++d) {
+        vel[d] = u[1 + d] * irho;
+        ke += vel[d] * u[1 + d];
+    }
+    const double E = u[NV - 1];
+    q[0] = rho;
+    q[1] = vel[DIR];
+    if (NDIM >= 2) q[2] = vel[t1_axis(DIR)];
+    if (NDIM == 3) q[3] = vel[t2_axis(DIR)];
+    q[NV - 1] = (gamma - 1.0) * (E - 0.5 * ke);
+}
+
+// GP-WENO interpolation of one characteristic field f[0..2R] to x_{i+1/2} (qp)
+// and x_{i-1/2} (qm). beta_m = sum_i (P_m,i . f_m)^2 is shared by both points.
+// The comparison schemes (polynomial WENO with Jiang-Shu or GP smoothness
+// indicators) run through the same code with their own tables. IK, the kind of
+// smoothness indicator:
+//   0  GP, zero mean: the one factor of K_m(sigma), the same for every m, read
+//      once (fewer scalar registers for the tables);
+//   1  a factor per sub-stencil of rank R (Jiang-Shu quadratic forms);
+//   2  GP with the centre cell's value as the mean: the factor of K_m(sigma)
+//      applied to f_m - f_i (the paper's non-zero-mean variant, Sec. 7).
+// Nonlinear weights gamma_m / (eps + beta_m)^2 are evaluated in the equivalent
+// form gamma_m * ((eps + beta_min)/(eps + beta_m))^2, which cannot overflow or
+// underflow to 0/0 in float32 (eps = 1e-36 squared is below float range).
+template <int R, typename Real, int IK>
+__device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Real>& T, Real& qp, Real& qm) {
+    Real e[R + 1], cp[R + 1], cm[R + 1];
+    Real g[2 * R + 1];  // the data the indicators see
+#pragma unroll
+    for (int j = 0; j <= 2 * R; ++j) g[j] = IK == 2 ? f[j] - f[R] : f[j];
+#pragma unroll
+    for (int m = 0; m <= R; ++m) {
+        Real b = Real(0);
+#pragma unroll
+        for (int i = 0; i < (IK == 1 ? R : R + 1); ++i) {  // Jiang-Shu forms have rank R
+            Real pr = T.P[IK == 1 ? m : 0][i][0] * g[m];
+#pragma unroll
+            for (int j = 1; j <= R; ++j) pr = fma(T.P[IK == 1 ? m : 0][i][j], g[m + j], pr);
+            b = fma(pr, pr, b);
+        }
+        e[m] = Real(1e-36) + b;
+        Real ap = T.wp[m][0] * f[m];
+        Real am = T.wm[m][0] * f[m];
+#pragma unroll
+        for (int j = 1; j <= R; ++j) {
+            ap = fma(T.wp[m][j], f[m + j], ap);
+            am = fma(T.wm[m][j], f[m + j], am);
+        }
+        cp[m] = ap;
+        cm[m] = am;
+    }
+    Real emin = e[0];
+#pragma unroll
+    for (int m = 1; m <= R; ++m) emin = fmin(emin, e[m]);
+    Real sp = Real(0), sm = Real(0), accp = Real(0), accm = Real(0);
+#pragma unroll
+    for (int m = 0; m <= R; ++m) {
+        const Real r = emin * frcp(e[m]);
+        const Real w = r * r;
+        const Real op = T.gp[m] * w;
+        const Real om = T.gm[m] * w;
+        sp += op;
+        sm += om;
+        accp = fma(op, cp[m], accp);
+        accm = fma(om, cm[m], accm);
+    }
+    // both normalisations from one reciprocal: 1/sp = sm/(sp sm), 1/sm = sp/(sp sm)
+    const Real inv = frcp(sp * sm);
+    qp = accp * (sm * inv);
+    qm = accm * (sp * inv);
+}
+
+// Adaptive-order GP interpolation (the paper's App. A) of one characteristic
+// field f[0..2R] to x_{i+1/2} (qp) and x_{i-1/2} (qm); R = 3 gives GP-AO(3,2,3),
+// R = 2 gives GP-AO(2,3).
+//   indicators: the negative log-likelihood with its normalisation and
+//     complexity terms, beta_N = c_N + 1/2 sum_i (P_i . f_N)^2 (Eqs. (log-like),
+//     (beta-eigen)), for the 7- and 5-point stencils and the three 3-point
+//     sub-stencils of the 5-point one;
+//   GP-AO(R,3): omega^R and omega_m from gamma_HI/(eps+beta^R)^2 and
+//     gamma_m/(eps+beta_m)^2 normalised together (Eq. (nonlin-AO), with gamma_m
+//     for the sub-stencils), q = omega^R/gamma_HI q^R + sum_m (omega_m -
+//     omega^R gamma_m/gamma_HI) q^m (Eq. (GP-AO));
+//   GP-AO(3,2,3): weights gamma_HI/(eps+beta^7)^2 and (1-gamma_HI)/(eps+beta^5)^2
+//     normalised (Eq. (recursive-weights)) combine the two (Eq. (AO-recursive)).
+// The weights are evaluated as ratios to the smallest |eps + beta| (the
+// indicators can be negative: the log-det term of a 7-point K is), so no
+// intermediate overflows. Both faces share the indicators and weights.
+template <int N, typename Real>
+__device__ __forceinline__ Real half_quad(const Real (&P)[N][N], const Real* f) {
+    Real s = Real(0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        Real pr = P[i][0] * f[0];
+#pragma unroll
+        for (int j = 1; j < N; ++j) pr = fma(P[i][j], f[j], pr);
+        s = fma(pr, pr, s);
+    }
+    return Real(0.5) * s;
+}
+
+// Coefficients (a_hi, a_m) of q = a_hi q^hi + sum_m a_m q^m for GP-AO(R,3)
+// given e = eps + beta of the high-order stencil and of the sub-stencils.
+template <typename Real>
+__device__ __forceinline__ void ao_coeffs(Real eh, const Real (&em)[3], const Tab<Real>& T, Real& ah, Real (&am)[3]) {
+    Real mn = fabs(eh);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) mn = fmin(mn, fabs(em[m]));
+    const Real ghi = T.ao.ghi;
+    Real r = mn * frcp(eh);
+    const Real wh = ghi * r * r;
+    Real wm[3], sum = wh;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        r = mn * frcp(em[m]);
+        wm[m] = T.gp[m] * r * r;
+        sum += wm[m];
+    }
+    const Real inv = frcp(sum);
+    ah = wh * inv * frcp(ghi);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) am[m] = fma(-ah, T.gp[m], wm[m] * inv);
+}
+
+template <int R, typename Real>
+__device__ __forceinline__ void gp_ao(const Real (&f)[2 * R + 1], const Tab<Real>& T, Real& qp, Real& qm) {
+    static_assert(R == 2 || R == 3, "GP-AO uses stencils of radius 2 and 3");
+    const Real* f5 = f + (R - 2);
+    const Real e5 = Real(1e-36) + (T.ao.c[1] + half_quad<5, Real>(T.ao.P5, f5));
+    Real em[3], q3p[3], q3m[3];
+    Real P3[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) P3[i][j] = T.P[0][i][j];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        em[m] = Real(1e-36) + (T.ao.c[2] + half_quad<3, Real>(P3, f5 + m));
+        Real a = T.wp[m][0] * f5[m], b = T.wm[m][0] * f5[m];
+#pragma unroll
+        for (int j = 1; j < 3; ++j) {
+            a = fma(T.wp[m][j], f5[m + j], a);
+            b = fma(T.wm[m][j], f5[m + j], b);
+        }
+        q3p[m] = a;
+        q3m[m] = b;
+    }
+    Real q5p = T.ao.w5p[0] * f5[0], q5m = T.ao.w5m[0] * f5[0];
+#pragma unroll
+    for (int j = 1; j < 5; ++j) {
+        q5p = fma(T.ao.w5p[j], f5[j], q5p);
+        q5m = fma(T.ao.w5m[j], f5[j], q5m);
+    }
+    Real a5, c5[3];
+    ao_coeffs<Real>(e5, em, T, a5, c5);
+    Real ao5p = a5 * q5p, ao5m = a5 * q5m;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        ao5p = fma(c5[m], q3p[m], ao5p);
+        ao5m = fma(c5[m], q3m[m], ao5m);
+    }
+    if constexpr (R == 2) {
+        qp = ao5p;
+        qm = ao5m;
+    } else {
+        const Real e7 = Real(1e-36) + (T.ao.c[0] + half_quad<7, Real>(T.ao.P7, f));
+        Real q7p = T.ao.w7p[0] * f[0], q7m = T.ao.w7m[0] * f[0];
+#pragma unroll
+        for (int j = 1; j < 7; ++j) {
+            q7p = fma(T.ao.w7p[j], f[j], q7p);
+            q7m = fma(T.ao.w7m[j], f[j], q7m);
+        }
+        Real a7, c7[3];
+        ao_coeffs<Real>(e7, em, T, a7, c7);
+        Real ao7p = a7 * q7p, ao7m = a7 * q7m;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            ao7p = fma(c7[m], q3p[m], ao7p);
+            ao7m = fma(c7[m], q3m[m], ao7m);
+        }
+        // recursive weights of the 7- and 5-point stencils, as ratios
+        const Real ghi = T.ao.ghi;
+        const Real mn = fmin(fabs(e7), fabs(e5));
+        Real r = mn * frcp(e7);
+        const Real nh = ghi * r * r;
+        r = mn * frcp(e5);
+        const Real nl = (Real(1) - ghi) * r * r;
+        const Real inv = frcp(nh + nl);
+        const Real bh = nh * inv * frcp(ghi);
+        const Real bl = fma(-bh, Real(1) - ghi, nl * inv);
+        qp = fma(bh, ao7p, bl * ao5p);
+        qm = fma(bh, ao7m, bl * ao5m);
+    }
+}
+
+// The interpolation of one field for the indicator kind.
+template <int R, typename Real, int IK>
+__device__ __forceinline__ void interp(const Real (&f)[2 * R + 1], const Tab<Real>& T, Real& qp, Real& qm) {
+    if constexpr (IK == 3) gp_ao<R, Real>(f, T, qp, qm);
+    else gp_weno<R, Real, IK>(f, T, qp, qm);
+}
+
+// Riemann states of the cell at lane position l: stencil entries l .. l+2R of a
+// pencil in LDS (field k at s[k * fs + .]). Projects the primitive stencil on the
+// left eigenvectors of the primitive Jacobian at the centre cell, interpolates
+// each characteristic field, and projects back with the right eigenvectors:
+//   acoustic -:  -rho/(2c) u_n + p/(2c^2)       r = (1, -c/rho, 0, 0, c^2)
+//   entropy   :  rho - p/c^2                    r = (1, 0, 0, 0, 0)
+//   shear     :  u_t1, u_t2                     r = unit vectors
+//   acoustic +:   rho/(2c) u_n + p/(2c^2)       r = (1,  c/rho, 0, 0, c^2)
+template <int NDIM, int R, typename Real, int IK>
+__device__ __forceinline__ void reconstruct(const Real* __restrict__ s, int fs, int l, const Tab<Real>& T,
+                                            Real gamma, int positivity, Real (&qp)[2 + NDIM],
+                                            Real (&qm)[2 + NDIM]) {
+    constexpr int NV = 2 + NDIM;
+    constexpr int NS = 2 * R + 1;
+    Real v[NV][NS];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int j = 0; j < NS; ++j) v[k][j] = s[k * fs + l + j];
+
+    const Real rho = v[0][R], p = v[NV - 1][R];
+    const Real irho = frcp(rho);
+    const Real c2 = gamma * p * irho;
+    const Real ic = frsq(c2);
+    const Real c = c2 * ic;
+    const Real ic2 = ic * ic;
+    const Real a = Real(0.5) * rho * ic;
+    const Real b = Real(0.5) * ic2;
+
+    Real f[NS];
+    Real acm_p, acm_m, ent_p, ent_m, acp_p, acp_m;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) f[j] = fma(-a, v[1][j], b * v[NV - 1][j]);
+    interp<R, Real, IK>(f, T, acm_p, acm_m);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) f[j] = fma(-ic2, v[NV - 1][j], v[0][j]);
+    interp<R, Real, IK>(f, T, ent_p, ent_m);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) f[j] = fma(a, v[1][j], b * v[NV - 1][j]);
+    interp<R, Real, IK>(f, T, acp_p, acp_m);
+#pragma unroll
+    for (int t = 0; t < NDIM - 1; ++t) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) f[j] = v[2 + t][j];
+        interp<R, Real, IK>(f, T, qp[2 + t], qm[2 + t]);
+    }
+    const Real cr = c * irho;
+    qp[0] = acm_p + ent_p + acp_p;
+    qm[0] = acm_m + ent_m + acp_m;
+    qp[1] = cr * (acp_p - acm_p);
+    qm[1] = cr * (acp_m - acm_m);
+    qp[NV - 1] = c2 * (acm_p + acp_p);
+    qm[NV - 1] = c2 * (acm_m + acp_m);
+    if (positivity) {
+        if (!(qp[0] > Real(0)) || !(qp[NV - 1] > Real(0))) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) qp[k] = v[k][R];
+        }
+        if (!(qm[0] > Real(0)) || !(qm[NV - 1] > Real(0))) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) qm[k] = v[k][R];
+        }
+    }
+}
+
+// Euler flux of a rotated primitive state, and its conserved vector.
+template <int NDIM, typename Real>
+__device__ __forceinline__ void flux_of(const Real (&q)[2 + NDIM], Real inv_gm1, Real (&F)[2 + NDIM],
+                                        Real (&Uc)[2 + NDIM]) {
+    constexpr int NV = 2 + NDIM;
+    const Real r = q[0], u = q[1], p = q[NV - 1];
+    Real k2 = u * u;
+#pragma unroll
+    for (int t = 0; t < NDIM - 1; ++t) k2 = fma(q[2 + t], q[2 + t], k2);
+    const Real E = fma(p, inv_gm1, Real(0.5) * r * k2);
+    const Real mu = r * u;
+    F[0] = mu;
+    F[1] = fma(mu, u, p);
+#pragma unroll
+    for (int t = 0; t < NDIM - 1; ++t) F[2 + t] = mu * q[2 + t];
+    F[NV - 1] = u * (E + p);
+    Uc[0] = r;
+    Uc[1] = mu;
+#pragma unroll
+    for (int t = 0; t < NDIM - 1; ++t) Uc[2 + t] = r * q[2 + t];
+    Uc[NV - 1] = E;
+}
+
+// HLLC flux (rotated frame) with Davis wave-speed estimates; at S* = 0 the left
+// star state is used. Branch-free: the star state of the upwind side of the
+// contact is built once and the final flux is selected.
+template <int NDIM, typename Real>
+__device__ __forceinline__ void hllc(const Real (&qL)[2 + NDIM], const Real (&qR)[2 + NDIM], Real gamma,
+                                     Real inv_gm1, Real (&F)[2 + NDIM]) {
+    constexpr int NV = 2 + NDIM;
+    Real FL[NV], FR[NV], UL[NV], UR[NV];
+    flux_of<NDIM, Real>(qL, inv_gm1, FL, UL);
+    flux_of<NDIM, Real>(qR, inv_gm1, FR, UR);
+    const Real rL = qL[0], uL = qL[1], pL = qL[NV - 1];
+    const Real rR = qR[0], uR = qR[1], pR = qR[NV - 1];
+    // 1/rho_L and 1/rho_R from one reciprocal
+    const Real irLR = frcp(rL * rR);
+    const Real c2L = gamma * pL * (rR * irLR);
+    const Real c2R = gamma * pR * (rL * irLR);
+    const Real cL = c2L * frsq(c2L);
+    const Real cR = c2R * frsq(c2R);
+    const Real SL = fmin(uL - cL, uR - cR);
+    const Real SR = fmax(uL + cL, uR + cR);
+    const Real mL = rL * (SL - uL);
+    const Real mR = rR * (SR - uR);
+    const Real Ss = (pR - pL + uL * mL - uR * mR) * frcp(mL - mR);
+    const bool left = Ss >= Real(0);
+    const Real u = left ? uL : uR;
+    const Real p = left ? pL : pR;
+    const Real S = left ? SL : SR;
+    const Real m = left ? mL : mR;
+    // with X = m (S - S*): m/(S - S*) = m^2/X, 1/m = (S - S*)/X and
+    // 1/rho = (S - u)/m = (S - u)(S - S*)/X, all from one reciprocal
+    const Real dS = S - Ss;
+    const Real iX = frcp(m * dS);
+    const Real fac = m * m * iX;
+    const Real im = dS * iX;
+    const Real ir = (S - u) * im;
+    Real Us[NV], Fs[NV];
+    Us[0] = fac;
+    Us[1] = fac * Ss;
+#pragma unroll
+    for (int t = 0; t < NDIM - 1; ++t) Us[2 + t] = fac * (left ? qL[2 + t] : qR[2 + t]);
+    const Real EK = left ? UL[NV - 1] : UR[NV - 1];
+    Us[NV - 1] = fac * (EK * ir + (Ss - u) * (Ss + p * im));
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const Real Fk = left ? FL[k] : FR[k];
+        const Real Uk = left ? UL[k] : UR[k];
+        Fs[k] = fma(S, Us[k] - Uk, Fk);
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) F[k] = (SL >= Real(0)) ? FL[k] : ((SR <= Real(0)) ? FR[k] : Fs[k]);
+}
+
+template <int NDIM, int DIR, int R, typename Real>
+struct SweepCfg {
+    static constexpr int NV = 2 + NDIM;
+    static constexpr int SLEN = WAVE + 2 * R;
+    static constexpr int PITCH = SLEN | 1;
+    static constexpr int WPB = (DIR == 0) ? 4 : 8;  // pencils (waves) per block
+    static constexpr int THREADS = WPB * WAVE;
+    static constexpr size_t IN_BYTES = sizeof(Real) * NV * WPB * PITCH;
+    static constexpr int OPITCH = WPB + 1;  // padded row of the output tile (no bank conflicts)
+    static constexpr size_t OUT_BYTES = (DIR == 0) ? 0 : sizeof(double) * NV * TOUT * OPITCH;
+    static constexpr size_t SMEM = IN_BYTES > OUT_BYTES ? IN_BYTES : OUT_BYTES;
+};
+
+inline __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long w = __shfl_xor(v, o);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+// Finish one cell. FIN = false: accumulate the direction's contribution into
+// dU. FIN = true (last direction of an RK stage): form the stage output
+// (SSP-RK3, Shu-Osher form), check it is physical and, in stage 3, track the
+// CFL speed of the new state.
+template <int NDIM, bool FIN, typename Real>
+__device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long cell, const double (&d)[2 + NDIM],
+                                            const double (&pd)[2 + NDIM], const double (&pu)[2 + NDIM],
+                                            const double (&pn)[2 + NDIM], double dt, unsigned long long& smax) {
+    constexpr int NV = 2 + NDIM;
+    const long long nc = a.ncell;
+    if (!FIN) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) a.dU[k * nc + cell] = a.first ? d[k] : pd[k] + d[k];
+        return;
+    }
+    double o[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        const double L = a.first ? d[k] : pd[k] + d[k];
+        const double adv = pu[k] + dt * L;
+        double out;
+        if (a.stage == 1) out = adv;
+        else if (a.stage == 2) out = 0.75 * pn[k] + 0.25 * adv;
+        else out = (1.0 / 3.0) * pn[k] + (2.0 / 3.0) * adv;
+        a.Uout[k * nc + cell] = out;
+        o[k] = out;
+    }
+    const double rho = o[0];
+    const double irho = frcp(rho);
+    double ke = 0.0, vel[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int dd = 0; dd < NDIM; ++dd) {
+        vel[dd] = o[1 + dd] * irho;
+        ke += vel[dd] * o[1 + dd];
+    }
+    const double p = (a.gamma - 1.0) * (o[NV - 1] - 0.5 * ke);
+    if (!(rho > 0.0) || !(p > 0.0)) {
+        atomicOr(&a.ctl->err, 1);
+        atomicMin(&a.ctl->bad_cell, cell);
+    }
+    if (a.stage == 3) {
+        const double c = sqrt(a.gamma * p * irho);
+        double s = 0.0;
+#pragma unroll
+        for (int dd = 0; dd < NDIM; ++dd) s += (fabs(vel[dd]) + c) * a.inv_dx_all[dd];
+        // non-negative doubles order like their bit images; NaN sorts above +inf
+        const unsigned long long bits = (s != s) ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(s);
+        smax = bits > smax ? bits : smax;
+    }
+}
+
+// XCD-aware block order. Workgroups are dealt to the 8 XCDs round-robin by
+// index; renumber them so that each XCD gets one contiguous range of logical
+// blocks. Logical order is "band-major" in every direction (rows for x sweeps,
+// runs along y / z for y / z sweeps), so an XCD keeps working on roughly the
+// same slab of the grid in every sweep, and the slab's stage states and
+// accumulator stay in that XCD's L2 between kernels.
+inline __device__ __forceinline__ long long xcd_logical_block() {
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    const unsigned q8 = nb >> 3, r8 = nb & 7u, xcd = b & 7u;
+    return (long long)(xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3));
+}
+
+// One block of a sweep: logical block L of the problem's blocks.
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
+__device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long long L, unsigned char* smem,
+                                            unsigned long long* sred) {
+    using C = SweepCfg<NDIM, DIR, R, Real>;
+    constexpr int NV = C::NV, WPB = C::WPB, PITCH = C::PITCH, SLEN = C::SLEN, THREADS = C::THREADS;
+    Real* sV = reinterpret_cast<Real*>(smem);
+    double* sO = reinterpret_cast<double*>(smem);
+
+    double t0 = 0.0, dt = 0.0;
+    long long nstep = 0;
+    if (a.stage > 0) {
+        const bool go = step_go<FIN>(a.ctl, FIN && a.stage == 3, t0, dt, nstep);
+        if (a.step_start && L == 0 && threadIdx.x == 0) {
+            // mark the step as running (or not) and clear the next speed slot
+            a.ctl->started = go ? nstep : -1;
+            if (go) {
+#pragma unroll
+                for (int x = 0; x < 8; ++x) a.ctl->xcd[x].speed[(nstep + 1) & 1] = 0ull;
+            }
+        }
+        if (!go) return;
+    }
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int w = tid / WAVE;
+    const int N = a.n[DIR];
+    int seg;
+    long long grp;       // DIR 0: row group; else x group
+    long long other = 0; // z for DIR 1, y for DIR 2
+    const int nxb = (a.n[0] + WPB - 1) / WPB;
+    if (DIR == 0) {
+        seg = (int)(L % a.nseg);
+        grp = L / a.nseg;
+    } else if (DIR == 1) {
+        grp = L % nxb;
+        const long long t = L / nxb;
+        seg = (int)(t % a.nseg);
+        other = t / a.nseg;
+    } else {
+        grp = L % nxb;
+        const long long t = L / nxb;
+        other = t % a.n[1];
+        seg = (int)(t / a.n[1]);
+    }
+    const int s0 = (int)((long long)seg * N / a.nseg);
+    const int tseg = (int)((long long)(seg + 1) * N / a.nseg) - s0;
+    const int sbase = s0 - LEFT - R;
+    const long long nc = a.ncell;
+    const double gamma = a.gamma;
+
+    // ---- pencil geometry ----------------------------------------------------
+    long long stride;
+    long long blk_base;   // cell of column 0 at s = 0
+    int ncol_valid;       // pencils of this block that exist
+    if (DIR == 0) {
+        stride = 1;
+        const long long nrows = (long long)a.n[1] * a.n[2];
+        const long long row0 = grp * WPB;
+        blk_base = row0 * a.n[0];
+        ncol_valid = (int)((nrows - row0) < WPB ? (nrows - row0) : WPB);
+    } else {
+        const int xb = (int)grp * WPB;
+        stride = (DIR == 1) ? (long long)a.n[0] : (long long)a.n[0] * a.n[1];
+        blk_base = xb + other * (DIR == 1 ? (long long)a.n[0] * a.n[1] : (long long)a.n[0]);
+        ncol_valid = (a.n[0] - xb) < WPB ? (a.n[0] - xb) : WPB;
+    }
+    // column c of the block starts at blk_base + c * cstride
+    const long long cstride = (DIR == 0) ? (long long)a.n[0] : 1;
+
+    // ---- epilogue operands, fetched now so their latency hides behind the sweep
+    // Each thread finishes at most one cell: its own lane's cell in x sweeps,
+    // one cell of the transposed output tile in y / z sweeps.
+    static_assert(DIR == 0 || TOUT * WPB <= THREADS, "one epilogue cell per thread");
+    long long ecell = -1;
+    if (DIR == 0) {
+        if (w < ncol_valid && lane >= LEFT && lane < LEFT + tseg)
+            ecell = blk_base + w * cstride + (s0 + lane - LEFT);
+    } else {
+        const int row = tid / WPB, c = tid % WPB;
+        if (row < tseg && c < ncol_valid) ecell = blk_base + c * cstride + (long long)(s0 + row) * stride;
+    }
+    double pd[NV], pu[NV], pn[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) pd[k] = pu[k] = pn[k] = 0.0;
+    if (ecell >= 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            if (!a.first) pd[k] = a.dU[k * nc + ecell];
+            if (FIN && DIR == 0) pu[k] = a.U[k * nc + ecell];
+            if (FIN && a.stage >= 2) pn[k] = a.Un[k * nc + ecell];
+        }
+    }
+
+    // ---- load the stencil tile (rotated primitive variables) into LDS --------
+    {
+        constexpr int FS = WPB * PITCH;
+        if (DIR == 0) {
+            // the block's rows are loaded as one flat range, so only the last
+            // wave takes a partial second round
+            for (int idx = tid; idx < WPB * SLEN; idx += THREADS) {
+                const int c = idx / SLEN, pos = idx - c * SLEN;
+                double q[NV];
+                if (c < ncol_valid) {
+                    bool flip = false;
+                    const long long cell = blk_base + c * cstride +
+                                           (BCG ? ghost_src(sbase + pos, N, a.bc[0], a.bc[1], flip) : wrap(sbase + pos, N));
+                    double u[NV];
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) u[k] = a.U[k * nc + cell];
+                    if (BCG && flip) u[1 + DIR] = -u[1 + DIR];
+                    cons_to_rot<NDIM, DIR>(u, gamma, q);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) q[k] = (k == 0 || k == NV - 1) ? 1.0 : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < NV; ++k) sV[k * FS + c * PITCH + pos] = (Real)q[k];
+            }
+        } else {
+            // rows are dealt rotated by LEFT + R, so that in the first round thread
+            // t loads the cell it finishes in the epilogue (row t / WPB of the
+            // output tile) and keeps its float64 conserved values
+            const int c = tid % WPB;
+            constexpr int ROWS = THREADS / WPB;
+            for (int p = tid / WPB; p < SLEN; p += ROWS) {
+                const int idx = (p + LEFT + R) % SLEN;
+                double q[NV];
+                if (c < ncol_valid) {
+                    bool flip = false;
+                    const long long cell =
+                        blk_base + c * cstride +
+                        (long long)(BCG ? ghost_src(sbase + idx, N, a.bc[0], a.bc[1], flip) : wrap(sbase + idx, N)) * stride;
+                    double u[NV];
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) u[k] = a.U[k * nc + cell];
+                    if (FIN && p == tid / WPB && ecell >= 0) {
+#pragma unroll
+                        for (int k = 0; k < NV; ++k) pu[k] = u[k];
+                    }
+                    if (BCG && flip) u[1 + DIR] = -u[1 + DIR];
+                    cons_to_rot<NDIM, DIR>(u, gamma, q);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < NV; ++k) q[k] = (k == 0 || k == NV - 1) ? 1.0 : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < NV; ++k) sV[k * FS + c * PITCH + idx] = (Real)q[k];
+            }
+        }
+    }
+
+    __syncthreads();
+
+    // ---- per-lane reconstruction, face flux, correction, difference ----------
+    double dcons[NV];
+    {
+        constexpr int FS = WPB * PITCH;
+        const Real g = (Real)gamma;
+        const Real inv_gm1 = (Real)(1.0 / (gamma - 1.0));
+        Real qp[NV], qm[NV];
+        reconstruct<NDIM, R, Real, IK>(sV + w * PITCH, FS, lane, a.tab, g, a.positivity, qp, qm);
+        Real qR[NV], F[NV];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) qR[k] = __shfl_down(qm[k], 1);
+        hllc<NDIM, Real>(qp, qR, g, inv_gm1, F);
+        const Real alpha = Real(-1.0 / 24.0), beta = Real(3.0 / 640.0);
+        // This lane's face is x_{i+1/2} of cell i. At a reflecting wall the mirror
+        // ghosts make the fluxes of mass, tangential momentum and energy vanish
+        // (and the correction terms with them, by antisymmetry) up to rounding;
+        // they are set to exactly zero so that float32 sweeps conserve mass and
+        // energy in a closed box to float64 rounding as well.
+        const int icell = s0 - LEFT + lane;
+        const bool wall = BCG && ((a.bc[0] == 2 && icell == -1) || (a.bc[1] == 2 && icell == N - 1));
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const Real fm2 = __shfl_up(F[k], 2), fm1 = __shfl_up(F[k], 1);
+            const Real fp1 = __shfl_down(F[k], 1), fp2 = __shfl_down(F[k], 2);
+            const Real d2 = fm1 - Real(2) * F[k] + fp1;
+            const Real d4 = fm2 - Real(4) * fm1 + Real(6) * F[k] - Real(4) * fp1 + fp2;
+            const Real fh = (wall && k != 1) ? Real(0) : F[k] + alpha * d2 + beta * d4;
+            const Real fhm = __shfl_up(fh, 1);
+            dcons[cons_slot<NDIM, DIR>(k)] = -((double)fh - (double)fhm) * a.inv_dx;
+        }
+    }
+
+    unsigned long long smax = 0;
+    const bool lane_out = lane >= LEFT && lane < LEFT + tseg;
+    if (DIR == 0) {
+        if (ecell >= 0) finish_cell<NDIM, FIN, Real>(a, ecell, dcons, pd, pu, pn, dt, smax);
+    } else {
+        __syncthreads();  // every wave is done reading the stencil tile
+        if (lane_out) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) sO[(k * TOUT + (lane - LEFT)) * C::OPITCH + w] = dcons[k];
+        }
+        __syncthreads();
+        if (ecell >= 0) {
+            const int row = tid / WPB, c = tid % WPB;
+            double d[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) d[k] = sO[(k * TOUT + row) * C::OPITCH + c];
+            finish_cell<NDIM, FIN, Real>(a, ecell, d, pd, pu, pn, dt, smax);
+        }
+    }
+    if (FIN && a.stage == 3) {
+        // CFL speed of the new state into the next step's slot (one atomic per
+        // block, no return value), and block 0 closes the step by writing the
+        // next step state into the older record (see Ctl).
+        smax = wave_max_u64(smax);
+        if (lane == 0) sred[w] = smax;
+        __syncthreads();
+        if (tid == 0) {
+            unsigned long long m = sred[0];
+#pragma unroll
+            for (int i = 1; i < WPB; ++i) m = sred[i] > m ? sred[i] : m;
+            Ctl* c = a.ctl;
+            atomicMax(&c->xcd[blockIdx.x & 7u].speed[(nstep + 1) & 1], m);
+            if (L == 0) {
+                const int older = (c->rec[0].nsteps == nstep) ? 1 : 0;
+                c->rec[older].t = t0 + dt;
+                c->rec[older].dt = dt;
+                c->rec[older].nsteps = nstep + 1;
+            }
+        }
+    }
+}
+
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
+__global__ void __launch_bounds__(DIR == 0 ? 4 * WAVE : 8 * WAVE)
+sweep_kernel(const SweepArgs<Real> a) {
+    using C = SweepCfg<NDIM, DIR, R, Real>;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
+    __shared__ unsigned long long sred[C::WPB];
+    sweep_block<NDIM, DIR, R, Real, FIN, IK, BCG>(a, xcd_logical_block(), smem, sred);
+}
+
+// Batched sweep over many independent problems (same ndim, R, precision and
+// tables). Logical blocks are laid out problem after problem; owner[L] names
+// the problem of logical block L. Every block runs exactly the code of the
+// single-problem sweep on its own problem's data, so a problem's result does
+// not depend on what else is in the batch.
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
+__global__ void __launch_bounds__(DIR == 0 ? 4 * WAVE : 8 * WAVE)
+sweep_batch_kernel(const BatchArgs<Real> ba) {
+    using C = SweepCfg<NDIM, DIR, R, Real>;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
+    __shared__ unsigned long long sred[C::WPB];
+    const long long Lg = xcd_logical_block();
+    const int p = ba.owner[Lg];
+    const ProbDesc& P = ba.probs[p];
+    SweepArgs<Real> a;
+    a.U = P.U;
+    a.Un = P.Un;
+    a.dU = P.dU;
+    a.Uout = P.Uout;
+    a.ctl = P.ctl;
+    a.n[0] = P.n[0];
+    a.n[1] = P.n[1];
+    a.n[2] = P.n[2];
+    a.nseg = P.nseg;
+    a.ncell = P.ncell;
+    a.inv_dx = P.inv_dx;
+    a.inv_dx_all[0] = P.inv_dx_all[0];
+    a.inv_dx_all[1] = P.inv_dx_all[1];
+    a.inv_dx_all[2] = P.inv_dx_all[2];
+    a.gamma = P.gamma;
+    a.positivity = P.positivity;
+    a.bc[0] = P.bc[0];
+    a.bc[1] = P.bc[1];
+    a.first = ba.first;
+    a.stage = ba.stage;
+    a.step_start = ba.step_start;
+    a.tab = ba.tab;
+    sweep_block<NDIM, DIR, R, Real, FIN, IK, BCG>(a, Lg - P.block0, smem, sred);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
+hipError_t launch_one(const void* args, hipStream_t s) {
+    using C = SweepCfg<NDIM, DIR, R, Real>;
+    const SweepArgs<Real>& a = *static_cast<const SweepArgs<Real>*>(args);
+    long long groups;
+    if (DIR == 0) {
+        groups = ((long long)a.n[1] * a.n[2] + C::WPB - 1) / C::WPB;
+    } else {
+        const long long nxb = (a.n[0] + C::WPB - 1) / C::WPB;
+        groups = nxb * (DIR == 1 ? a.n[2] : a.n[1]);
+    }
+    const long long blocks = groups * a.nseg;
+    if (blocks <= 0 || blocks > INT_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep_kernel<NDIM, DIR, R, Real, FIN, IK, BCG>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+// A finishing kernel exists only for the last direction.
+template <int NDIM, int R, typename Real, int IK, bool BCG>
+hipError_t launch_dir(int dir, bool fin, const void* args, hipStream_t s) {
+    if (fin) {
+        if (dir != NDIM - 1) return hipErrorInvalidValue;
+        return launch_one<NDIM, NDIM - 1, R, Real, true, IK, BCG>(args, s);
+    }
+    if (dir == 0) return launch_one<NDIM, 0, R, Real, false, IK, BCG>(args, s);
+    if (NDIM >= 2 && dir == 1) return launch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false, IK, BCG>(args, s);
+    if (NDIM == 3 && dir == 2) return launch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false, IK, BCG>(args, s);
+    return hipErrorInvalidValue;
+}
+
+template <int NDIM, int R, typename Real, int IK>
+hipError_t launch_bcg(int dir, bool fin, bool bcg, const void* args, hipStream_t s) {
+    return bcg ? launch_dir<NDIM, R, Real, IK, true>(dir, fin, args, s)
+               : launch_dir<NDIM, R, Real, IK, false>(dir, fin, args, s);
+}
+
+// Indicator kinds: 0 for R = 1..3, 1 (Jiang-Shu) for R = 1, 2, 2 for R = 1..3,
+// 3 (adaptive order) for R = 2, 3.
+template <int NDIM, typename Real, int IK>
+hipError_t launch_rk(int dir, int R, bool fin, bool bcg, const void* args, hipStream_t s) {
+    switch (R) {
+        case 1:
+            if constexpr (IK != 3) return launch_bcg<NDIM, 1, Real, IK>(dir, fin, bcg, args, s);
+            return hipErrorInvalidValue;
+        case 2: return launch_bcg<NDIM, 2, Real, IK>(dir, fin, bcg, args, s);
+        case 3:
+            if constexpr (IK != 1) return launch_bcg<NDIM, 3, Real, IK>(dir, fin, bcg, args, s);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int NDIM, typename Real>
+hipError_t launch_r(int dir, int R, bool fin, int ik, bool bcg, const void* args, hipStream_t s) {
+    switch (ik) {
+        case 0: return launch_rk<NDIM, Real, 0>(dir, R, fin, bcg, args, s);
+        case 1: return launch_rk<NDIM, Real, 1>(dir, R, fin, bcg, args, s);
+        case 2: return launch_rk<NDIM, Real, 2>(dir, R, fin, bcg, args, s);
+        case 3: return launch_rk<NDIM, Real, 3>(dir, R, fin, bcg, args, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
+hipError_t launch_batch_one(const void* args, long long blocks, hipStream_t s) {
+    using C = SweepCfg<NDIM, DIR, R, Real>;
+    const BatchArgs<Real>& a = *static_cast<const BatchArgs<Real>*>(args);
+    if (blocks <= 0 || blocks > INT_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep_batch_kernel<NDIM, DIR, R, Real, FIN, IK, BCG>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
+                       a);
+    return hipGetLastError();
+}
+
+template <int NDIM, int R, typename Real, int IK, bool BCG>
+hipError_t launch_batch_dir(int dir, bool fin, const void* args, long long blocks, hipStream_t s) {
+    if (fin) {
+        if (dir != NDIM - 1) return hipErrorInvalidValue;
+        return launch_batch_one<NDIM, NDIM - 1, R, Real, true, IK, BCG>(args, blocks, s);
+    }
+    if (dir == 0) return launch_batch_one<NDIM, 0, R, Real, false, IK, BCG>(args, blocks, s);
+    if (NDIM >= 2 && dir == 1)
+        return launch_batch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false, IK, BCG>(args, blocks, s);
+    if (NDIM == 3 && dir == 2)
+        return launch_batch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false, IK, BCG>(args, blocks, s);
+    return hipErrorInvalidValue;
+}
+
+template <int NDIM, int R, typename Real, int IK>
+hipError_t launch_batch_bcg(int dir, bool fin, bool bcg, const void* args, long long blocks, hipStream_t s) {
+    return bcg ? launch_batch_dir<NDIM, R, Real, IK, true>(dir, fin, args, blocks, s)
+               : launch_batch_dir<NDIM, R, Real, IK, false>(dir, fin, args, blocks, s);
+}
+
+template <int NDIM, typename Real, int IK>
+hipError_t launch_batch_rk(int dir, int R, bool fin, bool bcg, const void* args, long long blocks, hipStream_t s) {
+    switch (R) {
+        case 1:
+            if constexpr (IK != 3) return launch_batch_bcg<NDIM, 1, Real, IK>(dir, fin, bcg, args, blocks, s);
+            return hipErrorInvalidValue;
+        case 2: return launch_batch_bcg<NDIM, 2, Real, IK>(dir, fin, bcg, args, blocks, s);
+        case 3:
+            if constexpr (IK != 1) return launch_batch_bcg<NDIM, 3, Real, IK>(dir, fin, bcg, args, blocks, s);
+            return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int NDIM, typename Real>
+hipError_t launch_batch_r(int dir, int R, bool fin, int ik, bool bcg, const void* args, long long blocks,
+                          hipStream_t s) {
+    switch (ik) {
+        case 0: return launch_batch_rk<NDIM, Real, 0>(dir, R, fin, bcg, args, blocks, s);
+        case 1: return launch_batch_rk<NDIM, Real, 1>(dir, R, fin, bcg, args, blocks, s);
+        case 2: return launch_batch_rk<NDIM, Real, 2>(dir, R, fin, bcg, args, blocks, s);
+        case 3: return launch_batch_rk<NDIM, Real, 3>(dir, R, fin, bcg, args, blocks, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+
+}  // namespace gpw
