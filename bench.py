@@ -301,8 +301,9 @@ def main():
                 s.step_kernel(k)
             e1.record(s.stream)
             e1.synchronize()
-            d = k % grid.ndim
-            fin = d == grid.ndim - 1
+            # sweeps of a stage run z, y, x; the x sweep finishes the stage
+            d = grid.ndim - 1 - k % grid.ndim
+            fin = d == 0
             # template arguments: ndim, dir, R, real type, finishes the stage,
             # indicator kind (0: GP), general boundaries (periodic: false)
             sym = f"sweep_kernel<{grid.ndim}, {d}, {R}, {real}, {'true' if fin else 'false'}, 0, false>"

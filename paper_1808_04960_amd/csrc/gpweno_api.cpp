@@ -111,6 +111,12 @@ gpw::SweepArgs<Real> base_args(const gpweno_ctx* c, int dir) {
     return a;
 }
 
+// Direction of the j-th sweep of an RK stage: z, y, then x. The last sweep
+// finishes the stage (RK combination, physical check, CFL speed), and running
+// it along x keeps that epilogue's reads and writes contiguous per wave
+// without a transpose through LDS.
+int sweep_dir(int ndim, int j) { return ndim - 1 - j; }
+
 // Smoothness-indicator kind of the kernels (see launch_sweep).
 int indicator_kind(const gpweno_ctx* c) {
     if (c->scheme == GPWENO_GP_AO) return 3;
@@ -145,13 +151,14 @@ int launch(gpweno_ctx* c, int dir, const double* in, const double* un, double* a
     return GPWENO_OK;
 }
 
-// The k-th launch of a step: stage k / ndim + 1, direction k % ndim.
+// The k-th launch of a step: stage k / ndim + 1, sweep j = k % ndim of the
+// stage in the direction sweep_dir(ndim, j).
 int launch_step_kernel(gpweno_ctx* c, int k, hipStream_t s) {
     const int ndim = c->grid.ndim;
-    const int stage = k / ndim + 1, dir = k % ndim;
+    const int stage = k / ndim + 1, j = k % ndim, dir = sweep_dir(ndim, j);
     const double* ins[3] = {c->state, c->U1, c->U2};
     double* outs[3] = {c->U1, c->U2, c->state};
-    return launch(c, dir, ins[stage - 1], c->state, c->dU, outs[stage - 1], stage, dir == ndim - 1, dir == 0,
+    return launch(c, dir, ins[stage - 1], c->state, c->dU, outs[stage - 1], stage, j == ndim - 1, j == 0,
                   k == 0, s);
 }
 
@@ -668,15 +675,15 @@ void batch_drop_graph(gpweno_batch* b) {
 
 // One batched launch: position k of the step sequence for group g.
 int batch_launch(gpweno_batch* b, const BatchGroup& g, int k, hipStream_t s) {
-    const int stage = k / g.ndim + 1, dir = k % g.ndim;
-    const bool fin = dir == g.ndim - 1;
+    const int stage = k / g.ndim + 1, j = k % g.ndim, dir = sweep_dir(g.ndim, j);
+    const bool fin = j == g.ndim - 1;
     hipError_t e;
     if (g.fp32) {
         gpw::BatchArgs<float> a;
         std::memset(&a, 0, sizeof a);
         a.probs = b->d_desc + g.desc_off[stage - 1][dir];
         a.owner = b->d_owner + g.owner_off[dir];
-        a.first = dir == 0;
+        a.first = j == 0;
         a.stage = stage;
         a.step_start = k == 0;
         a.tab = g.proto->tabf[0];
@@ -687,7 +694,7 @@ int batch_launch(gpweno_batch* b, const BatchGroup& g, int k, hipStream_t s) {
         std::memset(&a, 0, sizeof a);
         a.probs = b->d_desc + g.desc_off[stage - 1][dir];
         a.owner = b->d_owner + g.owner_off[dir];
-        a.first = dir == 0;
+        a.first = j == 0;
         a.stage = stage;
         a.step_start = k == 0;
         a.tab = g.proto->tabd[0];

@@ -894,12 +894,12 @@ hipError_t launch_one(const void* args, hipStream_t s) {
     return hipGetLastError();
 }
 
-// A finishing kernel exists only for the last direction.
+// A finishing kernel exists only for x, the last direction of a stage.
 template <int NDIM, int R, typename Real, int IK, bool BCG>
 hipError_t launch_dir(int dir, bool fin, const void* args, hipStream_t s) {
     if (fin) {
-        if (dir != NDIM - 1) return hipErrorInvalidValue;
-        return launch_one<NDIM, NDIM - 1, R, Real, true, IK, BCG>(args, s);
+        if (dir != 0) return hipErrorInvalidValue;
+        return launch_one<NDIM, 0, R, Real, true, IK, BCG>(args, s);
     }
     if (dir == 0) return launch_one<NDIM, 0, R, Real, false, IK, BCG>(args, s);
     if (NDIM >= 2 && dir == 1) return launch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false, IK, BCG>(args, s);
@@ -954,8 +954,8 @@ hipError_t launch_batch_one(const void* args, long long blocks, hipStream_t s) {
 template <int NDIM, int R, typename Real, int IK, bool BCG>
 hipError_t launch_batch_dir(int dir, bool fin, const void* args, long long blocks, hipStream_t s) {
     if (fin) {
-        if (dir != NDIM - 1) return hipErrorInvalidValue;
-        return launch_batch_one<NDIM, NDIM - 1, R, Real, true, IK, BCG>(args, blocks, s);
+        if (dir != 0) return hipErrorInvalidValue;
+        return launch_batch_one<NDIM, 0, R, Real, true, IK, BCG>(args, blocks, s);
     }
     if (dir == 0) return launch_batch_one<NDIM, 0, R, Real, false, IK, BCG>(args, blocks, s);
     if (NDIM >= 2 && dir == 1)
