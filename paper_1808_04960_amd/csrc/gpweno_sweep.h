@@ -686,7 +686,6 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             if (!a.first) pd[k] = a.dU[k * nc + ecell];
-            if (FIN && DIR == 0) pu[k] = a.U[k * nc + ecell];
             if (FIN && a.stage >= 2) pn[k] = a.Un[k * nc + ecell];
         }
     }
@@ -695,10 +694,22 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     {
         constexpr int FS = WPB * PITCH;
         if (DIR == 0) {
-            // the block's rows are loaded as one flat range, so only the last
-            // wave takes a partial second round
-            for (int idx = tid; idx < WPB * SLEN; idx += THREADS) {
-                const int c = idx / SLEN, pos = idx - c * SLEN;
+            // round 0: lane l of wave w loads tile position l + R of row w, its own
+            // cell, and keeps that cell's float64 conserved values for the
+            // epilogue; round 1: the first WPB * 2R threads load the 2R halo
+            // positions of every row (0 .. R-1 and 64 + R .. 64 + 2R - 1)
+#pragma unroll
+            for (int round = 0; round < 2; ++round) {
+                int c, pos;
+                if (round == 0) {
+                    c = w;
+                    pos = lane + R;
+                } else {
+                    if (tid >= WPB * 2 * R) break;
+                    c = tid / (2 * R);
+                    const int j = tid - c * (2 * R);
+                    pos = j < R ? j : WAVE + j;
+                }
                 double q[NV];
                 if (c < ncol_valid) {
                     bool flip = false;
@@ -707,6 +718,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
                     double u[NV];
 #pragma unroll
                     for (int k = 0; k < NV; ++k) u[k] = a.U[k * nc + cell];
+                    if (FIN && round == 0 && ecell >= 0) {
+#pragma unroll
+                        for (int k = 0; k < NV; ++k) pu[k] = u[k];
+                    }
                     if (BCG && flip) u[1 + DIR] = -u[1 + DIR];
                     cons_to_rot<NDIM, DIR>(u, gamma, q);
                 } else {
