@@ -1,14 +1,14 @@
 // GP-WENO FD-Prim sweep kernels for gfx950 (CDNA4, wave64).
 //
 // One kernel launch evaluates one direction's contribution to the right-hand
-// side of Eq. (disc_fd) for every cell, and in the last direction of an RK
-// stage also finishes the stage. Work decomposition:
+// side of Eq. (disc_fd) for every cell. The sweeps of an RK stage run z, y, x,
+// and the x sweep also finishes the stage. Work decomposition:
 //
 //   * A "run" is 64 consecutive cells of one pencil along the sweep axis,
 //     mapped one cell per lane of a wave. Each lane reconstructs the Riemann
 //     states of its cell (stencil of 2R+1 cells read from LDS), the wave then
-//     forms face fluxes, corrected fluxes and flux differences with cross-lane
-//     shuffles. The flux correction needs face fluxes two faces either side
+//     forms face fluxes, corrected fluxes and flux differences exchanging
+//     neighbouring lanes' values with DPP wave shifts. The flux correction needs face fluxes two faces either side
 //     and the difference one more face, so lanes 3..60 produce output: a run
 //     yields 58 cells, and consecutive runs overlap by 6 cells.
 //   * A block holds several pencils (one wave each) and the same run segment.
@@ -18,8 +18,8 @@
 //   * x sweeps: each wave loads its own row (contiguous along x) and writes its
 //     outputs directly (contiguous). y/z sweeps: a block holds 8 adjacent
 //     x-columns, so every global access covers 8 consecutive doubles; the
-//     outputs are transposed through LDS so the read-modify-write epilogue is
-//     also x-contiguous.
+//     outputs are transposed through LDS so the accumulator's read-modify-write
+//     is also x-contiguous.
 //
 // Per cell (paper references):
 //   characteristic projection of the primitive stencil at the centre cell
@@ -81,6 +81,31 @@ template <> inline __device__ __forceinline__ double frsq<double>(double x) {
     y = fma(0.5 * y, e, y);
     e = fma(-x * y, y, 1.0);
     return fma(0.5 * y, e, y);
+}
+
+// Value of the neighbouring lane across the whole wave, by DPP wave shifts
+// (wave_shr:1 / wave_shl:1): lane_prev gives lane l the value of lane l-1,
+// lane_next the value of lane l+1; the lane without a neighbour gets 0 (its
+// result is never used: a run's outputs come from lanes 3..60). One VALU move,
+// which the compiler can fold into the consuming instruction, instead of a
+// permute through the LDS crossbar.
+inline __device__ __forceinline__ float lane_prev(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xF, 0xF, true));
+}
+inline __device__ __forceinline__ float lane_next(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xF, 0xF, true));
+}
+inline __device__ __forceinline__ double lane_prev(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x138, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+inline __device__ __forceinline__ double lane_next(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x130, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // Periodic index. For n >= 64 every index a sweep forms lies in [-n, 2n), so a
@@ -776,7 +801,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
         reconstruct<NDIM, R, Real, IK>(sV + w * PITCH, FS, lane, a.tab, g, a.positivity, qp, qm);
         Real qR[NV], F[NV];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) qR[k] = __shfl_down(qm[k], 1);
+        for (int k = 0; k < NV; ++k) qR[k] = lane_next(qm[k]);
         hllc<NDIM, Real>(qp, qR, g, inv_gm1, F);
         const Real alpha = Real(-1.0 / 24.0), beta = Real(3.0 / 640.0);
         // This lane's face is x_{i+1/2} of cell i. At a reflecting wall the mirror
@@ -788,12 +813,12 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
         const bool wall = BCG && ((a.bc[0] == 2 && icell == -1) || (a.bc[1] == 2 && icell == N - 1));
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
-            const Real fm2 = __shfl_up(F[k], 2), fm1 = __shfl_up(F[k], 1);
-            const Real fp1 = __shfl_down(F[k], 1), fp2 = __shfl_down(F[k], 2);
+            const Real fm1 = lane_prev(F[k]), fm2 = lane_prev(fm1);
+            const Real fp1 = lane_next(F[k]), fp2 = lane_next(fp1);
             const Real d2 = fm1 - Real(2) * F[k] + fp1;
             const Real d4 = fm2 - Real(4) * fm1 + Real(6) * F[k] - Real(4) * fp1 + fp2;
             const Real fh = (wall && k != 1) ? Real(0) : F[k] + alpha * d2 + beta * d4;
-            const Real fhm = __shfl_up(fh, 1);
+            const Real fhm = lane_prev(fh);
             dcons[cons_slot<NDIM, DIR>(k)] = -((double)fh - (double)fhm) * a.inv_dx;
         }
     }
