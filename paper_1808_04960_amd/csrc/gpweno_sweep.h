@@ -719,9 +719,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     {
         constexpr int FS = WPB * PITCH;
         if (DIR == 0) {
-            // round 0: lane l of wave w loads tile position l + R of row w, its own
-            // cell, and keeps that cell's float64 conserved values for the
-            // epilogue; round 1: the first WPB * 2R threads load the 2R halo
+            // first pass: lane l of wave w loads tile position l + R of row w, its
+            // own cell, and keeps that cell's float64 conserved values for the
+            // epilogue; second pass: the first WPB * 2R threads load the 2R halo
             // positions of every row (0 .. R-1 and 64 + R .. 64 + 2R - 1)
 #pragma unroll
             for (int round = 0; round < 2; ++round) {
