@@ -202,6 +202,21 @@ def test_nonphysical_state_is_reported():
         s.run(1.0, max_steps=3)
 
 
+def test_run_that_cannot_advance_time_fails_instead_of_spinning():
+    """At t = 1e20 a step of 1 does not change t in float64: the run loop sees a
+    replay that moves neither the time nor the end condition and reports it
+    (every kernel still runs and exits normally)."""
+    announce("stalled run")
+    g = inputs.grid1d(64)
+    U = inputs.uniform_state(g)    # stays exactly uniform whatever the step
+    dx = g.dx[0]
+    s = gw.Solver(g, 2, 12 * dx, 3 * dx, fixed_dt=1.0, U0=U)
+    s.set_state(U, t=1e20)
+    with pytest.raises(gw.GpwenoError) as e:
+        s.run(2e20)
+    assert e.value.code == gw.ESTATE and "stalled" in str(e.value)
+
+
 def test_fixed_dt_matches_oracle():
     announce("fixed dt")
     g, U = inputs.sine_wave_1d(64)
