@@ -102,6 +102,7 @@ gpw::SweepArgs<Real> base_args(const gpweno_ctx* c, int dir) {
     a.inv_dx = 1.0 / c->dx[dir];
     for (int d = 0; d < 3; ++d) a.inv_dx_all[d] = d < c->grid.ndim ? 1.0 / c->dx[d] : 0.0;
     a.gamma = c->gamma;
+    a.inv_gm1 = 1.0 / (c->gamma - 1.0);
     a.positivity = c->opt.positivity_fallback ? 1 : 0;
     a.bc[0] = c->grid.bc[dir][0];
     a.bc[1] = c->grid.bc[dir][1];
@@ -828,6 +829,7 @@ int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stre
                     P.inv_dx = 1.0 / c->dx[dir];
                     for (int d = 0; d < 3; ++d) P.inv_dx_all[d] = d < c->grid.ndim ? 1.0 / c->dx[d] : 0.0;
                     P.gamma = c->gamma;
+                    P.inv_gm1 = 1.0 / (c->gamma - 1.0);
                     P.positivity = c->opt.positivity_fallback ? 1 : 0;
                     P.bc[0] = c->grid.bc[dir][0];
                     P.bc[1] = c->grid.bc[dir][1];

@@ -88,6 +88,7 @@ struct SweepArgs {
     double inv_dx;      // 1/dx along the sweep axis
     double inv_dx_all[3];
     double gamma;
+    double inv_gm1;     // 1/(gamma - 1)
     int first;          // first direction: the accumulator starts at zero
     int stage;          // 0: right-hand side only; 1..3: SSP-RK3 stage
     int positivity;     // positivity fallback of the Riemann states
@@ -110,6 +111,7 @@ struct ProbDesc {
     double inv_dx;
     double inv_dx_all[3];
     double gamma;
+    double inv_gm1;     // 1/(gamma - 1)
     int positivity;
     int bc[2];          // boundary kinds of the sweep axis (low, high side)
     unsigned nblk;      // logical blocks of this problem in the launch

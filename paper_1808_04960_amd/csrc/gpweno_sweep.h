@@ -16,8 +16,8 @@
 //     from HBM (ghost positions: periodic image, outflow copy or mirror image),
 //     converted to rotated primitive variables and staged in LDS.
 //   * x sweeps: each wave loads its own row (contiguous along x) and writes its
-//     outputs directly (contiguous). y/z sweeps: a block holds 8 adjacent
-//     x-columns, so every global access covers 8 consecutive doubles; the
+//     outputs directly (contiguous). y/z sweeps: a block holds 4 adjacent
+//     x-columns, so every global access covers 4 consecutive doubles; the
 //     outputs are transposed through LDS so the accumulator's read-modify-write
 //     is also x-contiguous.
 //
@@ -44,6 +44,12 @@ namespace gpw {
 constexpr int WAVE = 64;
 constexpr int LEFT = 3;             // first output lane of a run
 constexpr int TOUT = WAVE - 6;      // outputs per run
+
+// Pencils (waves) per block: 4 rows in x sweeps, 4 adjacent x columns in y/z
+// sweeps. Four-wave blocks fill the register-limited wave slots of a compute
+// unit without stranding any, and spread small grids evenly over the compute
+// units (eight-wave y blocks left a 512^2 grid at 2.25 blocks per unit).
+__host__ __device__ constexpr int sweep_wpb(int) { return 4; }
 
 __host__ __device__ constexpr int t1_axis(int dir) { return dir == 0 ? 1 : 0; }
 __host__ __device__ constexpr int t2_axis(int dir) { return dir == 2 ? 1 : 2; }
@@ -541,7 +547,7 @@ struct SweepCfg {
     static constexpr int NV = 2 + NDIM;
     static constexpr int SLEN = WAVE + 2 * R;
     static constexpr int PITCH = SLEN | 1;
-    static constexpr int WPB = (DIR == 0) ? 4 : 8;  // pencils (waves) per block
+    static constexpr int WPB = sweep_wpb(DIR);  // pencils (waves) per block
     static constexpr int THREADS = WPB * WAVE;
     static constexpr size_t IN_BYTES = sizeof(Real) * NV * WPB * PITCH;
     static constexpr int OPITCH = WPB + 1;  // padded row of the output tile (no bank conflicts)
@@ -558,11 +564,21 @@ inline __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long 
     return v;
 }
 
+// Store of a sweep output. x sweeps write whole rows with non-temporal
+// stores: the rows bypass L2, so the writeback of dirty lines at the end of
+// the kernel has nothing left to do (on a 512^2 grid that writeback held each
+// launch up by about 2 us). y/z sweeps write partial lines and keep L2.
+template <bool NT>
+__device__ __forceinline__ void put(double* p, double v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // Finish one cell. FIN = false: accumulate the direction's contribution into
 // dU. FIN = true (last direction of an RK stage): form the stage output
 // (SSP-RK3, Shu-Osher form), check it is physical and, in stage 3, track the
 // CFL speed of the new state.
-template <int NDIM, bool FIN, typename Real>
+template <int NDIM, bool FIN, typename Real, bool NT>
 __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long cell, const double (&d)[2 + NDIM],
                                             const double (&pd)[2 + NDIM], const double (&pu)[2 + NDIM],
                                             const double (&pn)[2 + NDIM], double dt, unsigned long long& smax) {
@@ -570,7 +586,7 @@ __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long 
     const long long nc = a.ncell;
     if (!FIN) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) a.dU[k * nc + cell] = a.first ? d[k] : pd[k] + d[k];
+        for (int k = 0; k < NV; ++k) put<NT>(&a.dU[k * nc + cell], a.first ? d[k] : pd[k] + d[k]);
         return;
     }
     double o[NV];
@@ -582,7 +598,7 @@ __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long 
         if (a.stage == 1) out = adv;
         else if (a.stage == 2) out = 0.75 * pn[k] + 0.25 * adv;
         else out = (1.0 / 3.0) * pn[k] + (2.0 / 3.0) * adv;
-        a.Uout[k * nc + cell] = out;
+        put<NT>(&a.Uout[k * nc + cell], out);
         o[k] = out;
     }
     const double rho = o[0];
@@ -630,6 +646,97 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     Real* sV = reinterpret_cast<Real*>(smem);
     double* sO = reinterpret_cast<double*>(smem);
 
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int w = tid / WAVE;
+    const int N = a.n[DIR];
+    // Block geometry in 32-bit arithmetic: logical blocks number below 2^31
+    // (checked at launch). Segment seg of a pencil covers cells s0 .. s0 + tseg
+    // - 1; the first N % nseg segments take one cell more than the others.
+    const unsigned Lu = (unsigned)L, nseg = (unsigned)a.nseg;
+    unsigned seg, grp, other = 0;  // grp: row group (DIR 0) or x group; other: z (DIR 1) or y (DIR 2)
+    const unsigned nxb = ((unsigned)a.n[0] + WPB - 1) / WPB;
+    if (DIR == 0) {
+        seg = Lu % nseg;
+        grp = Lu / nseg;
+    } else if (DIR == 1) {
+        grp = Lu % nxb;
+        const unsigned t = Lu / nxb;
+        seg = t % nseg;
+        other = t / nseg;
+    } else {
+        grp = Lu % nxb;
+        const unsigned t = Lu / nxb;
+        other = t % (unsigned)a.n[1];
+        seg = t / (unsigned)a.n[1];
+    }
+    const unsigned sq = (unsigned)N / nseg, sr = (unsigned)N % nseg;
+    const int s0 = (int)(seg * sq + (seg < sr ? seg : sr));
+    const int tseg = (int)(sq + (seg < sr ? 1u : 0u));
+    const int sbase = s0 - LEFT - R;
+    const long long nc = a.ncell;
+    const double gamma = a.gamma;
+
+    // ---- pencil geometry ----------------------------------------------------
+    long long stride;
+    long long blk_base;   // cell of column 0 at s = 0
+    int ncol_valid;       // pencils of this block that exist
+    if (DIR == 0) {
+        stride = 1;
+        const long long nrows = (long long)a.n[1] * a.n[2];
+        const long long row0 = (long long)grp * WPB;
+        blk_base = row0 * a.n[0];
+        ncol_valid = (int)((nrows - row0) < WPB ? (nrows - row0) : WPB);
+    } else {
+        const int xb = (int)grp * WPB;
+        stride = (DIR == 1) ? (long long)a.n[0] : (long long)a.n[0] * a.n[1];
+        blk_base = xb + (long long)other * (DIR == 1 ? (long long)a.n[0] * a.n[1] : (long long)a.n[0]);
+        ncol_valid = (a.n[0] - xb) < WPB ? (a.n[0] - xb) : WPB;
+    }
+    // column c of the block starts at blk_base + c * cstride
+    const long long cstride = (DIR == 0) ? (long long)a.n[0] : 1;
+
+    // ---- the stencil tile's float64 conserved values ---------------------------
+    // Every tile load of a thread is issued before any of them is used, so a
+    // block waits for one round trip before it computes.
+    // x sweeps: pass 0, lane l of wave w loads tile position l + R of row w (its
+    // own cell); pass 1, lanes 0 .. 2R-1 of wave w load row w's halo positions
+    // 0 .. R-1 and 64 + R .. 64 + 2R - 1.
+    // y/z sweeps: tile rows are dealt rotated by LEFT + R, so that in pass 0
+    // thread t loads the cell it finishes in the epilogue (row t / WPB of the
+    // output tile); pass 1 covers the remaining 2R rows.
+    constexpr int FS = WPB * PITCH;
+    int tcol, tpos[2];
+    bool tact1;
+    if (DIR == 0) {
+        tcol = w;
+        tpos[0] = lane + R;
+        tpos[1] = lane < R ? lane : WAVE + lane;
+        tact1 = lane < 2 * R;
+    } else {
+        constexpr int ROWS = THREADS / WPB;
+        static_assert(SLEN <= 2 * ROWS, "two passes cover the tile");
+        tcol = tid % WPB;
+        const int p = tid / WPB;
+        tpos[0] = (p + LEFT + R) % SLEN;
+        tpos[1] = (p + ROWS + LEFT + R) % SLEN;
+        tact1 = p + ROWS < SLEN;
+    }
+    const bool tcol_ok = tcol < ncol_valid;
+    double u[2][NV];
+    bool flip[2] = {false, false};
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        if (tcol_ok && (r == 0 || tact1)) {
+            const int src = BCG ? ghost_src(sbase + tpos[r], N, a.bc[0], a.bc[1], flip[r]) : wrap(sbase + tpos[r], N);
+            const long long cell = blk_base + tcol * cstride + (long long)src * stride;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) u[r][k] = a.U[k * nc + cell];
+        }
+    }
+
+    // ---- step control: read after the tile loads are in flight, so the two
+    // round trips overlap (a halted step's loads are simply dropped)
     double t0 = 0.0, dt = 0.0;
     long long nstep = 0;
     if (a.stage > 0) {
@@ -645,54 +752,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
         if (!go) return;
     }
 
-    const int tid = threadIdx.x;
-    const int lane = tid & (WAVE - 1);
-    const int w = tid / WAVE;
-    const int N = a.n[DIR];
-    int seg;
-    long long grp;       // DIR 0: row group; else x group
-    long long other = 0; // z for DIR 1, y for DIR 2
-    const int nxb = (a.n[0] + WPB - 1) / WPB;
-    if (DIR == 0) {
-        seg = (int)(L % a.nseg);
-        grp = L / a.nseg;
-    } else if (DIR == 1) {
-        grp = L % nxb;
-        const long long t = L / nxb;
-        seg = (int)(t % a.nseg);
-        other = t / a.nseg;
-    } else {
-        grp = L % nxb;
-        const long long t = L / nxb;
-        other = t % a.n[1];
-        seg = (int)(t / a.n[1]);
-    }
-    const int s0 = (int)((long long)seg * N / a.nseg);
-    const int tseg = (int)((long long)(seg + 1) * N / a.nseg) - s0;
-    const int sbase = s0 - LEFT - R;
-    const long long nc = a.ncell;
-    const double gamma = a.gamma;
-
-    // ---- pencil geometry ----------------------------------------------------
-    long long stride;
-    long long blk_base;   // cell of column 0 at s = 0
-    int ncol_valid;       // pencils of this block that exist
-    if (DIR == 0) {
-        stride = 1;
-        const long long nrows = (long long)a.n[1] * a.n[2];
-        const long long row0 = grp * WPB;
-        blk_base = row0 * a.n[0];
-        ncol_valid = (int)((nrows - row0) < WPB ? (nrows - row0) : WPB);
-    } else {
-        const int xb = (int)grp * WPB;
-        stride = (DIR == 1) ? (long long)a.n[0] : (long long)a.n[0] * a.n[1];
-        blk_base = xb + other * (DIR == 1 ? (long long)a.n[0] * a.n[1] : (long long)a.n[0]);
-        ncol_valid = (a.n[0] - xb) < WPB ? (a.n[0] - xb) : WPB;
-    }
-    // column c of the block starts at blk_base + c * cstride
-    const long long cstride = (DIR == 0) ? (long long)a.n[0] : 1;
-
-    // ---- epilogue operands, fetched now so their latency hides behind the sweep
+    // ---- the cell each thread finishes ---------------------------------------
     // Each thread finishes at most one cell: its own lane's cell in x sweeps,
     // one cell of the transposed output tile in y / z sweeps.
     static_assert(DIR == 0 || TOUT * WPB <= THREADS, "one epilogue cell per thread");
@@ -707,6 +767,30 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     double pd[NV], pu[NV], pn[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) pd[k] = pu[k] = pn[k] = 0.0;
+
+    // ---- convert to rotated primitive variables and stage in LDS --------------
+    // Pass 0 of the thread that finishes a cell loaded that very cell; its
+    // float64 conserved values are kept for the epilogue.
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        if (r == 1 && !tact1) break;
+        double q[NV];
+        if (tcol_ok) {
+            if (FIN && r == 0 && ecell >= 0) {
+#pragma unroll
+                for (int k = 0; k < NV; ++k) pu[k] = u[0][k];
+            }
+            if (BCG && flip[r]) u[r][1 + DIR] = -u[r][1 + DIR];
+            cons_to_rot<NDIM, DIR>(u[r], gamma, q);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) q[k] = (k == 0 || k == NV - 1) ? 1.0 : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sV[k * FS + tcol * PITCH + tpos[r]] = (Real)q[k];
+    }
+
+    // ---- epilogue operands: requested now, they arrive while the sweep computes
     if (ecell >= 0) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
@@ -715,88 +799,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
         }
     }
 
-    // ---- load the stencil tile (rotated primitive variables) into LDS --------
-    {
-        constexpr int FS = WPB * PITCH;
-        if (DIR == 0) {
-            // first pass: lane l of wave w loads tile position l + R of row w, its
-            // own cell, and keeps that cell's float64 conserved values for the
-            // epilogue; second pass: the first WPB * 2R threads load the 2R halo
-            // positions of every row (0 .. R-1 and 64 + R .. 64 + 2R - 1)
-#pragma unroll
-            for (int round = 0; round < 2; ++round) {
-                int c, pos;
-                if (round == 0) {
-                    c = w;
-                    pos = lane + R;
-                } else {
-                    if (tid >= WPB * 2 * R) break;
-                    c = tid / (2 * R);
-                    const int j = tid - c * (2 * R);
-                    pos = j < R ? j : WAVE + j;
-                }
-                double q[NV];
-                if (c < ncol_valid) {
-                    bool flip = false;
-                    const long long cell = blk_base + c * cstride +
-                                           (BCG ? ghost_src(sbase + pos, N, a.bc[0], a.bc[1], flip) : wrap(sbase + pos, N));
-                    double u[NV];
-#pragma unroll
-                    for (int k = 0; k < NV; ++k) u[k] = a.U[k * nc + cell];
-                    if (FIN && round == 0 && ecell >= 0) {
-#pragma unroll
-                        for (int k = 0; k < NV; ++k) pu[k] = u[k];
-                    }
-                    if (BCG && flip) u[1 + DIR] = -u[1 + DIR];
-                    cons_to_rot<NDIM, DIR>(u, gamma, q);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < NV; ++k) q[k] = (k == 0 || k == NV - 1) ? 1.0 : 0.0;
-                }
-#pragma unroll
-                for (int k = 0; k < NV; ++k) sV[k * FS + c * PITCH + pos] = (Real)q[k];
-            }
-        } else {
-            // rows are dealt rotated by LEFT + R, so that in the first round thread
-            // t loads the cell it finishes in the epilogue (row t / WPB of the
-            // output tile) and keeps its float64 conserved values
-            const int c = tid % WPB;
-            constexpr int ROWS = THREADS / WPB;
-            for (int p = tid / WPB; p < SLEN; p += ROWS) {
-                const int idx = (p + LEFT + R) % SLEN;
-                double q[NV];
-                if (c < ncol_valid) {
-                    bool flip = false;
-                    const long long cell =
-                        blk_base + c * cstride +
-                        (long long)(BCG ? ghost_src(sbase + idx, N, a.bc[0], a.bc[1], flip) : wrap(sbase + idx, N)) * stride;
-                    double u[NV];
-#pragma unroll
-                    for (int k = 0; k < NV; ++k) u[k] = a.U[k * nc + cell];
-                    if (FIN && p == tid / WPB && ecell >= 0) {
-#pragma unroll
-                        for (int k = 0; k < NV; ++k) pu[k] = u[k];
-                    }
-                    if (BCG && flip) u[1 + DIR] = -u[1 + DIR];
-                    cons_to_rot<NDIM, DIR>(u, gamma, q);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < NV; ++k) q[k] = (k == 0 || k == NV - 1) ? 1.0 : 0.0;
-                }
-#pragma unroll
-                for (int k = 0; k < NV; ++k) sV[k * FS + c * PITCH + idx] = (Real)q[k];
-            }
-        }
-    }
-
     __syncthreads();
 
     // ---- per-lane reconstruction, face flux, correction, difference ----------
     double dcons[NV];
     {
-        constexpr int FS = WPB * PITCH;
         const Real g = (Real)gamma;
-        const Real inv_gm1 = (Real)(1.0 / (gamma - 1.0));
+        const Real inv_gm1 = (Real)a.inv_gm1;
         Real qp[NV], qm[NV];
         reconstruct<NDIM, R, Real, IK>(sV + w * PITCH, FS, lane, a.tab, g, a.positivity, qp, qm);
         Real qR[NV], F[NV];
@@ -826,7 +835,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     unsigned long long smax = 0;
     const bool lane_out = lane >= LEFT && lane < LEFT + tseg;
     if (DIR == 0) {
-        if (ecell >= 0) finish_cell<NDIM, FIN, Real>(a, ecell, dcons, pd, pu, pn, dt, smax);
+        if (ecell >= 0) finish_cell<NDIM, FIN, Real, true>(a, ecell, dcons, pd, pu, pn, dt, smax);
     } else {
         __syncthreads();  // every wave is done reading the stencil tile
         if (lane_out) {
@@ -839,7 +848,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
             double d[NV];
 #pragma unroll
             for (int k = 0; k < NV; ++k) d[k] = sO[(k * TOUT + row) * C::OPITCH + c];
-            finish_cell<NDIM, FIN, Real>(a, ecell, d, pd, pu, pn, dt, smax);
+            finish_cell<NDIM, FIN, Real, false>(a, ecell, d, pd, pu, pn, dt, smax);
         }
     }
     if (FIN && a.stage == 3) {
@@ -866,7 +875,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
 }
 
 template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
-__global__ void __launch_bounds__(DIR == 0 ? 4 * WAVE : 8 * WAVE)
+__global__ void __launch_bounds__(sweep_wpb(DIR) * WAVE)
 sweep_kernel(const SweepArgs<Real> a) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
@@ -880,7 +889,7 @@ sweep_kernel(const SweepArgs<Real> a) {
 // single-problem sweep on its own problem's data, so a problem's result does
 // not depend on what else is in the batch.
 template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
-__global__ void __launch_bounds__(DIR == 0 ? 4 * WAVE : 8 * WAVE)
+__global__ void __launch_bounds__(sweep_wpb(DIR) * WAVE)
 sweep_batch_kernel(const BatchArgs<Real> ba) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
@@ -904,6 +913,7 @@ sweep_batch_kernel(const BatchArgs<Real> ba) {
     a.inv_dx_all[1] = P.inv_dx_all[1];
     a.inv_dx_all[2] = P.inv_dx_all[2];
     a.gamma = P.gamma;
+    a.inv_gm1 = P.inv_gm1;
     a.positivity = P.positivity;
     a.bc[0] = P.bc[0];
     a.bc[1] = P.bc[1];
