@@ -153,7 +153,7 @@ hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, int
 
 // ---- batched launches --------------------------------------------------------
 long long sweep_blocks(int ndim, int dir, const int n[3], int nseg) {
-    const int wpb = sweep_wpb(dir);
+    const int wpb = SWEEP_WPB;
     long long groups;
     if (dir == 0) groups = ((long long)n[1] * n[2] + wpb - 1) / wpb;
     else groups = (long long)((n[0] + wpb - 1) / wpb) * (dir == 1 ? n[2] : n[1]);
