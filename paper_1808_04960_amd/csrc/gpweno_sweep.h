@@ -700,36 +700,40 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     // Every tile load of a thread is issued before any of them is used, so a
     // block waits for one round trip before it computes.
     // x sweeps: pass 0, lane l of wave w loads tile position l + R of row w (its
-    // own cell); pass 1, lanes 0 .. 2R-1 of wave w load row w's halo positions
-    // 0 .. R-1 and 64 + R .. 64 + 2R - 1.
+    // own cell); pass 1, the first WPB * 2R threads (all in wave 0) load the 2R
+    // halo positions of every row (0 .. R-1 and 64 + R .. 64 + 2R - 1), so the
+    // other waves skip the pass.
     // y/z sweeps: tile rows are dealt rotated by LEFT + R, so that in pass 0
     // thread t loads the cell it finishes in the epilogue (row t / WPB of the
     // output tile); pass 1 covers the remaining 2R rows.
     constexpr int FS = WPB * PITCH;
-    int tcol, tpos[2];
+    static_assert(WPB * 2 * R <= WAVE, "the halo pass fits one wave");
+    int tcol[2], tpos[2];
     bool tact1;
     if (DIR == 0) {
-        tcol = w;
+        tcol[0] = w;
         tpos[0] = lane + R;
-        tpos[1] = lane < R ? lane : WAVE + lane;
-        tact1 = lane < 2 * R;
+        const int j = tid % (2 * R);
+        tcol[1] = tid / (2 * R);
+        tpos[1] = j < R ? j : WAVE + j;
+        tact1 = tid < WPB * 2 * R;
     } else {
         constexpr int ROWS = THREADS / WPB;
         static_assert(SLEN <= 2 * ROWS, "two passes cover the tile");
-        tcol = tid % WPB;
+        tcol[0] = tcol[1] = tid % WPB;
         const int p = tid / WPB;
         tpos[0] = (p + LEFT + R) % SLEN;
         tpos[1] = (p + ROWS + LEFT + R) % SLEN;
         tact1 = p + ROWS < SLEN;
     }
-    const bool tcol_ok = tcol < ncol_valid;
+    const bool tcol_ok[2] = {tcol[0] < ncol_valid, tcol[1] < ncol_valid};
     double u[2][NV];
     bool flip[2] = {false, false};
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
-        if (tcol_ok && (r == 0 || tact1)) {
+        if (tcol_ok[r] && (r == 0 || tact1)) {
             const int src = BCG ? ghost_src(sbase + tpos[r], N, a.bc[0], a.bc[1], flip[r]) : wrap(sbase + tpos[r], N);
-            const long long cell = blk_base + tcol * cstride + (long long)src * stride;
+            const long long cell = blk_base + tcol[r] * cstride + (long long)src * stride;
 #pragma unroll
             for (int k = 0; k < NV; ++k) u[r][k] = a.U[k * nc + cell];
         }
@@ -775,7 +779,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     for (int r = 0; r < 2; ++r) {
         if (r == 1 && !tact1) break;
         double q[NV];
-        if (tcol_ok) {
+        if (tcol_ok[r]) {
             if (FIN && r == 0 && ecell >= 0) {
 #pragma unroll
                 for (int k = 0; k < NV; ++k) pu[k] = u[0][k];
@@ -787,7 +791,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
             for (int k = 0; k < NV; ++k) q[k] = (k == 0 || k == NV - 1) ? 1.0 : 0.0;
         }
 #pragma unroll
-        for (int k = 0; k < NV; ++k) sV[k * FS + tcol * PITCH + tpos[r]] = (Real)q[k];
+        for (int k = 0; k < NV; ++k) sV[k * FS + tcol[r] * PITCH + tpos[r]] = (Real)q[k];
     }
 
     // ---- epilogue operands: requested now, they arrive while the sweep computes
