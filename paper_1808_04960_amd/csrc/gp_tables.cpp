@@ -306,6 +306,87 @@ int gpw_build_ao_tables(double ell_over_dx, double sigma_over_dx, GpAoTablesF64 
     return 0;
 }
 
+// GP indicator rows of K(sigma) on R + 1 = 3 or 4 nodes in symmetric /
+// antisymmetric form (GpTablesF64::Ps). In the orthonormal basis of mirrored
+// sums and differences, K splits into a symmetric and an antisymmetric block,
+// each diagonalised here; the eigenvectors of K are those of the blocks mapped
+// back, so the rows are the v_i / sqrt(lambda_i) of the eigen form, each
+// symmetric or antisymmetric by construction. K[i][j] = k[|i - j|].
+bool symmetric_rows(int R, const q128 *k, double Ps[4][2]) {
+    const q128 r2 = sqrtq((q128)2);
+    // blocks in the bases {(e_0 + e_R)/sqrt2, centre or (e_1 + e_{R-1})/sqrt2} and
+    // {(e_0 - e_R)/sqrt2, (e_1 - e_{R-1})/sqrt2}
+    q128 S[2][2], A[2][2];
+    int na;
+    if (R == 2) {
+        S[0][0] = k[0] + k[2];
+        S[0][1] = S[1][0] = r2 * k[1];
+        S[1][1] = k[0];
+        A[0][0] = k[0] - k[2];
+        na = 1;
+    } else if (R == 3) {
+        S[0][0] = k[0] + k[3];
+        S[0][1] = S[1][0] = k[1] + k[2];
+        S[1][1] = k[0] + k[1];
+        A[0][0] = k[0] - k[3];
+        A[0][1] = A[1][0] = k[1] - k[2];
+        A[1][1] = k[0] - k[1];
+        na = 2;
+    } else {
+        return false;
+    }
+    q128 VS[2][2], VA[2][2];
+    jacobi_eigen(2, S, VS);
+    jacobi_eigen(na, A, VA);
+    for (int i = 0; i < 2; ++i) {
+        if (!(S[i][i] > 0)) return false;
+        const q128 f = 1 / sqrtq(S[i][i]);
+        // R = 2: the centre basis vector is e_1 itself (no 1/sqrt2)
+        Ps[i][0] = (double)(VS[0][i] * f / r2);
+        Ps[i][1] = (double)(VS[1][i] * f / (R == 2 ? (q128)1 : r2));
+    }
+    for (int i = 0; i < na; ++i) {
+        if (!(A[i][i] > 0)) return false;
+        const q128 f = 1 / sqrtq(A[i][i]);
+        Ps[2 + i][0] = (double)(VA[0][i] * f / r2);
+        Ps[2 + i][1] = na == 2 ? (double)(VA[1][i] * f / r2) : 0.0;
+    }
+    return true;
+}
+
+// beta = f^T K^{-1} f from the eigen rows P and from the symmetric rows Ps, for
+// a fixed set of test vectors; true if they agree to the rounding of the
+// float64 rows, measured on the scale sum_i (sum_j |P_ij f_j|)^2 (beta itself
+// can be far smaller when K is badly conditioned). A wrong sign or row gives an
+// error of the order of that scale.
+bool symmetric_rows_agree(int R, const double (*P)[4], const double Ps[4][2]) {
+    const double tests[4][4] = {{1.0, -0.5, 0.25, 2.0}, {0.3, 0.3, 0.3, 0.3}, {-1.0, 2.0, -1.0, 0.5}, {0.0, 1e-3, 2e-3, 3e-3}};
+    for (const auto &f : tests) {
+        q128 b1 = 0, b2 = 0, scale = 0;
+        for (int i = 0; i <= R; ++i) {
+            q128 p = 0, pa = 0;
+            for (int j = 0; j <= R; ++j) {
+                p += (q128)P[i][j] * f[j];
+                pa += fabsq((q128)P[i][j] * f[j]);
+            }
+            b1 += p * p;
+            scale += pa * pa;
+        }
+        const q128 s0 = (q128)f[0] + f[R], d0 = (q128)f[0] - f[R];
+        const q128 s1 = R == 2 ? (q128)f[1] : (q128)f[1] + f[2], d1 = R == 2 ? (q128)0 : (q128)f[1] - f[2];
+        for (int i = 0; i < 2; ++i) {
+            const q128 p = Ps[i][0] * s0 + Ps[i][1] * s1;
+            b2 += p * p;
+        }
+        for (int i = 2; i <= R; ++i) {
+            const q128 p = Ps[i][0] * d0 + Ps[i][1] * d1;
+            b2 += p * p;
+        }
+        if (!(fabsq(b1 - b2) <= (q128)1e-12 * scale)) return false;
+    }
+    return true;
+}
+
 int gpw_build_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx, GpTablesF64 *out) {
     if (R < 1 || R > 3 || !(ell_over_dx > 0) || !(sigma_over_dx > 0) || !out) return -1;
     if (scheme != GPW_SCHEME_GP_WENO && scheme != GPW_SCHEME_WENO_JS && scheme != GPW_SCHEME_WENO_GP) return -1;
@@ -353,6 +434,12 @@ int gpw_build_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx
                 const double v = (double)(V[j][i] * inv);
                 for (int m = 0; m <= R; ++m) out->P[m][i][j] = v;
             }
+        }
+        if (R >= 2) {
+            q128 k[4];
+            for (int t = 0; t <= R; ++t) k[t] = se_kernel((q128)0, (q128)t, sig);
+            if (!symmetric_rows(R, k, out->Ps)) return -3;
+            if (!symmetric_rows_agree(R, out->P[0], out->Ps)) return -4;
         }
     }
     for (int m = 0; m <= R; ++m) {

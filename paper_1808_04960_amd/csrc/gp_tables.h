@@ -7,6 +7,13 @@ struct GpTablesF64 {
     double gam_plus[4];    // linear weights for x_* = +1/2
     double gam_minus[4];   // linear weights for x_* = -1/2
     double P[4][4][4];     // [m][i][j]: smoothness indicator beta_m = sum_i (P[m][i] . f_m)^2
+    // GP indicators, R = 2 and 3: the same rows v_i / sqrt(lambda_i) written on
+    // sums and differences of mirrored sub-stencil values. K(sigma) is symmetric
+    // Toeplitz, so each eigenvector is symmetric or antisymmetric about the
+    // sub-stencil centre. With s_j = f_j + f_{R-j} and d_j = f_j - f_{R-j}:
+    //   R = 2: rows 0, 1: Ps[i][0] s_0 + Ps[i][1] f_1;  row 2: Ps[2][0] d_0;
+    //   R = 3: rows 0, 1: Ps[i][0] s_0 + Ps[i][1] s_1;  rows 2, 3: Ps[i][0] d_0 + Ps[i][1] d_1.
+    double Ps[4][2];
 };
 
 // Interpolation schemes (values of gpweno_scheme).

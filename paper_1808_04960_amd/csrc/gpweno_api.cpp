@@ -259,6 +259,7 @@ void fill_tab(gpw::Tab<Real>& t, const GpTablesF64& s) {
             t.wm[m][j] = (Real)s.w_minus[m][j];
             for (int i = 0; i < 4; ++i) t.P[m][i][j] = (Real)s.P[m][i][j];
         }
+        for (int j = 0; j < 2; ++j) t.Ps[m][j] = (Real)s.Ps[m][j];
     }
 }
 

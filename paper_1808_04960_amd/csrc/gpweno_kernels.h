@@ -72,6 +72,7 @@ struct Tab {
     Real P[4][4][4];  // [m][i][j]: beta_m = sum_i (P[m][i] . f_m)^2 (GP: rows v_i / sqrt(lambda_i)
                       // of K_m(sigma), the same for every m; WENO-JS: a factor of the
                       // Jiang-Shu quadratic form of sub-stencil m)
+    Real Ps[4][2];    // GP rows of R = 2, 3 on mirrored sums / differences (GpTablesF64::Ps)
     AoTab<Real> ao;
 };
 
