@@ -232,7 +232,8 @@ __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Re
     for (int j = 0; j <= 2 * R; ++j) g[j] = IK == 2 ? f[j] - f[R] : f[j];
 #pragma unroll
     for (int m = 0; m <= R; ++m) {
-        Real b = Real(0);
+        // e_m = eps + beta_m, with eps = 1e-36 as the start of the accumulation
+        Real b;
         if constexpr (IK != 1 && R >= 2) {
             // GP rows in symmetric / antisymmetric form: K(sigma) is symmetric
             // Toeplitz, so every eigenvector is symmetric or antisymmetric about
@@ -244,14 +245,15 @@ __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Re
             const Real p1 = fma(T.Ps[1][0], s0, T.Ps[1][1] * s1);
             if constexpr (R == 2) {
                 const Real p2 = T.Ps[2][0] * d0;
-                b = fma(p0, p0, fma(p1, p1, p2 * p2));
+                b = fma(p0, p0, fma(p1, p1, fma(p2, p2, Real(1e-36))));
             } else {
                 const Real d1 = g[m + 1] - g[m + 2];
                 const Real p2 = fma(T.Ps[2][0], d0, T.Ps[2][1] * d1);
                 const Real p3 = fma(T.Ps[3][0], d0, T.Ps[3][1] * d1);
-                b = fma(p0, p0, fma(p1, p1, fma(p2, p2, p3 * p3)));
+                b = fma(p0, p0, fma(p1, p1, fma(p2, p2, fma(p3, p3, Real(1e-36)))));
             }
         } else {
+            b = Real(1e-36);
 #pragma unroll
             for (int i = 0; i < (IK == 1 ? R : R + 1); ++i) {  // Jiang-Shu forms have rank R
                 Real pr = T.P[IK == 1 ? m : 0][i][0] * g[m];
@@ -260,7 +262,7 @@ __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Re
                 b = fma(pr, pr, b);
             }
         }
-        e[m] = Real(1e-36) + b;
+        e[m] = b;
         Real ap = T.wp[m][0] * f[m];
         Real am = T.wm[m][0] * f[m];
 #pragma unroll
@@ -836,7 +838,11 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
 #pragma unroll
         for (int k = 0; k < NV; ++k) qR[k] = lane_next(qm[k]);
         hllc<NDIM, Real>(qp, qR, g, inv_gm1, F);
-        const Real alpha = Real(-1.0 / 24.0), beta = Real(3.0 / 640.0);
+        // f^ = F + alpha (F_{-1} - 2F + F_{+1}) + beta (F_{-2} - 4F_{-1} + 6F - 4F_{+1} + F_{+2}),
+        // alpha = -1/24, beta = 3/640, gathered by neighbour distance
+        const Real c0 = Real(1.0 + 2.0 / 24.0 + 18.0 / 640.0);  // 1 - 2 alpha + 6 beta
+        const Real c1 = Real(-1.0 / 24.0 - 12.0 / 640.0);       // alpha - 4 beta
+        const Real c2 = Real(3.0 / 640.0);                      // beta
         // This lane's face is x_{i+1/2} of cell i. At a reflecting wall the mirror
         // ghosts make the fluxes of mass, tangential momentum and energy vanish
         // (and the correction terms with them, by antisymmetry) up to rounding;
@@ -848,9 +854,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
         for (int k = 0; k < NV; ++k) {
             const Real fm1 = lane_prev(F[k]), fm2 = lane_prev(fm1);
             const Real fp1 = lane_next(F[k]), fp2 = lane_next(fp1);
-            const Real d2 = fm1 - Real(2) * F[k] + fp1;
-            const Real d4 = fm2 - Real(4) * fm1 + Real(6) * F[k] - Real(4) * fp1 + fp2;
-            const Real fh = (wall && k != 1) ? Real(0) : F[k] + alpha * d2 + beta * d4;
+            const Real fh = (wall && k != 1) ? Real(0) : fma(c0, F[k], fma(c1, fm1 + fp1, c2 * (fm2 + fp2)));
             const Real fhm = lane_prev(fh);
             dcons[cons_slot<NDIM, DIR>(k)] = -((double)fh - (double)fhm) * a.inv_dx;
         }
