@@ -52,15 +52,21 @@ def kernel_source_hash() -> str:
 
 def flops_per_cell_sweep(ndim: int, R: int) -> int:
     """Algorithmic flops of one cell in one direction's sweep (FMA = 2, divide and
-    square root = 1), counted from the per-cell formulas:
+    square root = 1), counted from the per-cell formulas in the forms the sweep
+    evaluates:
       cons->prim 3*ndim+3, eigen quantities 8, projection 6n (n = 2R+1),
-      GP-WENO per field (R+1)^2 (2R+3) + 2(R+1)(2R+1) + 11(R+1) + 2,
-      back-projection 14, HLLC 53 + 9(ndim-1) + 3 nv, correction and difference 16 nv."""
+      GP-WENO per field: indicators (R+1) * b_R, where b_R is one sub-stencil's
+        sum of squared rows on mirrored sums and differences (b_1 = 10 for the
+        plain 2x2 form, b_2 = 15, b_3 = 24), interpolation 2(R+1)(2R+1),
+        weights 11(R+1) + 2,
+      back-projection 14, HLLC 53 + 9(ndim-1) + 3 nv,
+      flux correction gathered by neighbour distance and difference 9 nv."""
     nv = 2 + ndim
     n = 2 * R + 1
-    weno = (R + 1) ** 2 * (2 * R + 3) + 2 * (R + 1) * (2 * R + 1) + 11 * (R + 1) + 2
+    beta_window = {1: 10, 2: 15, 3: 24}[R]
+    weno = (R + 1) * beta_window + 2 * (R + 1) * (2 * R + 1) + 11 * (R + 1) + 2
     hllc = 53 + 9 * (ndim - 1) + 3 * nv
-    return (3 * ndim + 3) + 8 + 6 * n + nv * weno + 14 + hllc + 16 * nv
+    return (3 * ndim + 3) + 8 + 6 * n + nv * weno + 14 + hllc + 9 * nv
 
 
 WORKLOADS = {
