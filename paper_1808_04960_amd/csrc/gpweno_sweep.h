@@ -513,15 +513,15 @@ __device__ __forceinline__ void flux_of(const Real (&q)[2 + NDIM], Real inv_gm1,
 }
 
 // HLLC flux (rotated frame) with Davis wave-speed estimates; at S* = 0 the left
-// star state is used. Branch-free: the star state of the upwind side of the
-// contact is built once and the final flux is selected.
+// star state is used. Branch-free. The face takes the flux of one side K only:
+// the upwind side of a supersonic face (S_L >= 0: left, S_R <= 0: right), else
+// the side of the contact the face lies on. So the primitive state of K is
+// selected first and only its flux and conserved vector are formed; the star
+// state of K gives F = F_K + S_K (U*_K - U_K) on subsonic faces.
 template <int NDIM, typename Real>
 __device__ __forceinline__ void hllc(const Real (&qL)[2 + NDIM], const Real (&qR)[2 + NDIM], Real gamma,
                                      Real inv_gm1, Real (&F)[2 + NDIM]) {
     constexpr int NV = 2 + NDIM;
-    Real FL[NV], FR[NV], UL[NV], UR[NV];
-    flux_of<NDIM, Real>(qL, inv_gm1, FL, UL);
-    flux_of<NDIM, Real>(qR, inv_gm1, FR, UR);
     const Real rL = qL[0], uL = qL[1], pL = qL[NV - 1];
     const Real rR = qR[0], uR = qR[1], pR = qR[NV - 1];
     // 1/rho_L and 1/rho_R from one reciprocal
@@ -535,9 +535,13 @@ __device__ __forceinline__ void hllc(const Real (&qL)[2 + NDIM], const Real (&qR
     const Real mL = rL * (SL - uL);
     const Real mR = rR * (SR - uR);
     const Real Ss = (pR - pL + uL * mL - uR * mR) * frcp(mL - mR);
-    const bool left = Ss >= Real(0);
-    const Real u = left ? uL : uR;
-    const Real p = left ? pL : pR;
+    const bool sup = SL >= Real(0) || SR <= Real(0);
+    const bool left = SL >= Real(0) || (SR > Real(0) && Ss >= Real(0));
+    Real qK[NV], FK[NV], UK[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) qK[k] = left ? qL[k] : qR[k];
+    flux_of<NDIM, Real>(qK, inv_gm1, FK, UK);
+    const Real u = qK[1], p = qK[NV - 1];
     const Real S = left ? SL : SR;
     const Real m = left ? mL : mR;
     // with X = m (S - S*): m/(S - S*) = m^2/X, 1/m = (S - S*)/X and
@@ -547,21 +551,14 @@ __device__ __forceinline__ void hllc(const Real (&qL)[2 + NDIM], const Real (&qR
     const Real fac = m * m * iX;
     const Real im = dS * iX;
     const Real ir = (S - u) * im;
-    Real Us[NV], Fs[NV];
+    Real Us[NV];
     Us[0] = fac;
     Us[1] = fac * Ss;
 #pragma unroll
-    for (int t = 0; t < NDIM - 1; ++t) Us[2 + t] = fac * (left ? qL[2 + t] : qR[2 + t]);
-    const Real EK = left ? UL[NV - 1] : UR[NV - 1];
-    Us[NV - 1] = fac * (EK * ir + (Ss - u) * (Ss + p * im));
+    for (int t = 0; t < NDIM - 1; ++t) Us[2 + t] = fac * qK[2 + t];
+    Us[NV - 1] = fac * (UK[NV - 1] * ir + (Ss - u) * (Ss + p * im));
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        const Real Fk = left ? FL[k] : FR[k];
-        const Real Uk = left ? UL[k] : UR[k];
-        Fs[k] = fma(S, Us[k] - Uk, Fk);
-    }
-#pragma unroll
-    for (int k = 0; k < NV; ++k) F[k] = (SL >= Real(0)) ? FL[k] : ((SR <= Real(0)) ? FR[k] : Fs[k]);
+    for (int k = 0; k < NV; ++k) F[k] = sup ? FK[k] : fma(S, Us[k] - UK[k], FK[k]);
 }
 
 template <int NDIM, int DIR, int R, typename Real>
