@@ -59,13 +59,14 @@ def flops_per_cell_sweep(ndim: int, R: int) -> int:
         sum of squared rows on mirrored sums and differences (b_1 = 10 for the
         plain 2x2 form, b_2 = 15, b_3 = 24), interpolation 2(R+1)(2R+1),
         weights 11(R+1) + 2,
-      back-projection 14, HLLC 53 + 9(ndim-1) + 3 nv,
+      back-projection 14, HLLC 43 + 5(ndim-1) + 3 nv (the flux and conserved
+        vector of the one side the face takes),
       flux correction gathered by neighbour distance and difference 9 nv."""
     nv = 2 + ndim
     n = 2 * R + 1
     beta_window = {1: 10, 2: 15, 3: 24}[R]
     weno = (R + 1) * beta_window + 2 * (R + 1) * (2 * R + 1) + 11 * (R + 1) + 2
-    hllc = 53 + 9 * (ndim - 1) + 3 * nv
+    hllc = 43 + 5 * (ndim - 1) + 3 * nv
     return (3 * ndim + 3) + 8 + 6 * n + nv * weno + 14 + hllc + 9 * nv
 
 
