@@ -22,6 +22,10 @@ namespace gpw {
 //   * The CFL speed of the state with step count n is reduced (atomic max of
 //     the bit images of non-negative doubles) into xcd[.].speed[n & 1], one
 //     cache line per XCD; the first sweep of step n clears slot (n + 1) & 1.
+//   * Block 0 of the first sweep of step n turns those speeds into the step's
+//     dt and stores it in dt_step[n & 1]; the sweeps that finish a stage read
+//     that one value. Where the first sweep itself finishes a stage (1D), its
+//     blocks derive dt from the speeds directly.
 struct StepRec {
     double t;          // time of the state
     double dt;         // time step that produced it (0 for an initial state)
@@ -43,6 +47,7 @@ struct Ctl {
     int err;                // 1: a stage produced rho <= 0, p <= 0 or NaN
     int pad;
     long long bad_cell;     // smallest cell index of such a failure
+    double dt_step[2];      // dt of step n in slot n & 1
     double sums[8];         // conserved sums (reduction output)
     XcdSlot xcd[8];
 };

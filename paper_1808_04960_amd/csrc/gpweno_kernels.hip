@@ -47,6 +47,8 @@ __global__ void set_time_kernel(Ctl* c, double t, long long nsteps, double cfl, 
     c->fixed_dt = fixed_dt;
     c->err = 0;
     c->bad_cell = LLONG_MAX;
+    c->dt_step[0] = 0.0;
+    c->dt_step[1] = 0.0;
     for (int x = 0; x < 8; ++x) {
         c->xcd[x].speed[0] = 0ull;
         c->xcd[x].speed[1] = 0ull;

@@ -145,30 +145,41 @@ inline __device__ __forceinline__ int ghost_src(int x, int n, int lo, int hi, bo
     return j < 0 ? 0 : (j >= n ? n - 1 : j);
 }
 
+// dt of step n starting at t0 from the CFL speeds of its initial state (the
+// max over the per-XCD slots n & 1), or the fixed step, clipped to t_final.
+__device__ __forceinline__ double step_dt(const Ctl* c, long long n, double t0) {
+    unsigned long long smax = 0;
+#pragma unroll
+    for (int x = 0; x < 8; ++x) {
+        const unsigned long long v = c->xcd[x].speed[n & 1];
+        smax = v > smax ? v : smax;
+    }
+    const double speed = __longlong_as_double((long long)smax);
+    double d = c->fixed_dt > 0.0 ? c->fixed_dt : c->cfl / speed;
+    if (t0 + d > c->t_final) d = c->t_final - t0;
+    return d;
+}
+
 // Time step of the step in flight and whether it runs. final_sweep: the
 // sweep that closes the step (its block 0 writes the next step state). Only
-// sweeps that finish an RK stage need dt (NEED_DT); the others read no speeds.
-// Every field is read up front, with no address depending on another read, so
-// the control block costs one round trip of scalar loads.
+// sweeps that finish an RK stage need dt (NEED_DT): from the value the step's
+// first sweep stored, or, for a first sweep that finishes a stage itself
+// (from_speeds), from the CFL speeds. Every field is read up front, with no
+// address depending on another read, so the control block costs one round
+// trip of scalar loads.
 template <bool NEED_DT>
-__device__ __forceinline__ bool step_go(const Ctl* c, bool final_sweep, double& t0, double& dt, long long& n) {
+__device__ __forceinline__ bool step_go(const Ctl* c, bool final_sweep, bool from_speeds, double& t0, double& dt,
+                                        long long& n) {
     const long long n0 = c->rec[0].nsteps, n1 = c->rec[1].nsteps;
     const double ta = c->rec[0].t, tb = c->rec[1].t;
     const long long st = c->started;
     const int err = c->err;
     const double tf = c->t_final;
     const long long lim = c->step_limit;
-    unsigned long long s0 = 0, s1 = 0;
-    double fixed = 0.0, cfl = 0.0;
-    if (NEED_DT) {
-        fixed = c->fixed_dt;
-        cfl = c->cfl;
-#pragma unroll
-        for (int x = 0; x < 8; ++x) {
-            const unsigned long long a0 = c->xcd[x].speed[0], a1 = c->xcd[x].speed[1];
-            s0 = a0 > s0 ? a0 : s0;
-            s1 = a1 > s1 ? a1 : s1;
-        }
+    double d0 = 0.0, d1 = 0.0;
+    if (NEED_DT && !from_speeds) {
+        d0 = c->dt_step[0];
+        d1 = c->dt_step[1];
     }
     int r;
     if (final_sweep) {
@@ -181,12 +192,7 @@ __device__ __forceinline__ bool step_go(const Ctl* c, bool final_sweep, double& 
     t0 = r ? tb : ta;
     n = r ? n1 : n0;
     if (err || !(t0 < tf) || n >= lim) return false;
-    if (NEED_DT) {
-        const double speed = __longlong_as_double((long long)((n & 1) ? s1 : s0));
-        double d = fixed > 0.0 ? fixed : cfl / speed;
-        if (t0 + d > tf) d = tf - t0;
-        dt = d;
-    }
+    if (NEED_DT) dt = from_speeds ? step_dt(c, n, t0) : ((n & 1) ? d1 : d0);
     return true;
 }
 
@@ -763,11 +769,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     double t0 = 0.0, dt = 0.0;
     long long nstep = 0;
     if (a.stage > 0) {
-        const bool go = step_go<FIN>(a.ctl, FIN && a.stage == 3, t0, dt, nstep);
+        const bool go = step_go<FIN>(a.ctl, FIN && a.stage == 3, FIN && a.step_start, t0, dt, nstep);
         if (a.step_start && L == 0 && threadIdx.x == 0) {
-            // mark the step as running (or not) and clear the next speed slot
+            // mark the step as running (or not), store its dt for the sweeps
+            // that finish a stage, and clear the next speed slot
             a.ctl->started = go ? nstep : -1;
             if (go) {
+                a.ctl->dt_step[nstep & 1] = FIN ? dt : step_dt(a.ctl, nstep, t0);
 #pragma unroll
                 for (int x = 0; x < 8; ++x) a.ctl->xcd[x].speed[(nstep + 1) & 1] = 0ull;
             }
