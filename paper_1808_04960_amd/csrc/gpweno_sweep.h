@@ -668,6 +668,12 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
                                             unsigned long long* sred) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     constexpr int NV = C::NV, WPB = C::WPB, PITCH = C::PITCH, SLEN = C::SLEN, THREADS = C::THREADS;
+    // float64 x sweeps request their epilogue operands (and their own cell's
+    // conserved values) after the reconstruction rather than before it: held
+    // through it, those 24 registers cost the float64 finishing sweep an
+    // occupancy level (111 against 87 VGPRs for 2D R = 2), which outweighs the
+    // shorter time the loads have to arrive.
+    constexpr bool LATE = DIR == 0 && sizeof(Real) == 8;
     Real* sV = reinterpret_cast<Real*>(smem);
     double* sO = reinterpret_cast<double*>(smem);
 
@@ -807,7 +813,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
         if (r == 1 && !tact1) break;
         double q[NV];
         if (tcol_ok[r]) {
-            if (FIN && r == 0 && ecell >= 0) {
+            if (FIN && !LATE && r == 0 && ecell >= 0) {
 #pragma unroll
                 for (int k = 0; k < NV; ++k) pu[k] = u[0][k];
             }
@@ -822,7 +828,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     }
 
     // ---- epilogue operands: requested now, they arrive while the sweep computes
-    if (ecell >= 0) {
+    if (!LATE && ecell >= 0) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) {
             if (!a.first) pd[k] = a.dU[k * nc + ecell];
@@ -839,6 +845,14 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
         const Real inv_gm1 = (Real)a.inv_gm1;
         Real qp[NV], qm[NV];
         reconstruct<NDIM, R, Real, IK>(sV + w * PITCH, FS, lane, a.tab, g, a.positivity, qp, qm);
+        if (LATE && ecell >= 0) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) {
+                if (!a.first) pd[k] = a.dU[k * nc + ecell];
+                if (FIN && a.stage >= 2) pn[k] = a.Un[k * nc + ecell];
+                if (FIN) pu[k] = a.U[k * nc + ecell];
+            }
+        }
         Real qR[NV], F[NV];
 #pragma unroll
         for (int k = 0; k < NV; ++k) qR[k] = lane_next(qm[k]);
