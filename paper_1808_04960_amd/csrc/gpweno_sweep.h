@@ -164,9 +164,10 @@ __device__ __forceinline__ double step_dt(const Ctl* c, long long n, double t0) 
 // sweep that closes the step (its block 0 writes the next step state). Only
 // sweeps that finish an RK stage need dt (NEED_DT): from the value the step's
 // first sweep stored, or, for a first sweep that finishes a stage itself
-// (from_speeds), from the CFL speeds. Every field is read up front, with no
-// address depending on another read, so the control block costs one round
-// trip of scalar loads.
+// (from_speeds, 1D only), from the CFL speeds. The fields are read up front,
+// with no address depending on another read, so the control block costs one
+// round trip of scalar loads; the speeds of the from_speeds path follow once
+// the step count is known.
 template <bool NEED_DT>
 __device__ __forceinline__ bool step_go(const Ctl* c, bool final_sweep, bool from_speeds, double& t0, double& dt,
                                         long long& n) {
