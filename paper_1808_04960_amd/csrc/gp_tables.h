@@ -32,5 +32,7 @@ struct GpAoTablesF64 {
 
 int gpw_build_ao_tables(double ell_over_dx, double sigma_over_dx, GpAoTablesF64 *out);
 
-// Returns 0 on success, < 0 on invalid input or a failed factorisation.
+// Returns 0 on success, < 0 on failure: -1 invalid input, -2 a failed weight
+// solve, -3 a non-positive eigenvalue, -4 indicator rows in symmetric form that
+// do not reproduce the eigen form.
 int gpw_build_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx, GpTablesF64 *out);
