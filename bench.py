@@ -40,13 +40,24 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}  # MI355X published vector peaks
 CSRC = os.path.join(ROOT, "paper_1808_04960_amd", "csrc")
 
 
+def _code_only(text: str) -> str:
+    """Source text without comments and whitespace (the sources hold no string
+    literal with a comment marker), so that editing a comment does not count as
+    a kernel change."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return "".join(text.split())
+
+
 def kernel_source_hash() -> str:
-    """sha256[:16] of the device sources (every .hip file and the kernel headers)."""
+    """sha256[:16] of the device sources (every .hip file and the kernel headers),
+    comments and whitespace excluded."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
         if name.endswith(".hip") or name in ("gpweno_sweep.h", "gpweno_kernels.h"):
-            with open(os.path.join(CSRC, name), "rb") as fh:
-                h.update(name.encode() + b"\0" + fh.read())
+            with open(os.path.join(CSRC, name), encoding="utf-8") as fh:
+                h.update(name.encode() + b"\0" + _code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
