@@ -590,6 +590,34 @@ inline __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long 
     return v;
 }
 
+// DPP move of a double (both halves with the same control): lanes the row mask
+// leaves out keep `old`; with bound_ctrl a lane whose source is out of range
+// reads 0.
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ double dpp_f64(double x, double old) {
+    const long long b = __double_as_longlong(x), o = __double_as_longlong(old);
+    const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffll), (int)(b & 0xffffffffll), CTRL, ROW_MASK, 0xF, BOUND);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, ROW_MASK, 0xF, BOUND);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Max over the wave of non-negative doubles, returned to every lane. Row shifts
+// by 1, 2, 4, 8 (out-of-row sources read 0, the identity here) leave each row's
+// max in its lane 15; row_bcast:15 and row_bcast:31 carry those across rows into
+// lane 63. Registers only, no LDS round trips.
+inline __device__ __forceinline__ double wave_max_nonneg(double v) {
+    v = fmax(v, dpp_f64<0x111, 0xF, true>(v, v));  // row_shr:1
+    v = fmax(v, dpp_f64<0x112, 0xF, true>(v, v));  // row_shr:2
+    v = fmax(v, dpp_f64<0x114, 0xF, true>(v, v));  // row_shr:4
+    v = fmax(v, dpp_f64<0x118, 0xF, true>(v, v));  // row_shr:8
+    v = fmax(v, dpp_f64<0x142, 0xA, false>(v, v)); // row_bcast:15 into rows 1, 3
+    v = fmax(v, dpp_f64<0x143, 0xC, false>(v, v)); // row_bcast:31 into rows 2, 3
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Store of a sweep output. x sweeps write whole rows with non-temporal
 // stores: the rows bypass L2, so the writeback of dirty lines at the end of
 // the kernel has nothing left to do (on a 512^2 grid that writeback held each
@@ -607,7 +635,7 @@ __device__ __forceinline__ void put(double* p, double v) {
 template <int NDIM, bool FIN, typename Real, bool NT>
 __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long cell, const double (&d)[2 + NDIM],
                                             const double (&pd)[2 + NDIM], const double (&pu)[2 + NDIM],
-                                            const double (&pn)[2 + NDIM], double dt, unsigned long long& smax) {
+                                            const double (&pn)[2 + NDIM], double dt, double& spd) {
     constexpr int NV = 2 + NDIM;
     const long long nc = a.ncell;
     if (!FIN) {
@@ -641,13 +669,14 @@ __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long 
         atomicMin(&a.ctl->bad_cell, cell);
     }
     if (a.stage == 3) {
-        const double c = sqrt(a.gamma * p * irho);
+        // sound speed from the reciprocal square root (to an ulp or two); a
+        // non-physical cell (flagged above) reads as an infinite speed
+        const double c2 = a.gamma * p * irho;
+        const double c = c2 * frsq(c2);
         double s = 0.0;
 #pragma unroll
         for (int dd = 0; dd < NDIM; ++dd) s += (fabs(vel[dd]) + c) * a.inv_dx_all[dd];
-        // non-negative doubles order like their bit images; NaN sorts above +inf
-        const unsigned long long bits = (s != s) ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(s);
-        smax = bits > smax ? bits : smax;
+        spd = (s != s) ? (double)INFINITY : s;
     }
 }
 
@@ -880,10 +909,10 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
         }
     }
 
-    unsigned long long smax = 0;
+    double spd = 0.0;  // this lane's CFL speed (stage 3 of a finishing sweep)
     const bool lane_out = lane >= LEFT && lane < LEFT + tseg;
     if (DIR == 0) {
-        if (ecell >= 0) finish_cell<NDIM, FIN, Real, true>(a, ecell, dcons, pd, pu, pn, dt, smax);
+        if (ecell >= 0) finish_cell<NDIM, FIN, Real, true>(a, ecell, dcons, pd, pu, pn, dt, spd);
     } else {
         __syncthreads();  // every wave is done reading the stencil tile
         if (lane_out) {
@@ -896,15 +925,16 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
             double d[NV];
 #pragma unroll
             for (int k = 0; k < NV; ++k) d[k] = sO[(k * TOUT + row) * C::OPITCH + c];
-            finish_cell<NDIM, FIN, Real, false>(a, ecell, d, pd, pu, pn, dt, smax);
+            finish_cell<NDIM, FIN, Real, false>(a, ecell, d, pd, pu, pn, dt, spd);
         }
     }
     if (FIN && a.stage == 3) {
         // CFL speed of the new state into the next step's slot (one atomic per
         // block, no return value), and block 0 closes the step by writing the
         // next step state into the older record (see Ctl).
-        smax = wave_max_u64(smax);
-        if (lane == 0) sred[w] = smax;
+        // non-negative doubles order like their bit images
+        const double wmax = wave_max_nonneg(spd);
+        if (lane == 0) sred[w] = (unsigned long long)__double_as_longlong(wmax);
         __syncthreads();
         if (tid == 0) {
             unsigned long long m = sred[0];
