@@ -804,7 +804,7 @@ int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stre
                 const gpweno_ctx* c = b->set[g.members[j]];
                 int nn[3] = {c->grid.n[0], c->grid.n[1], c->grid.n[2]};
                 const int nseg = (nn[dir] + TOUT - 1) / TOUT;
-                nblk[j] = gpw::sweep_blocks(g.ndim, dir, nn, nseg);
+                nblk[j] = gpw::sweep_blocks(g.ndim, dir, g.fp32, nn, nseg);
                 b0[j] = total;
                 total += nblk[j];
                 for (long long q = 0; q < nblk[j]; ++q) owner.push_back((unsigned short)j);

@@ -152,7 +152,7 @@ struct BatchStatus {
 hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, int ik, bool bcg, const void* args,
                         hipStream_t s);
 hipError_t launch_set_run(Ctl* ctl, double t_final, long long step_limit, hipStream_t s);
-long long sweep_blocks(int ndim, int dir, const int n[3], int nseg);
+long long sweep_blocks(int ndim, int dir, bool fp32, const int n[3], int nseg);
 hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, int ik, bool bcg, const void* args, long long blocks,
                               hipStream_t s);
 hipError_t launch_gather_status(Ctl* const* ctls, int nprob, BatchStatus* out, hipStream_t s);

@@ -154,12 +154,11 @@ hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, int
 
 
 // ---- batched launches --------------------------------------------------------
-long long sweep_blocks(int ndim, int dir, const int n[3], int nseg) {
-    const int wpb = SWEEP_WPB;
+long long sweep_blocks(int ndim, int dir, bool fp32, const int n[3], int nseg) {
+    const int wpb = sweep_wpb(ndim, dir, fp32);
     long long groups;
     if (dir == 0) groups = ((long long)n[1] * n[2] + wpb - 1) / wpb;
     else groups = (long long)((n[0] + wpb - 1) / wpb) * (dir == 1 ? n[2] : n[1]);
-    (void)ndim;
     return groups * nseg;
 }
 

@@ -49,7 +49,12 @@ constexpr int TOUT = WAVE - 6;      // outputs per run
 // sweeps. Four-wave blocks fill the register-limited wave slots of a compute
 // unit without stranding any, and spread small grids evenly over the compute
 // units (eight-wave y blocks left a 512^2 grid at 2.25 blocks per unit).
-constexpr int SWEEP_WPB = 4;
+// float32 y/z sweeps of 3D grids take 8 columns: their tile rows become 64
+// contiguous bytes of float64 state instead of 32, which shortens those sweeps
+// by 5-10 % on a 256^3 grid; float64 ones, at four waves per SIMD, lose as much.
+__host__ __device__ constexpr int sweep_wpb(int ndim, int dir, bool fp32) {
+    return (ndim == 3 && dir != 0 && fp32) ? 8 : 4;
+}
 
 __host__ __device__ constexpr int t1_axis(int dir) { return dir == 0 ? 1 : 0; }
 __host__ __device__ constexpr int t2_axis(int dir) { return dir == 2 ? 1 : 2; }
@@ -573,7 +578,7 @@ struct SweepCfg {
     static constexpr int NV = 2 + NDIM;
     static constexpr int SLEN = WAVE + 2 * R;
     static constexpr int PITCH = SLEN | 1;
-    static constexpr int WPB = SWEEP_WPB;  // pencils (waves) per block
+    static constexpr int WPB = sweep_wpb(NDIM, DIR, sizeof(Real) == 4);  // pencils (waves) per block
     static constexpr int THREADS = WPB * WAVE;
     static constexpr size_t IN_BYTES = sizeof(Real) * NV * WPB * PITCH;
     static constexpr int OPITCH = WPB + 1;  // padded row of the output tile (no bank conflicts)
@@ -953,7 +958,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
 }
 
 template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
-__global__ void __launch_bounds__(SWEEP_WPB * WAVE)
+__global__ void __launch_bounds__((SweepCfg<NDIM, DIR, R, Real>::THREADS))
 sweep_kernel(const SweepArgs<Real> a) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
@@ -967,7 +972,7 @@ sweep_kernel(const SweepArgs<Real> a) {
 // single-problem sweep on its own problem's data, so a problem's result does
 // not depend on what else is in the batch.
 template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
-__global__ void __launch_bounds__(SWEEP_WPB * WAVE)
+__global__ void __launch_bounds__((SweepCfg<NDIM, DIR, R, Real>::THREADS))
 sweep_batch_kernel(const BatchArgs<Real> ba) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
