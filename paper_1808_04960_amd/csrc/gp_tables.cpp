@@ -283,6 +283,31 @@ bool kernel_rows(int N, q128 sig, double *P /* [N][N] */, double *cN) {
     return true;
 }
 
+// The weights of x_* = -1/2 are those of x_* = +1/2 mirrored about the centre
+// node: K and the stencil set are symmetric under x -> -x, which maps node j of
+// sub-stencil m to node R - j of sub-stencil R - m. The sweep kernels read only
+// the +1/2 set; this checks the identity on the two binary128 solves, to the
+// accuracy they keep (12 digits at the worst conditioning in use).
+bool mirror_agrees(int n, const q128 *wp, const q128 *wm) {  // one stencil of n nodes
+    q128 scale = 0;
+    for (int j = 0; j < n; ++j) scale = fmaxq(scale, fabsq(wp[j]));
+    for (int j = 0; j < n; ++j)
+        if (!(fabsq(wm[j] - wp[n - 1 - j]) <= (q128)1e-12 * scale)) return false;
+    return true;
+}
+
+bool mirror_agrees(int R, const q128 wp[4][4], const q128 wm[4][4], const q128 *gp, const q128 *gm) {
+    q128 scale = 0;
+    for (int m = 0; m <= R; ++m)
+        for (int j = 0; j <= R; ++j) scale = fmaxq(scale, fabsq(wp[m][j]));
+    for (int m = 0; m <= R; ++m) {
+        if (!(fabsq(gm[m] - gp[R - m]) <= (q128)1e-12)) return false;
+        for (int j = 0; j <= R; ++j)
+            if (!(fabsq(wm[m][j] - wp[R - m][R - j]) <= (q128)1e-12 * scale)) return false;
+    }
+    return true;
+}
+
 }  // namespace
 
 int gpw_build_ao_tables(double ell_over_dx, double sigma_over_dx, GpAoTablesF64 *out) {
@@ -292,6 +317,7 @@ int gpw_build_ao_tables(double ell_over_dx, double sigma_over_dx, GpAoTablesF64 
     q128 w7p[NMAX], w7m[NMAX], w5p[NMAX], w5m[NMAX];
     if (!full_weights(3, ell, (q128)0.5, w7p) || !full_weights(3, ell, (q128)-0.5, w7m)) return -2;
     if (!full_weights(2, ell, (q128)0.5, w5p) || !full_weights(2, ell, (q128)-0.5, w5m)) return -2;
+    if (!mirror_agrees(7, w7p, w7m) || !mirror_agrees(5, w5p, w5m)) return -5;
     for (int j = 0; j < 7; ++j) {
         out->w7_plus[j] = (double)w7p[j];
         out->w7_minus[j] = (double)w7m[j];
@@ -401,6 +427,7 @@ int gpw_build_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx
         if (!poly_weights_for_point(R, (q128)0.5, wp, gp)) return -2;
         if (!poly_weights_for_point(R, (q128)-0.5, wm, gm)) return -2;
     }
+    if (!mirror_agrees(R, wp, wm, gp, gm)) return -5;
     if (scheme == GPW_SCHEME_WENO_JS) {
         // factor each B_m = V diag(lambda) V^T; rows sqrt(lambda_i) v_i in order of
         // decreasing lambda. B_m is positive semi-definite of rank R (its null

@@ -30,9 +30,12 @@ struct GpAoTablesF64 {
     double c[3];           // N = 7, 5, 3
 };
 
+// Same return codes as gpw_build_tables (-4 does not occur).
 int gpw_build_ao_tables(double ell_over_dx, double sigma_over_dx, GpAoTablesF64 *out);
 
 // Returns 0 on success, < 0 on failure: -1 invalid input, -2 a failed weight
 // solve, -3 a non-positive eigenvalue, -4 indicator rows in symmetric form that
-// do not reproduce the eigen form.
+// do not reproduce the eigen form, -5 weights of x_* = -1/2 that are not the
+// mirror image of those of x_* = +1/2 (w_minus[m][j] = w_plus[R-m][R-j],
+// gam_minus[m] = gam_plus[R-m]), on which the sweep kernels rely.
 int gpw_build_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx, GpTablesF64 *out);

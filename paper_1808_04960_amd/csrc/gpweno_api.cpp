@@ -237,12 +237,10 @@ template <typename Real>
 void fill_ao(gpw::AoTab<Real>& t, const GpAoTablesF64& s) {
     for (int j = 0; j < 7; ++j) {
         t.w7p[j] = (Real)s.w7_plus[j];
-        t.w7m[j] = (Real)s.w7_minus[j];
         for (int i = 0; i < 7; ++i) t.P7[i][j] = (Real)s.P7[i][j];
     }
     for (int j = 0; j < 5; ++j) {
         t.w5p[j] = (Real)s.w5_plus[j];
-        t.w5m[j] = (Real)s.w5_minus[j];
         for (int i = 0; i < 5; ++i) t.P5[i][j] = (Real)s.P5[i][j];
     }
     for (int k = 0; k < 3; ++k) t.c[k] = (Real)s.c[k];
@@ -253,10 +251,8 @@ template <typename Real>
 void fill_tab(gpw::Tab<Real>& t, const GpTablesF64& s) {
     for (int m = 0; m < 4; ++m) {
         t.gp[m] = (Real)s.gam_plus[m];
-        t.gm[m] = (Real)s.gam_minus[m];
         for (int j = 0; j < 4; ++j) {
             t.wp[m][j] = (Real)s.w_plus[m][j];
-            t.wm[m][j] = (Real)s.w_minus[m][j];
             for (int i = 0; i < 4; ++i) t.P[m][i][j] = (Real)s.P[m][i][j];
         }
         for (int j = 0; j < 2; ++j) t.Ps[m][j] = (Real)s.Ps[m][j];

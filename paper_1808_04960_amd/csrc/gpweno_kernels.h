@@ -56,24 +56,25 @@ struct Ctl {
 inline const StepRec& current_rec(const Ctl& c) { return c.rec[0].nsteps > c.rec[1].nsteps ? c.rec[0] : c.rec[1]; }
 
 // Tables of the adaptive-order GP interpolation (indicator kind 3): whole-stencil
-// GP weights of radius 3 and 2 at x_{i+-1/2}, rows v_i / sqrt(lambda_i) of
+// GP weights of radius 3 and 2 at x_{i+1/2}, rows v_i / sqrt(lambda_i) of
 // K_7(sigma) and K_5(sigma), the constants N/2 log(2 pi) + 1/2 log det K_N(sigma)
-// for N = 7, 5, 3, and gamma_HI. The 3-point sub-stencils use Tab::wp / wm,
-// Tab::P[0] (K_3(sigma)) and Tab::gp (the CWENO linear weights).
+// for N = 7, 5, 3, and gamma_HI. The 3-point sub-stencils use Tab::wp,
+// Tab::P[0] (K_3(sigma)) and Tab::gp (the CWENO linear weights). The weights
+// of x_{i-1/2} are these mirrored (the host checks the identity).
 template <typename Real>
 struct AoTab {
-    Real w7p[7], w7m[7], w5p[5], w5m[5];
+    Real w7p[7], w5p[5];
     Real P7[7][7], P5[5][5];
     Real c[3];
     Real ghi;
 };
 
+// Interpolation tables of x_{i+1/2}; those of x_{i-1/2} are their mirror
+// images, w_{R-m, R-j} and gamma_{R-m} (the host checks the identity).
 template <typename Real>
 struct Tab {
     Real wp[4][4];  // w_m at x_* = +1/2, [m][j]
-    Real wm[4][4];  // w_m at x_* = -1/2
     Real gp[4];     // gamma_m for x_* = +1/2
-    Real gm[4];     // gamma_m for x_* = -1/2
     Real P[4][4][4];  // [m][i][j]: beta_m = sum_i (P[m][i] . f_m)^2 (GP: rows v_i / sqrt(lambda_i)
                       // of K_m(sigma), the same for every m; WENO-JS: a factor of the
                       // Jiang-Shu quadratic form of sub-stencil m)

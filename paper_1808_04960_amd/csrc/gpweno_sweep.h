@@ -236,6 +236,10 @@ __device__ __forceinline__ void cons_to_rot(const double (&u)[2 + NDIM], double 
 // Nonlinear weights gamma_m / (eps + beta_m)^2 are evaluated in the equivalent
 // form gamma_m * ((eps + beta_min)/(eps + beta_m))^2, which cannot overflow or
 // underflow to 0/0 in float32 (eps = 1e-36 squared is below float range).
+// The weights of x_{i-1/2} are those of x_{i+1/2} mirrored about the centre
+// cell (the covariance kernel and the stencils are symmetric): sub-stencil m,
+// node j at -1/2 takes w_{R-m, R-j} at +1/2 and gamma_m takes gamma_{R-m}.
+// Reading one set halves the tables a sweep holds in scalar registers.
 template <int R, typename Real, int IK>
 __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Real>& T, Real& qp, Real& qm) {
     Real e[R + 1], cp[R + 1], cm[R + 1];
@@ -276,11 +280,11 @@ __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Re
         }
         e[m] = b;
         Real ap = T.wp[m][0] * f[m];
-        Real am = T.wm[m][0] * f[m];
+        Real am = T.wp[R - m][R] * f[m];
 #pragma unroll
         for (int j = 1; j <= R; ++j) {
             ap = fma(T.wp[m][j], f[m + j], ap);
-            am = fma(T.wm[m][j], f[m + j], am);
+            am = fma(T.wp[R - m][R - j], f[m + j], am);
         }
         cp[m] = ap;
         cm[m] = am;
@@ -294,7 +298,7 @@ __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Re
         const Real r = emin * frcp(e[m]);
         const Real w = r * r;
         const Real op = T.gp[m] * w;
-        const Real om = T.gm[m] * w;
+        const Real om = T.gp[R - m] * w;
         sp += op;
         sm += om;
         accp = fma(op, cp[m], accp);
@@ -321,7 +325,8 @@ __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Re
 //     normalised (Eq. (recursive-weights)) combine the two (Eq. (AO-recursive)).
 // The weights are evaluated as ratios to the smallest |eps + beta| (the
 // indicators can be negative: the log-det term of a 7-point K is), so no
-// intermediate overflows. Both faces share the indicators and weights.
+// intermediate overflows. Both faces share the indicators and weights; the
+// interpolation weights of x_{i-1/2} are those of x_{i+1/2} mirrored.
 template <int N, typename Real>
 __device__ __forceinline__ Real half_quad(const Real (&P)[N][N], const Real* f) {
     Real s = Real(0);
@@ -372,20 +377,20 @@ __device__ __forceinline__ void gp_ao(const Real (&f)[2 * R + 1], const Tab<Real
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         em[m] = Real(1e-36) + (T.ao.c[2] + half_quad<3, Real>(P3, f5 + m));
-        Real a = T.wp[m][0] * f5[m], b = T.wm[m][0] * f5[m];
+        Real a = T.wp[m][0] * f5[m], b = T.wp[2 - m][2] * f5[m];
 #pragma unroll
         for (int j = 1; j < 3; ++j) {
             a = fma(T.wp[m][j], f5[m + j], a);
-            b = fma(T.wm[m][j], f5[m + j], b);
+            b = fma(T.wp[2 - m][2 - j], f5[m + j], b);
         }
         q3p[m] = a;
         q3m[m] = b;
     }
-    Real q5p = T.ao.w5p[0] * f5[0], q5m = T.ao.w5m[0] * f5[0];
+    Real q5p = T.ao.w5p[0] * f5[0], q5m = T.ao.w5p[4] * f5[0];
 #pragma unroll
     for (int j = 1; j < 5; ++j) {
         q5p = fma(T.ao.w5p[j], f5[j], q5p);
-        q5m = fma(T.ao.w5m[j], f5[j], q5m);
+        q5m = fma(T.ao.w5p[4 - j], f5[j], q5m);
     }
     Real a5, c5[3];
     ao_coeffs<Real>(e5, em, T, a5, c5);
@@ -400,11 +405,11 @@ __device__ __forceinline__ void gp_ao(const Real (&f)[2 * R + 1], const Tab<Real
         qm = ao5m;
     } else {
         const Real e7 = Real(1e-36) + (T.ao.c[0] + half_quad<7, Real>(T.ao.P7, f));
-        Real q7p = T.ao.w7p[0] * f[0], q7m = T.ao.w7m[0] * f[0];
+        Real q7p = T.ao.w7p[0] * f[0], q7m = T.ao.w7p[6] * f[0];
 #pragma unroll
         for (int j = 1; j < 7; ++j) {
             q7p = fma(T.ao.w7p[j], f[j], q7p);
-            q7m = fma(T.ao.w7m[j], f[j], q7m);
+            q7m = fma(T.ao.w7p[6 - j], f[j], q7m);
         }
         Real a7, c7[3];
         ao_coeffs<Real>(e7, em, T, a7, c7);

@@ -130,6 +130,24 @@ def test_binary128_ao_tables_match_oracle(ell, sigma):
     np.testing.assert_allclose(got["c"], [ref["c7"], ref["c5"], ref["c3"]], rtol=1e-15, atol=1e-15)
 
 
+@pytest.mark.parametrize("scheme,R", [("gp-weno", 1), ("gp-weno", 2), ("gp-weno", 3), ("weno-js", 1),
+                                      ("weno-js", 2), ("weno-gp", 3)])
+@pytest.mark.parametrize("ell", [6.0, 12.0, 51.2])
+def test_minus_face_tables_are_the_mirror_image(scheme, R, ell):
+    # The sweep kernels read only the x_* = +1/2 weights and take those of -1/2 as
+    # their mirror image (kernel and stencils are symmetric under x -> -x); the
+    # library computes both sets by separate solves, so they must agree.
+    t = gw.compute_tables(R, ell, 3.0, scheme=scheme)
+    wp, wm = t["w+"][: R + 1, : R + 1], t["w-"][: R + 1, : R + 1]
+    np.testing.assert_allclose(wm, wp[::-1, ::-1], rtol=0, atol=1e-12 * np.abs(wp).max())
+    np.testing.assert_allclose(t["gamma-"][: R + 1], t["gamma+"][: R + 1][::-1], rtol=0, atol=1e-12)
+    if ell <= 12.0:  # well-conditioned enough for the two solves to round alike
+        assert np.array_equal(wm, wp[::-1, ::-1])
+    ao = gw.compute_ao_tables(ell, 3.0)
+    for key in ("w7", "w5"):
+        np.testing.assert_allclose(ao[key][1], ao[key][0][::-1], rtol=0, atol=1e-12 * np.abs(ao[key][0]).max())
+
+
 def test_gp_ao_needs_radius_two_or_three(L):
     g = gw.make_grid(_G(1, (64, 1, 1)))
     ctx = ctypes.c_void_p()
