@@ -233,9 +233,10 @@ __device__ __forceinline__ void cons_to_rot(const double (&u)[2 + NDIM], double 
 //   1  a factor per sub-stencil of rank R (Jiang-Shu quadratic forms);
 //   2  GP with the centre cell's value as the mean: the factor of K_m(sigma)
 //      applied to f_m - f_i (the paper's non-zero-mean variant, Sec. 7).
-// Nonlinear weights gamma_m / (eps + beta_m)^2 are evaluated in the equivalent
-// form gamma_m * ((eps + beta_min)/(eps + beta_m))^2, which cannot overflow or
-// underflow to 0/0 in float32 (eps = 1e-36 squared is below float range).
+// Nonlinear weights gamma_m / (eps + beta_m)^2 are evaluated, in float32, in
+// the equivalent form gamma_m * ((eps + beta_min)/(eps + beta_m))^2, which
+// cannot overflow or underflow to 0/0 (eps = 1e-36 squared is below float
+// range), and in float64 over a common denominator, without reciprocals.
 // The weights of x_{i-1/2} are those of x_{i+1/2} mirrored about the centre
 // cell (the covariance kernel and the stencils are symmetric): sub-stencil m,
 // node j at -1/2 takes w_{R-m, R-j} at +1/2 and gamma_m takes gamma_{R-m}.
@@ -289,25 +290,63 @@ __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Re
         cp[m] = ap;
         cm[m] = am;
     }
-    Real emin = e[0];
+    // w_m: 1/e_m^2 up to a factor common to all m
+    Real w[R + 1];
+    if constexpr (sizeof(Real) == 8) {
+        // float64: over the common denominator prod_k e_k^2, w_m = prod_{k != m}
+        // e_k^2, with no reciprocal. From e_k >= eps = 1e-36 up to 1e51 (R = 3)
+        // or 1e77 (R <= 2) every product below and the sums sp, sm stay normal
+        // doubles; beyond that (GP data of magnitude about 1e24 for R = 3, 1e37
+        // for R <= 2) they overflow, the interpolant becomes NaN and the stage
+        // check reports a non-physical state.
+        Real E[R + 1];
 #pragma unroll
-    for (int m = 1; m <= R; ++m) emin = fmin(emin, e[m]);
+        for (int m = 0; m <= R; ++m) E[m] = e[m] * e[m];
+        if constexpr (R == 1) {
+            w[0] = E[1];
+            w[1] = E[0];
+        } else if constexpr (R == 2) {
+            w[0] = E[1] * E[2];
+            w[1] = E[0] * E[2];
+            w[2] = E[0] * E[1];
+        } else {
+            const Real e01 = E[0] * E[1], e23 = E[2] * E[3];
+            w[0] = E[1] * e23;
+            w[1] = E[0] * e23;
+            w[2] = e01 * E[3];
+            w[3] = e01 * E[2];
+        }
+    } else {
+        // float32: as ratios to the smallest e_m, (e_min / e_m)^2 in (0, 1]
+        Real emin = e[0];
+#pragma unroll
+        for (int m = 1; m <= R; ++m) emin = fmin(emin, e[m]);
+#pragma unroll
+        for (int m = 0; m <= R; ++m) {
+            const Real r = emin * frcp(e[m]);
+            w[m] = r * r;
+        }
+    }
     Real sp = Real(0), sm = Real(0), accp = Real(0), accm = Real(0);
 #pragma unroll
     for (int m = 0; m <= R; ++m) {
-        const Real r = emin * frcp(e[m]);
-        const Real w = r * r;
-        const Real op = T.gp[m] * w;
-        const Real om = T.gp[R - m] * w;
+        const Real op = T.gp[m] * w[m];
+        const Real om = T.gp[R - m] * w[m];
         sp += op;
         sm += om;
         accp = fma(op, cp[m], accp);
         accm = fma(om, cm[m], accm);
     }
-    // both normalisations from one reciprocal: 1/sp = sm/(sp sm), 1/sm = sp/(sp sm)
-    const Real inv = frcp(sp * sm);
-    qp = accp * (sm * inv);
-    qm = accm * (sp * inv);
+    if constexpr (sizeof(Real) == 8) {
+        // sp sm would leave the double range: normalised one at a time
+        qp = accp * frcp(sp);
+        qm = accm * frcp(sm);
+    } else {
+        // both normalisations from one reciprocal: 1/sp = sm/(sp sm), 1/sm = sp/(sp sm)
+        const Real inv = frcp(sp * sm);
+        qp = accp * (sm * inv);
+        qm = accm * (sp * inv);
+    }
 }
 
 // Adaptive-order GP interpolation (the paper's App. A) of one characteristic

@@ -84,6 +84,28 @@ def test_rhs_matches_oracle(ndim, R, prec):
     assert err < bound
 
 
+@pytest.mark.parametrize("scale", [1e-20, 1e20])
+@pytest.mark.parametrize("R", [1, 2, 3])
+def test_rhs_over_the_range_of_the_data(R, scale):
+    """Density, momentum and energy scaled together (pressure with them, velocities
+    unchanged) by 1e-20 or 1e20: the smoothness indicators move to the eps-dominated
+    end (near 1e-40, against eps = 1e-36) or up to about 1e44, where the float64
+    sweeps, which form the nonlinear weights over a common denominator, hold
+    products of up to three squared indicators (about 1e260). Same bound as the
+    unscaled test; the flux sizes scale with the data."""
+    g = GRIDS[2]()
+    announce(f"rhs scaled by {scale:g} R={R} fp64 n={g.n}")
+    U = scale * inputs.random_smooth(g, seed=20 + R)
+    dx = g.dx[0]
+    ref = oracle.OracleSolver(g, R, 12 * dx, 3 * dx).rhs(U)
+    got = gw.Solver(g, R, 12 * dx, 3 * dx, precision="fp64", U0=U).rhs(U)
+    err = float(np.abs(got - ref).sum())
+    bound = 16 * EPS["fp64"] * flux_bound(g, U)
+    announce(f"  abs L1 {err:.3e}  bound {bound:.3e}  rel L1 {rel_l1(got, ref):.3e}")
+    assert np.isfinite(got).all()
+    assert err < bound
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 def test_config1_full_run(prec, tol):
     """1D sine wave, N = 128, R = 2, ell = 12 dx, sigma = 3 dx, CFL 0.4, t = 1."""
