@@ -475,6 +475,7 @@ int gpw_build_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx
         for (int j = 0; j <= R; ++j) {
             out->w_plus[m][j] = (double)wp[m][j];
             out->w_minus[m][j] = (double)wm[m][j];
+            out->gw_plus[m][j] = (double)(gp[m] * wp[m][j]);
         }
     }
     return 0;

@@ -14,6 +14,7 @@ struct GpTablesF64 {
     //   R = 2: rows 0, 1: Ps[i][0] s_0 + Ps[i][1] f_1;  row 2: Ps[2][0] d_0;
     //   R = 3: rows 0, 1: Ps[i][0] s_0 + Ps[i][1] s_1;  rows 2, 3: Ps[i][0] d_0 + Ps[i][1] d_1.
     double Ps[4][2];
+    double gw_plus[4][4];  // gam_plus[m] * w_plus[m][j], rounded once from binary128
 };
 
 // Interpolation schemes (values of gpweno_scheme).

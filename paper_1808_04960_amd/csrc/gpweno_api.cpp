@@ -229,7 +229,10 @@ int build_ao(double ell_dx, double sigma_dx, GpTablesF64* t, GpAoTablesF64* ao) 
     if (st) return st;
     const double g[3] = {0.5 * (1 - AO_GAMMA_HI) * (1 - AO_GAMMA_LO), (1 - AO_GAMMA_HI) * AO_GAMMA_LO,
                          0.5 * (1 - AO_GAMMA_HI) * (1 - AO_GAMMA_LO)};
-    for (int m = 0; m < 4; ++m) t->gam_plus[m] = t->gam_minus[m] = m < 3 ? g[m] : 0.0;
+    for (int m = 0; m < 4; ++m) {
+        t->gam_plus[m] = t->gam_minus[m] = m < 3 ? g[m] : 0.0;
+        for (int j = 0; j < 4; ++j) t->gw_plus[m][j] = t->gam_plus[m] * t->w_plus[m][j];  // unused by GP-AO
+    }
     return gpw_build_ao_tables(ell_dx, sigma_dx, ao);
 }
 
@@ -253,6 +256,7 @@ void fill_tab(gpw::Tab<Real>& t, const GpTablesF64& s) {
         t.gp[m] = (Real)s.gam_plus[m];
         for (int j = 0; j < 4; ++j) {
             t.wp[m][j] = (Real)s.w_plus[m][j];
+            t.gwp[m][j] = (Real)s.gw_plus[m][j];
             for (int i = 0; i < 4; ++i) t.P[m][i][j] = (Real)s.P[m][i][j];
         }
         for (int j = 0; j < 2; ++j) t.Ps[m][j] = (Real)s.Ps[m][j];

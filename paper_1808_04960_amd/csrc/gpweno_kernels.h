@@ -73,8 +73,9 @@ struct AoTab {
 // images, w_{R-m, R-j} and gamma_{R-m} (the host checks the identity).
 template <typename Real>
 struct Tab {
-    Real wp[4][4];  // w_m at x_* = +1/2, [m][j]
-    Real gp[4];     // gamma_m for x_* = +1/2
+    Real wp[4][4];   // w_m at x_* = +1/2, [m][j] (the GP-AO sub-stencils)
+    Real gwp[4][4];  // gamma_m w_m at x_* = +1/2 (GP-WENO and the polynomial schemes)
+    Real gp[4];      // gamma_m for x_* = +1/2
     Real P[4][4][4];  // [m][i][j]: beta_m = sum_i (P[m][i] . f_m)^2 (GP: rows v_i / sqrt(lambda_i)
                       // of K_m(sigma), the same for every m; WENO-JS: a factor of the
                       // Jiang-Shu quadratic form of sub-stencil m)

@@ -280,12 +280,13 @@ __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Re
             }
         }
         e[m] = b;
-        Real ap = T.wp[m][0] * f[m];
-        Real am = T.wp[R - m][R] * f[m];
+        // gamma_m q_m at both points (the candidates enter only in that product)
+        Real ap = T.gwp[m][0] * f[m];
+        Real am = T.gwp[R - m][R] * f[m];
 #pragma unroll
         for (int j = 1; j <= R; ++j) {
-            ap = fma(T.wp[m][j], f[m + j], ap);
-            am = fma(T.wp[R - m][R - j], f[m + j], am);
+            ap = fma(T.gwp[m][j], f[m + j], ap);
+            am = fma(T.gwp[R - m][R - j], f[m + j], am);
         }
         cp[m] = ap;
         cm[m] = am;
@@ -327,15 +328,14 @@ __device__ __forceinline__ void gp_weno(const Real (&f)[2 * R + 1], const Tab<Re
             w[m] = r * r;
         }
     }
-    Real sp = Real(0), sm = Real(0), accp = Real(0), accm = Real(0);
+    // q = sum_m w_m gamma_m q_m / sum_m w_m gamma_m at each point
+    Real sp = T.gp[0] * w[0], sm = T.gp[R] * w[0], accp = w[0] * cp[0], accm = w[0] * cm[0];
 #pragma unroll
-    for (int m = 0; m <= R; ++m) {
-        const Real op = T.gp[m] * w[m];
-        const Real om = T.gp[R - m] * w[m];
-        sp += op;
-        sm += om;
-        accp = fma(op, cp[m], accp);
-        accm = fma(om, cm[m], accm);
+    for (int m = 1; m <= R; ++m) {
+        sp = fma(T.gp[m], w[m], sp);
+        sm = fma(T.gp[R - m], w[m], sm);
+        accp = fma(w[m], cp[m], accp);
+        accm = fma(w[m], cm[m], accm);
     }
     if constexpr (sizeof(Real) == 8) {
         // sp sm would leave the double range: normalised one at a time
