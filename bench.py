@@ -61,22 +61,26 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def flops_per_cell_sweep(ndim: int, R: int) -> int:
+def flops_per_cell_sweep(ndim: int, R: int, fp64: bool = False) -> int:
     """Algorithmic flops of one cell in one direction's sweep (FMA = 2, divide and
     square root = 1), counted from the per-cell formulas in the forms the sweep
     evaluates:
       cons->prim 3*ndim+3, eigen quantities 8, projection 6n (n = 2R+1),
       GP-WENO per field: indicators (R+1) * b_R, where b_R is one sub-stencil's
         sum of squared rows on mirrored sums and differences (b_1 = 10 for the
-        plain 2x2 form, b_2 = 15, b_3 = 24), interpolation 2(R+1)(2R+1),
-        weights 11(R+1) + 2,
+        plain 2x2 form, b_2 = 15, b_3 = 24), interpolation 2(R+1)(2R+1)
+        (candidates pre-multiplied by their linear weights), weights and the two
+        normalised sums: float32, ratios (e_min/e_m)^2, 11(R+1) + 2; float64,
+        over a common denominator, (R+1) squares + p_R products (p = 0 / 3 / 6)
+        + 8R + 8,
       back-projection 14, HLLC 43 + 5(ndim-1) + 3 nv (the flux and conserved
         vector of the one side the face takes),
       flux correction gathered by neighbour distance and difference 9 nv."""
     nv = 2 + ndim
     n = 2 * R + 1
     beta_window = {1: 10, 2: 15, 3: 24}[R]
-    weno = (R + 1) * beta_window + 2 * (R + 1) * (2 * R + 1) + 11 * (R + 1) + 2
+    weights = (R + 1) + {1: 0, 2: 3, 3: 6}[R] + 8 * R + 8 if fp64 else 11 * (R + 1) + 2
+    weno = (R + 1) * beta_window + 2 * (R + 1) * (2 * R + 1) + weights
     hllc = 43 + 5 * (ndim - 1) + 3 * nv
     return (3 * ndim + 3) + 8 + 6 * n + nv * weno + 14 + hllc + 9 * nv
 
@@ -424,6 +428,7 @@ def main():
         return max(syms, key=lambda sym: kern[(prec, sym)][0] * kern[(prec, sym)][1])
 
     fl = flops_per_cell_sweep(grid.ndim, R) * ncell
+    fl64 = flops_per_cell_sweep(grid.ndim, R, fp64=True) * ncell
     sym32, sym64 = dominant("fp32"), dominant("fp64")
     t32, t64 = kern[("fp32", sym32)][0], kern[("fp64", sym64)][0]
     achieved = fl / t32 / 1e12
@@ -431,8 +436,9 @@ def main():
             "frac": achieved / PEAK_TFLOPS["fp32"], "traffic": traffic_from_profiles(sym32, W["tag"]), "kernel": sym32,
             "avg_launch_us": t32 * 1e6, "flops_per_launch": fl,
             "kernels_us": {k[1]: v[0] * 1e6 for k, v in kern.items()},
-            "fp64": {"kernel": sym64, "avg_launch_us": t64 * 1e6, "achieved": fl / t64 / 1e12,
-                     "peak": PEAK_TFLOPS["fp64"], "frac": fl / t64 / 1e12 / PEAK_TFLOPS["fp64"],
+            "fp64": {"kernel": sym64, "avg_launch_us": t64 * 1e6, "achieved": fl64 / t64 / 1e12,
+                     "flops_per_launch": fl64,
+                     "peak": PEAK_TFLOPS["fp64"], "frac": fl64 / t64 / 1e12 / PEAK_TFLOPS["fp64"],
                      "traffic": traffic_from_profiles(sym64, W["tag"])}}
     out = {
         "metric": METRIC,
