@@ -747,12 +747,14 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
                                             unsigned long long* sred) {
     using C = SweepCfg<NDIM, DIR, R, Real>;
     constexpr int NV = C::NV, WPB = C::WPB, PITCH = C::PITCH, SLEN = C::SLEN, THREADS = C::THREADS;
-    // float64 x sweeps request their epilogue operands (and their own cell's
-    // conserved values) after the reconstruction rather than before it: held
-    // through it, those 24 registers cost the float64 finishing sweep an
-    // occupancy level (111 against 87 VGPRs for 2D R = 2), which outweighs the
-    // shorter time the loads have to arrive.
-    constexpr bool LATE = DIR == 0 && sizeof(Real) == 8;
+    // float64 sweeps request their epilogue operands (and, in x sweeps, their
+    // own cell's conserved values) after the reconstruction rather than before
+    // it: held through it, those registers cost the float64 finishing sweep an
+    // occupancy level (111 against 87 VGPRs for 2D R = 2) and the 2D R = 3 y
+    // sweep another (103 against 95), which outweighs the shorter time the
+    // loads have to arrive (the 3D y sweep gains 7 % at equal occupancy).
+    // float32 sweeps gain nothing either way and keep the early requests.
+    constexpr bool LATE = sizeof(Real) == 8;
     Real* sV = reinterpret_cast<Real*>(smem);
     double* sO = reinterpret_cast<double*>(smem);
 
