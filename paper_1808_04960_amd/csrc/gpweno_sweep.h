@@ -509,23 +509,27 @@ __device__ __forceinline__ void reconstruct(const Real* __restrict__ s, int fs, 
     const Real a = Real(0.5) * rho * ic;
     const Real b = Real(0.5) * ic2;
 
+    // Fields in the order that retires stencil values soonest: the shear
+    // velocities, then the entropy wave (density), then the two acoustic
+    // waves (normal velocity and pressure). Bitwise the same result as any
+    // other order; it saves 10-24 registers (3D float64 R = 3: 139 -> 115).
     Real f[NS];
     Real acm_p, acm_m, ent_p, ent_m, acp_p, acp_m;
-#pragma unroll
-    for (int j = 0; j < NS; ++j) f[j] = fma(-a, v[1][j], b * v[NV - 1][j]);
-    interp<R, Real, IK>(f, T, acm_p, acm_m);
-#pragma unroll
-    for (int j = 0; j < NS; ++j) f[j] = fma(-ic2, v[NV - 1][j], v[0][j]);
-    interp<R, Real, IK>(f, T, ent_p, ent_m);
-#pragma unroll
-    for (int j = 0; j < NS; ++j) f[j] = fma(a, v[1][j], b * v[NV - 1][j]);
-    interp<R, Real, IK>(f, T, acp_p, acp_m);
 #pragma unroll
     for (int t = 0; t < NDIM - 1; ++t) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) f[j] = v[2 + t][j];
         interp<R, Real, IK>(f, T, qp[2 + t], qm[2 + t]);
     }
+#pragma unroll
+    for (int j = 0; j < NS; ++j) f[j] = fma(-ic2, v[NV - 1][j], v[0][j]);
+    interp<R, Real, IK>(f, T, ent_p, ent_m);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) f[j] = fma(-a, v[1][j], b * v[NV - 1][j]);
+    interp<R, Real, IK>(f, T, acm_p, acm_m);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) f[j] = fma(a, v[1][j], b * v[NV - 1][j]);
+    interp<R, Real, IK>(f, T, acp_p, acp_m);
     const Real cr = c * irho;
     qp[0] = acm_p + ent_p + acp_p;
     qm[0] = acm_m + ent_m + acp_m;
