@@ -8,18 +8,19 @@
 //     mapped one cell per lane of a wave. Each lane reconstructs the Riemann
 //     states of its cell (stencil of 2R+1 cells read from LDS), the wave then
 //     forms face fluxes, corrected fluxes and flux differences exchanging
-//     neighbouring lanes' values with DPP wave shifts. The flux correction needs face fluxes two faces either side
-//     and the difference one more face, so lanes 3..60 produce output: a run
-//     yields 58 cells, and consecutive runs overlap by 6 cells.
+//     neighbouring lanes' values with DPP wave shifts. The flux correction
+//     needs face fluxes two faces either side and the difference one more
+//     face, so lanes 3..60 produce output: a run yields 58 cells, and
+//     consecutive runs overlap by 6 cells.
 //   * A block holds several pencils (one wave each) and the same run segment.
 //     The input tile [2+ndim fields][pencils][64 + 2R cells] is loaded once
 //     from HBM (ghost positions: periodic image, outflow copy or mirror image),
 //     converted to rotated primitive variables and staged in LDS.
 //   * x sweeps: each wave loads its own row (contiguous along x) and writes its
 //     outputs directly (contiguous). y/z sweeps: a block holds 4 adjacent
-//     x-columns, so every global access covers 4 consecutive doubles; the
-//     outputs are transposed through LDS so the accumulator's read-modify-write
-//     is also x-contiguous.
+//     x-columns (8 for float32 3D grids, see sweep_wpb), so every global access
+//     covers 4 (8) consecutive doubles; the outputs are transposed through LDS
+//     so the accumulator's read-modify-write is also x-contiguous.
 //
 // Per cell (paper references):
 //   characteristic projection of the primitive stencil at the centre cell
