@@ -153,3 +153,14 @@ def test_gp_ao_needs_radius_two_or_three(L):
     ctx = ctypes.c_void_p()
     assert L.gpweno_init_scheme(ctypes.byref(g), 3, 1, 0.1, 0.05, 1.4, ctypes.byref(ctx)) == gw.EINVAL
     assert not ctx.value
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    # The product path has no fallback: without the built HIP library every
+    # entry point raises instead of computing anything elsewhere.
+    monkeypatch.setattr(gw, "_lib", None)
+    monkeypatch.setattr(gw, "LIB_PATH", str(tmp_path / "libgpweno.so"))
+    with pytest.raises(gw.GpwenoError, match="is not built"):
+        gw.lib()
+    with pytest.raises(gw.GpwenoError, match="is not built"):
+        gw.compute_tables(2, 12.0, 3.0)
