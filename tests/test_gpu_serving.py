@@ -68,6 +68,38 @@ def test_batch_is_bitwise_the_single_problem_path(prec):
     b.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batch_3d_is_bitwise_the_single_problem_path(prec):
+    """3D problems through the batched kernels: every y/z block (8 x columns in
+    float32, 4 in float64) and every ragged pencil group and run segment of a
+    problem must be owned by that problem and reproduce its single-problem
+    result bitwise; periodic and outflow problems form separate kernel groups."""
+    announce(f"3D batch vs single, {prec}")
+    stream = torch.cuda.Stream()
+    probs = []
+    for i, (nx, ny, nz) in enumerate([(41, 20, 18), (33, 33, 24), (20, 45, 30), (67, 12, 9)]):
+        g = inputs.grid3d(nx, ny, nz, (0.0, 0.0, 0.0), (nx / 32, ny / 32, nz / 32))  # square cells, exactly
+        probs.append((g, inputs.random_smooth(g, seed=300 + i)))
+    probs.append(inputs.explosion(3, 26))
+    solvers = []
+    for g, U in probs:
+        dx = g.dx[0]
+        s = gw.Solver(g, 2, 12 * dx, 3 * dx, precision=prec, U0=U, stream=stream)
+        s.set_end(1e30, 6)
+        solvers.append(s)
+    b = gw.Batch(stream)
+    b.set(solvers)
+    b.run(7)
+    _, _, ns, err = b.status()
+    assert list(ns) == [6] * len(probs) and not err.any()
+    for s, (g, U) in zip(solvers, probs):
+        dx = g.dx[0]
+        ref = gw.Solver(g, 2, 12 * dx, 3 * dx, precision=prec, U0=U)
+        ref.run(1e30, max_steps=6)
+        assert np.array_equal(s.get_state(), ref.get_state()), g.n
+    b.close()
+
+
 def test_server_alone_equals_mix_bitwise():
     announce("server alone vs mix")
     # arrivals closer together than a job lasts: later requests join while earlier
