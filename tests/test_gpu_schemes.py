@@ -151,7 +151,8 @@ def test_paper_vortex_tables_on_gpu(scheme, R, n):
 def test_batch_mixing_schemes_is_bitwise_the_single_problem_path():
     announce("batch with mixed schemes")
     stream = torch.cuda.Stream()
-    probs = [("gp-weno", 2, 64), ("weno-js", 2, 64), ("weno-gp", 3, 80), ("weno-js", 1, 72), ("gp-weno", 2, 96)]
+    probs = [("gp-weno", 2, 64), ("weno-js", 2, 64), ("weno-gp", 3, 80), ("weno-js", 1, 72), ("gp-weno", 2, 96),
+             ("gp-ao", 2, 64), ("gp-ao", 3, 72)]
     solvers, states = [], []
     for scheme, R, n in probs:
         g, U = inputs.isentropic_vortex_2d(n)
