@@ -35,6 +35,8 @@ CONFIGS = {
     "C3-kh-2048x1024": (lambda: inputs.kelvin_helmholtz_2d(2048, 1024), 3),
     "C4-wave-256": (lambda: inputs.density_wave_3d(256), 2),
     "C4-vortex-256": (lambda: inputs.isentropic_vortex_3d(256), 2),
+    # the largest axis the library accepts (2^24 cells): 289,262 runs per pencil
+    "max-axis-1d-2^24": (lambda: inputs.sine_wave_1d(1 << 24), 2),
 }
 
 
