@@ -38,5 +38,7 @@ int gpw_build_ao_tables(double ell_over_dx, double sigma_over_dx, GpAoTablesF64 
 // solve, -3 a non-positive eigenvalue, -4 indicator rows in symmetric form that
 // do not reproduce the eigen form, -5 weights of x_* = -1/2 that are not the
 // mirror image of those of x_* = +1/2 (w_minus[m][j] = w_plus[R-m][R-j],
-// gam_minus[m] = gam_plus[R-m]), on which the sweep kernels rely.
+// gam_minus[m] = gam_plus[R-m]) to 1e-6, on which the sweep kernels rely (for
+// R = 3 this also rejects ell beyond about 220-250 dx, where K is too badly
+// conditioned for the binary128 solves to agree).
 int gpw_build_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx, GpTablesF64 *out);

@@ -148,6 +148,18 @@ def test_minus_face_tables_are_the_mirror_image(scheme, R, ell):
         np.testing.assert_allclose(ao[key][1], ao[key][0][::-1], rtol=0, atol=1e-12 * np.abs(ao[key][0]).max())
 
 
+@pytest.mark.parametrize("ell", [80.0, 192.0])
+def test_tables_at_large_ell_still_build(ell):
+    # K_7 loses conditioning fast with ell/dx (about 1e28 at 192 dx): the two
+    # binary128 solves of R = 3 then drift apart (1e-12 at 80 dx, 7e-8 at 192 dx)
+    # but stay within the 1e-6 the mirror check allows.
+    t = gw.compute_tables(3, ell, 3.0)
+    np.testing.assert_allclose(t["gamma-"][:4], t["gamma+"][:4][::-1], rtol=0, atol=1e-6)
+    np.testing.assert_allclose(t["w-"][:4, :4], t["w+"][:4, :4][::-1, ::-1], rtol=0, atol=1e-6 * np.abs(t["w+"]).max())
+    ao = gw.compute_ao_tables(ell, 3.0)
+    np.testing.assert_allclose(ao["w7"][1], ao["w7"][0][::-1], rtol=0, atol=1e-6 * np.abs(ao["w7"][0]).max())
+
+
 def test_gp_ao_needs_radius_two_or_three(L):
     g = gw.make_grid(_G(1, (64, 1, 1)))
     ctx = ctypes.c_void_p()
