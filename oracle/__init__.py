@@ -61,6 +61,7 @@ class Cfg(ctypes.Structure):
         ("ao_P3", ctypes.c_double * 27),
         ("ao_c", ctypes.c_double * 9),
         ("ao_gam", ctypes.c_double * 4),
+        ("flux_corr_terms", ctypes.c_int),
     ]
 
 
@@ -102,6 +103,8 @@ def lib():
         L.oracle_hllc.argtypes = [_dp, _dp, ctypes.c_double, _dp]
         L.oracle_flux_hat.restype = ctypes.c_double
         L.oracle_flux_hat.argtypes = [_dp]
+        L.oracle_flux_hat7.restype = ctypes.c_double
+        L.oracle_flux_hat7.argtypes = [_dp]
         L.oracle_char_vectors.restype = None
         L.oracle_char_vectors.argtypes = [_dp, ctypes.c_double, _dp, _dp]
         L.oracle_rk3_combine.restype = None
@@ -185,9 +188,14 @@ def hllc(qL, qR, gamma):
     return F
 
 
-def flux_hat(F5):
-    F5 = np.ascontiguousarray(F5, dtype=np.float64)
-    return lib().oracle_flux_hat(_ptr(F5))
+def flux_hat(F):
+    """Corrected flux from 5 face fluxes (alpha, beta) or 7 (with the sixth
+    difference), centred on the face."""
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    if F.size == 7:
+        return lib().oracle_flux_hat7(_ptr(F))
+    assert F.size == 5
+    return lib().oracle_flux_hat(_ptr(F))
 
 
 def char_vectors(q, gamma):
@@ -214,7 +222,7 @@ class OracleSolver:
     ``nonzero_mean``: GP indicators of the data minus the centre cell's value."""
 
     def __init__(self, grid, R, ell, sigma, gamma=1.4, cfl=0.4, positivity_fallback=False, scheme="gp-weno",
-                 nonzero_mean=False):
+                 nonzero_mean=False, flux_corr_terms=2):
         self.grid = grid
         self.R = R
         self.cfl = cfl
@@ -227,13 +235,16 @@ class OracleSolver:
         c.gamma = gamma
         c.positivity_fallback = 1 if positivity_fallback else 0
         c.nonzero_mean = 1 if nonzero_mean else 0
+        if flux_corr_terms not in (2, 3):
+            raise ValueError("flux_corr_terms is 2 or 3")
+        c.flux_corr_terms = flux_corr_terms
         bc = getattr(grid, "bc", ((0, 0),) * 3)
         for d in range(3):
             lo_bc, hi_bc = bc[d] if d < grid.ndim else (0, 0)
             if (lo_bc == 0) != (hi_bc == 0):
                 raise ValueError("a periodic axis must be periodic on both sides")
-            if 2 in (lo_bc, hi_bc) and grid.n[d] < R + 3:
-                raise ValueError("a reflecting side needs at least R + 3 cells on its axis")
+            if 2 in (lo_bc, hi_bc) and grid.n[d] < R + 1 + flux_corr_terms:
+                raise ValueError("a reflecting side needs at least R + 1 + flux_corr_terms cells on its axis")
             c.bc[2 * d] = lo_bc
             c.bc[2 * d + 1] = hi_bc
         self.tables = []

@@ -13,7 +13,9 @@
  *   - Sec. 2, Eq. (disc_fd):          dU_i/dt = -(fhat_{i+1/2} - fhat_{i-1/2})/dx - ...
  *   - Sec. 2, Eq. (riemann_prob):     face flux F_{i+1/2} = RP(U^L, U^R)
  *   - Sec. 2, Eqs. (numFlux_cor), (FD-ders): fhat = F + alpha dx^2 F'' + beta dx^4 F''''
- *                                     with alpha = -1/24, beta = 3/640, no limiter
+ *                                     with alpha = -1/24, beta = 3/640, no limiter;
+ *                                     optionally the next term of the series, -5/7168
+ *                                     on the sixth difference (the "+ ..." there)
  *   - Sec. 3.3, Eqs. (candidate_interp), (weight_sum), (weights), (gp-smooth),
  *     (beta-eigen):                   GP-WENO interpolation of the Riemann states
  *   - Sec. 4:                         stepwise algorithm
@@ -77,6 +79,8 @@ typedef struct {
     double ao_P3[3][3][3];
     double ao_c[3][3];          /* N/2 log 2pi + 1/2 log det K_N(sigma), N = 7, 5, 3 */
     double ao_gam[4];           /* CWENO linear weights gamma_1..3, then gamma_HI */
+    int flux_corr_terms;        /* 2: alpha, beta (the paper's); 3: also the sixth
+                                   difference; 0 reads as 2 */
 } oracle_cfg;
 
 enum { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_REFLECT = 2 };
@@ -91,6 +95,12 @@ enum { K_ACM = 0, K_ENT = 1, K_T1 = 2, K_T2 = 3, K_ACP = 4 };
 static const double EPS_WENO = 1e-36;   /* epsilon of Eq. (weights) */
 static const double ALPHA_FC = -1.0 / 24.0;   /* Eq. (numFlux_cor) */
 static const double BETA_FC = 3.0 / 640.0;
+/* Next term of the same series: the numerical flux h whose difference gives the
+ * derivative of F exactly, h = F - dx^2/24 F'' + 7 dx^4/5760 F'''' - 31 dx^6/967680
+ * F^(6) + ..., with the derivatives written as central differences of the face
+ * fluxes, gives -1/24 on the second, 3/640 on the fourth and -5/7168 on the
+ * sixth difference. */
+static const double C6_FC = -5.0 / 7168.0;
 
 /* Active characteristic fields for a given dimension (nv of them). */
 static int active_fields(int ndim, int *k) {
@@ -399,6 +409,17 @@ double oracle_flux_hat(const double *F5) {
     return F5[2] + ALPHA_FC * d2 + BETA_FC * d4;
 }
 
+/* The same with the sixth-difference term, from F_{j-5/2} .. F_{j+7/2}. */
+double oracle_flux_hat7(const double *F7) {
+    double d2 = F7[2] - 2.0 * F7[3] + F7[4];
+    double d4 = F7[1] - 4.0 * F7[2] + 6.0 * F7[3] - 4.0 * F7[4] + F7[5];
+    double d6 = F7[0] - 6.0 * F7[1] + 15.0 * F7[2] - 20.0 * F7[3] + 15.0 * F7[4] - 6.0 * F7[5] + F7[6];
+    return F7[3] + ALPHA_FC * d2 + BETA_FC * d4 + C6_FC * d6;
+}
+
+/* Terms of the correction in use (2 or 3). */
+static int corr_terms(const oracle_cfg *c) { return c->flux_corr_terms == 3 ? 3 : 2; }
+
 /* Reconstruct the Riemann states of one cell: the 2R+1 rotated primitive
  * vectors qs[0..2R] (centre at index R) -> q^+ at x_{i+1/2}, q^- at x_{i-1/2}. */
 static int reconstruct_cell(const oracle_cfg *c, int d, const double (*qs)[5],
@@ -478,7 +499,10 @@ long oracle_rhs(const oracle_cfg *c, const double *U, double *Lout) {
         frame_axes(d, ax);
         /* conserved-momentum slot for each rotated component */
         int slot[5] = {0, 1 + ax[0], 1 + ax[1], 1 + ax[2], nv - 1};
-        int G = R + 3;
+        /* ghost cells: the stencil radius, the nc face fluxes either side of a
+         * face that the correction takes, and the face of the difference */
+        int nc = corr_terms(c);
+        int G = R + 1 + nc;
         double inv_dx = 1.0 / c->dx[d];
 #pragma omp parallel for schedule(static) reduction(+ : fallbacks)
         for (long pi = 0; pi < (long)npencil; ++pi) {
@@ -515,13 +539,13 @@ long oracle_rhs(const oracle_cfg *c, const double *U, double *Lout) {
                 q[s][Q_UT2] = Vp[(size_t)(1 + ax[2]) * ncell + cell];
                 q[s][Q_P] = Vp[(size_t)4 * ncell + cell];
             }
-            /* Riemann states of cells -3 .. N+2 (pencil index s = i + G) */
-            for (int i = -3; i <= N + 2; ++i) {
+            /* Riemann states of cells -(nc+1) .. N+nc (pencil index s = i + G) */
+            for (int i = -(nc + 1); i <= N + nc; ++i) {
                 int s = i + G;
                 fallbacks += reconstruct_cell(c, d, (const double (*)[5])&q[s - R], qplus[s], qminus[s]);
             }
-            /* face fluxes F_{j+1/2}, j = -3 .. N+1 (Eq. (riemann_prob)) */
-            for (int j = -3; j <= N + 1; ++j) {
+            /* face fluxes F_{j+1/2}, j = -(nc+1) .. N+nc-1 (Eq. (riemann_prob)) */
+            for (int j = -(nc + 1); j <= N + nc - 1; ++j) {
                 int s = j + G;
                 oracle_hllc(qplus[s], qminus[s + 1], c->gamma, Ff[s]);
             }
@@ -529,8 +553,9 @@ long oracle_rhs(const oracle_cfg *c, const double *U, double *Lout) {
             for (int j = -1; j <= N - 1; ++j) {
                 int s = j + G;
                 for (int k = 0; k < 5; ++k) {
-                    double F5[5] = {Ff[s - 2][k], Ff[s - 1][k], Ff[s][k], Ff[s + 1][k], Ff[s + 2][k]};
-                    fh[5 * s + k] = oracle_flux_hat(F5);
+                    double Fn[7];
+                    for (int o = -nc; o <= nc; ++o) Fn[o + nc] = Ff[s + o][k];
+                    fh[5 * s + k] = nc == 3 ? oracle_flux_hat7(Fn) : oracle_flux_hat(Fn);
                 }
             }
             for (int i = 0; i < N; ++i) {

@@ -94,6 +94,53 @@ def test_smooth_data_interpolates_to_high_order(R):
     assert order > 2 * R + 1 - 0.6
 
 
+@pytest.mark.parametrize("scheme", ["gp-weno", "weno-gp"])
+@pytest.mark.parametrize("R", [1, 2, 3])
+def test_weight_ratios_fix_the_exponent_of_eq_weights(R, scheme):
+    """Geometric data f_j = r^j make sub-stencil m+1 hold exactly r times the
+    data of sub-stencil m. The GP indicator of every sub-stencil is the same
+    quadratic form f_m^T K(sigma)^-1 f_m (Eq. (gp-smooth); the sub-stencils are
+    translates of one another), so beta_{m+1} = r^2 beta_m, whatever K. With eps
+    negligible against beta, Eq. (weights) with p = 2 then gives
+    omega_{m+1}/omega_m = (gamma_{m+1}/gamma_m) r^(-2p) = (gamma_{m+1}/gamma_m)
+    / r^4 at both points; p = 1 or 3 would give r^-2 or r^-6. (The Jiang-Shu
+    forms differ per sub-stencil, so this does not apply to them.)"""
+    tab = oracle.gp_tables(R, 12.0, 3.0) if scheme == "gp-weno" else oracle.scheme_tables(scheme, R, 12.0, 3.0)
+    for r in (1.5, 2.0, 0.5):
+        f = r ** np.arange(2 * R + 1)
+        _, _, beta, omp, omm = oracle.gp_weno(f, tab)
+        assert beta.min() > 1e-20  # eps = 1e-36 is negligible here
+        for m in range(R):
+            for om, key in ((omp, "gamma+"), (omm, "gamma-")):
+                g = np.asarray(tab[key], dtype=float)
+                expect = g[m + 1] / g[m] / r**4
+                assert om[m + 1] / om[m] == pytest.approx(expect, rel=1e-12)
+
+
+@pytest.mark.parametrize("b1", [1e-38, 1e-36, 1e-34, 1e-30])
+def test_eps_of_eq_weights_is_1e_minus_36(b1):
+    """R = 1 with data (0, 0, a): sub-stencil 0 holds zeros, so beta_0 = 0
+    exactly, and beta_1 = a^2 (K^-1)_11 = a^2 / (1 - k^2) for the 2x2 kernel
+    matrix of K(sigma) with off-diagonal k = exp(-1/(2 (sigma/dx)^2)) (Eqs.
+    (gp-smooth), (kmat)). Eq. (weights) then gives omega_1/omega_0 =
+    (gamma_1/gamma_0) (eps/(eps + beta_1))^2, which fixes eps: with a beta_1
+    of the order of 1e-36 the ratio moves by orders of magnitude if eps does."""
+    import mpmath as mp
+    mp.mp.dps = 40
+    sig = 3.0
+    k = mp.e ** (-1 / (2 * mp.mpf(sig) ** 2))
+    a = float(mp.sqrt(mp.mpf(b1) * (1 - k * k)))
+    tab = oracle.gp_tables(1, 12.0, sig)
+    _, _, beta, omp, omm = oracle.gp_weno(np.array([0.0, 0.0, a]), tab)
+    assert beta[0] == 0.0
+    bb = mp.mpf(a) ** 2 / (1 - k * k)
+    eps = mp.mpf("1e-36")
+    for om, key in ((omp, "gamma+"), (omm, "gamma-")):
+        g = tab[key]
+        expect = mp.mpf(g[1]) / mp.mpf(g[0]) * (eps / (eps + bb)) ** 2
+        assert om[1] / om[0] == pytest.approx(float(expect), rel=1e-12)
+
+
 # ---------------------------------------------------------------------------
 # Characteristic projection
 # ---------------------------------------------------------------------------
@@ -180,6 +227,65 @@ def test_flux_correction_exact_to_degree_five(k):
         assert abs(err) < 1e-13
     else:
         assert abs(err) > 1e-3
+
+
+@pytest.mark.parametrize("k", range(0, 10))
+def test_three_term_flux_correction_exact_to_degree_seven(k):
+    """With the sixth-difference term (-5/7168, the next term of the series in
+    Eq. (numFlux_cor)) the corrected flux recovers Fhat exactly for polynomial
+    Fhat of degree <= 7, and not beyond (same cell-average construction as
+    above, seven face fluxes)."""
+    def cell_avg(x):
+        return ((x + 0.5) ** (k + 1) - (x - 0.5) ** (k + 1)) / (k + 1)
+
+    x0 = 0.37
+    F7 = np.array([cell_avg(x0 + o) for o in range(-3, 4)])
+    err = oracle.flux_hat(F7) - x0**k
+    if k <= 7:
+        assert abs(err) < 1e-12
+    else:
+        assert abs(err) > 1e-4
+
+
+def test_three_term_correction_in_the_scheme_is_its_sixth_difference():
+    """In a whole right-hand side the third term changes only the corrected
+    fluxes, by -5/7168 times the sixth difference of the face fluxes. For a
+    density wave advected at u = 1 with constant pressure, the face fluxes of a
+    sampled sine have a sixth difference of about (2 pi dx)^6 times their
+    amplitude, so the two right-hand sides differ by little; across a jump the
+    sixth difference is O(1) and they differ by orders of magnitude more."""
+    N = 48
+    g = inputs.grid1d(N)
+    dx = g.dx[0]
+    x = (np.arange(N) + 0.5) * dx
+    diffs = {}
+    for name, rho in (("sine", 1 + 0.2 * np.sin(2 * np.pi * x)), ("sharp", 1 + 0.5 * (x > 0.5))):
+        U = inputs.uniform_state(g)
+        U[0] = rho
+        U[1] = rho * 1.0
+        U[2] = 1.0 / 0.4 + 0.5 * rho
+        L2 = oracle.OracleSolver(g, 2, 12 * dx, 3 * dx, flux_corr_terms=2).rhs(U)
+        L3 = oracle.OracleSolver(g, 2, 12 * dx, 3 * dx, flux_corr_terms=3).rhs(U)
+        diffs[name] = float(np.abs(L3 - L2).max())
+    # sixth difference of a sampled sine is (2 sin(pi dx))^6 ~ (2 pi dx)^6 times it
+    assert 0 < diffs["sine"] < 1e-3
+    assert diffs["sharp"] > 100 * diffs["sine"]
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_three_term_correction_keeps_free_stream_and_conservation(ndim):
+    g = {1: inputs.grid1d(40), 2: inputs.grid2d(24, 20), 3: inputs.grid3d(12, 10, 9)}[ndim]
+    U = inputs.uniform_state(g)
+    U0 = U.copy()
+    s = oracle.OracleSolver(g, 3, 12 * g.dx[0], 3 * g.dx[0], flux_corr_terms=3)
+    s.step(U, 0.01)
+    assert np.array_equal(U, U0)
+    U = inputs.random_smooth(g, seed=4)
+    tot0 = U.reshape(g.nv, -1).sum(axis=1)
+    s.run(U, 1.0, max_steps=10)
+    tot1 = U.reshape(g.nv, -1).sum(axis=1)
+    scale = np.abs(U).reshape(g.nv, -1).sum(axis=1)
+    assert np.all(np.abs(tot1 - tot0) <= 1e-13 * scale)
 
 
 # ---------------------------------------------------------------------------
