@@ -1,7 +1,8 @@
 /*
  * gpweno.h -- C ABI of libgpweno: the GP-WENO finite-difference (FD-Prim)
- * scheme for the compressible Euler equations on static uniform periodic grids,
- * on one AMD Instinct MI355X (gfx950).
+ * scheme for the compressible Euler equations on static uniform grids (periodic,
+ * outflow or reflecting boundaries per axis side), on one AMD Instinct MI355X
+ * (gfx950).
  *
  * Method (Reyes, Lee, Graziani, Tzeferacos, "A variable high-order
  * shock-capturing finite difference method with GP-WENO"):
@@ -12,7 +13,8 @@
  *     GP-WENO on characteristic variables (Sec. 3.2-3.3, Sec. 4 step 2, Sec. 7);
  *   - face fluxes come from an HLLC Riemann solver (Eq. (riemann_prob)) and are
  *     corrected to high order with alpha = -1/24, beta = 3/640
- *     (Eqs. (numFlux_cor), (FD-ders));
+ *     (Eqs. (numFlux_cor), (FD-ders)), optionally with the next term of the
+ *     same series (gpweno_options.flux_corr_terms);
  *   - time integration is third-order SSP (TVD) Runge-Kutta.
  *
  * Conventions shared by every entry point
@@ -58,14 +60,16 @@ typedef enum {
                               RK combination, dt and conservation sums in float64 */
 } gpweno_precision;
 
-/* Uniform periodic grid. Axes beyond ndim are ignored. */
+/* Boundary kind of one side of an axis. */
 typedef enum {
     GPWENO_BC_PERIODIC = 0, /* periodic images (both sides of the axis) */
     GPWENO_BC_OUTFLOW = 1,  /* zero-gradient ghosts: copies of the boundary cell */
     GPWENO_BC_REFLECT = 2   /* reflecting wall: mirror image about the boundary face,
-                               normal velocity reversed; needs n >= R + 3 */
+                               normal velocity reversed; needs n >= R + 3 (R + 4
+                               with flux_corr_terms = 3) */
 } gpweno_bc;
 
+/* Uniform grid. Axes beyond ndim are ignored. */
 typedef struct {
     int ndim;              /* 1, 2 or 3 */
     int n[3];              /* cells per axis */
@@ -109,6 +113,16 @@ typedef struct {
                               0: zero mean, the paper's default (default 0). No
                               effect on the Jiang-Shu indicators, which ignore
                               constants. */
+    int flux_corr_terms;   /* terms of the high-order flux correction of Eq.
+                              (numFlux_cor): 2 (default, the paper's): alpha = -1/24
+                              on the second and beta = 3/640 on the fourth difference
+                              of the face fluxes; 3: also -5/7168 on the sixth
+                              difference, the next term of the same series (the
+                              "+ ..." of that equation), exact for face fluxes that
+                              are polynomials of degree <= 7 instead of 5. 3 needs
+                              one more ghost cell per side (R + 4) and is offered for
+                              the schemes with GP indicators of zero mean (GP-WENO,
+                              WENO-GP); EINVAL otherwise. */
 } gpweno_options;
 
 typedef struct gpweno_ctx gpweno_ctx;
@@ -159,12 +173,16 @@ int gpweno_bind(gpweno_ctx *ctx, double *d_state, void *d_workspace);
  * not bound. */
 int gpweno_set_time(gpweno_ctx *ctx, double t, long nsteps);
 
-/* One SSP-RK3 step (enqueued, asynchronous): dt = cfl / max_i sum_d (|u_d|+c)/dx_d
- * from the state at the start of the step (or fixed_dt), clipped so that t does
- * not pass t_final; no-op when t >= t_final. The state is updated in place.
- * ESTATE if not bound. Failures inside the step are reported by the next
- * blocking call (gpweno_get_time / gpweno_run) as ENONPHYS. */
-int gpweno_step(gpweno_ctx *ctx, double t_final);
+/* One SSP-RK3 step: dt = cfl / max_i sum_d (|u_d|+c)/dx_d from the state at the
+ * start of the step (or fixed_dt), clipped so that t does not pass t_final;
+ * no-op when t >= t_final. The state is updated in place.
+ * dt_out: NULL enqueues the step and returns at once (asynchronous); failures
+ * inside the step are then reported by the next blocking call (gpweno_get_time /
+ * gpweno_run) as ENONPHYS. Non-NULL (host pointer) waits for the step and
+ * stores the dt it took (0 if it did not run: t >= t_final or an earlier
+ * failure), returning ENONPHYS if the step produced a non-physical state.
+ * ESTATE if not bound. */
+int gpweno_step(gpweno_ctx *ctx, double t_final, double *dt_out);
 
 /* The k-th of the 3 * ndim kernel launches that make up one gpweno_step
  * (stage k / ndim + 1, direction k % ndim), enqueued on its own. Enqueuing
@@ -185,8 +203,14 @@ int gpweno_step_kernel(gpweno_ctx *ctx, int k);
 int gpweno_run(gpweno_ctx *ctx, double t_final, long max_steps, long *nsteps_out, double *t_out);
 
 /* Blocking: current time, the last step's dt, and the total step count
- * (each nullable). Returns ENONPHYS if a non-physical state was detected. */
+ * (each nullable). Returns ENONPHYS if a non-physical state was detected, with
+ * the smallest flagged cell index in the error text and in *bad_cell of
+ * gpweno_get_failure. */
 int gpweno_get_time(gpweno_ctx *ctx, double *t, double *dt, long *nsteps);
+
+/* Blocking: whether a non-physical state was detected (*failed = 1) and the
+ * smallest flagged cell index (*bad_cell, -1 if none); each nullable. */
+int gpweno_get_failure(gpweno_ctx *ctx, int *failed, long *bad_cell);
 
 /* One evaluation of the right-hand side of Eq. (disc_fd) for an arbitrary device
  * state d_U (same layout as the bound state), written to d_L (same size):
@@ -205,6 +229,49 @@ int gpweno_rhs_dir(gpweno_ctx *ctx, int dir, const double *d_U, double *d_L, int
  * state, written to host out[nv], by a deterministic device reduction. */
 int gpweno_conserved_sums(gpweno_ctx *ctx, double *out);
 
+/* Host-only, no device work: the pre-simulation tables this context uses along
+ * axis dir (0 <= dir < ndim), built by gpweno_init from ell/dx_dir and
+ * sigma/dx_dir (Sec. 4 step 1), as float64 host arrays (each nullable, caller
+ * owned), row-major:
+ *   w_sub[2][R+1][R+1]: GP (or polynomial) weights w_m of sub-stencil m = 0..R
+ *     (nodes m-R .. m relative to the centre cell) at x_* = +1/2 ([0]) and
+ *     -1/2 ([1]), Eq. (q-intrp) on K_m of Eq. (kmat);
+ *   gam[2][R+1]: linear weights gamma_m at x_* = +1/2 and -1/2, the least-squares
+ *     solution of Eq. (gamm-system);
+ *   P[R+1][R+1]: rows v_i / sqrt(lambda_i) of K_m(sigma), Eq. (beta-eigen), so
+ *     that beta_m = sum_i (P_i . f_m)^2 for every m. The Jiang-Shu indicators of
+ *     GPWENO_WENO_JS differ per sub-stencil (gpweno_compute_tables gives them):
+ *     P must be NULL there.
+ * For GPWENO_GP_AO, w_sub, gam and P are those of its 3-point sub-stencils
+ * (R + 1 reads 3 in the sizes; gamma: the CWENO linear weights; the 5- and
+ * 7-point tables come from gpweno_compute_ao_tables). The float32 path uses these values
+ * rounded to float32. Errors: EINVAL (NULL context, dir out of range, P for
+ * WENO-JS). */
+int gpweno_get_tables(const gpweno_ctx *ctx, int dir, double *w_sub, double *gam, double *P);
+
+/* Host-only: accuracy of this context's tables, the largest relative difference
+ * over all axes between the weights solved directly at x_* = -1/2 and the
+ * mirror image of those at x_* = +1/2, which agree exactly in exact arithmetic.
+ * K of Eq. (kmat) loses conditioning as ell/dx grows (R = 3 in binary128:
+ * 1e-16 at 40 dx, 2e-14 at 51 dx, 2e-13 at 60 dx, 1e-12 at 80 dx, 7e-8 at
+ * 192 dx; R <= 2 stays below 1e-15 up to 220 dx), and the linear weights are
+ * only as accurate as this residual (within a factor of about 5 against
+ * 60-digit solves). A context whose residual exceeds 1e-13 runs in
+ * GPWENO_FP32 only: gpweno_set_options refuses GPWENO_FP64 for it, and it
+ * starts in GPWENO_FP32. Errors: EINVAL. */
+int gpweno_table_residual(const gpweno_ctx *ctx, double *residual);
+
+/* Test hook (enqueued on the context's stream): overwrites the bound state's
+ * density and total energy at cell index `cell` (0 <= cell < ncells, x fastest)
+ * with -1, a non-physical state. The next stage that reads it produces
+ * non-finite or non-physical values in the cells whose stencils contain it; the
+ * physical check of the stage flags the step, which then reports ENONPHYS
+ * through the normal path (gpweno_run, gpweno_get_time, gpweno_batch_status),
+ * with the smallest flagged cell index, which lies within R + 3 cells (R + 4
+ * with flux_corr_terms = 3) of `cell` along each axis. No GPU fault is
+ * involved. Errors: EINVAL (cell out of range), ESTATE (not bound). */
+int gpweno_debug_poison(gpweno_ctx *ctx, long cell);
+
 /* Host-only (no device needed): the pre-simulation tables of gpweno_init_scheme
  * for a scheme (gpweno_scheme), stencil radius R and length scales in units of
  * dx (ell_over_dx, sigma_over_dx; ell is unused by the polynomial schemes).
@@ -217,6 +284,11 @@ int gpweno_conserved_sums(gpweno_ctx *ctx, double *out);
 int gpweno_compute_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx,
                           double *w_plus, double *w_minus, double *gam_plus,
                           double *gam_minus, double *P);
+
+/* Host-only: the mirror residual (see gpweno_table_residual) of the tables
+ * gpweno_compute_tables builds for the same arguments, into *residual.
+ * Errors: EINVAL. */
+int gpweno_compute_table_residual(int scheme, int R, double ell_over_dx, double sigma_over_dx, double *residual);
 
 /* Host-only: the extra tables of GPWENO_GP_AO for length scales in units of dx.
  * w7[2][7] and w5[2][5]: GP weights of the 7- and 5-point stencils (nodes -3..3,

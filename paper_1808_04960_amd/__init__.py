@@ -39,7 +39,8 @@ class _Grid(ctypes.Structure):
 
 class _Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("cfl", ctypes.c_double), ("fixed_dt", ctypes.c_double),
-                ("positivity_fallback", ctypes.c_int), ("stream", ctypes.c_void_p), ("nonzero_mean", ctypes.c_int)]
+                ("positivity_fallback", ctypes.c_int), ("stream", ctypes.c_void_p), ("nonzero_mean", ctypes.c_int),
+                ("flux_corr_terms", ctypes.c_int)]
 
 
 _lib = None
@@ -66,9 +67,15 @@ def lib():
         L.gpweno_workspace_bytes.restype = ctypes.c_size_t
         L.gpweno_bind.argtypes = [vp, vp, vp]
         L.gpweno_set_time.argtypes = [vp, ctypes.c_double, ctypes.c_long]
-        L.gpweno_step.argtypes = [vp, ctypes.c_double]
+        L.gpweno_step.argtypes = [vp, ctypes.c_double, _dp]
         L.gpweno_run.argtypes = [vp, ctypes.c_double, ctypes.c_long, ctypes.POINTER(ctypes.c_long), _dp]
         L.gpweno_get_time.argtypes = [vp, _dp, _dp, ctypes.POINTER(ctypes.c_long)]
+        L.gpweno_get_failure.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_long)]
+        L.gpweno_get_tables.argtypes = [vp, ctypes.c_int, _dp, _dp, _dp]
+        L.gpweno_table_residual.argtypes = [vp, _dp]
+        L.gpweno_compute_table_residual.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                                    _dp]
+        L.gpweno_debug_poison.argtypes = [vp, ctypes.c_long]
         L.gpweno_rhs.argtypes = [vp, vp, vp]
         L.gpweno_rhs_dir.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int]
         L.gpweno_step_kernel.argtypes = [vp, ctypes.c_int]
@@ -128,6 +135,14 @@ def compute_tables(R, ell_over_dx, sigma_over_dx, scheme="gp-weno"):
     return {"w+": wp, "w-": wm, "gamma+": gp, "gamma-": gm, "P": P}
 
 
+def compute_table_residual(R, ell_over_dx, sigma_over_dx, scheme="gp-weno"):
+    """Host-only: the mirror residual of the tables compute_tables builds (the
+    accuracy the binary128 solves reach; see gpweno_table_residual)."""
+    r = ctypes.c_double()
+    _check(lib().gpweno_compute_table_residual(_scheme_id(scheme), R, ell_over_dx, sigma_over_dx, ctypes.byref(r)))
+    return r.value
+
+
 def compute_ao_tables(ell_over_dx, sigma_over_dx):
     """Host-only extra tables of the adaptive-order GP scheme (binary128 rounded
     to float64): 'w7' (2, 7), 'w5' (2, 5) (rows: x_* = +1/2, -1/2), 'P7', 'P5',
@@ -168,7 +183,8 @@ class Solver:
     """
 
     def __init__(self, grid, R, ell, sigma, gamma=1.4, precision="fp64", cfl=0.4, fixed_dt=0.0,
-                 positivity_fallback=False, U0=None, device=None, stream=None, scheme="gp-weno", nonzero_mean=False):
+                 positivity_fallback=False, U0=None, device=None, stream=None, scheme="gp-weno", nonzero_mean=False,
+                 flux_corr_terms=2):
         import torch
 
         if not torch.cuda.is_available():
@@ -191,16 +207,21 @@ class Solver:
             self.workspace = torch.empty(lib().gpweno_workspace_bytes(self._ctx), dtype=torch.uint8,
                                          device=self.device)
         self._bound = False
+        self.scheme = scheme
         self.nonzero_mean = bool(nonzero_mean)
+        self.flux_corr_terms = int(flux_corr_terms)
         self.set_options(precision, cfl, fixed_dt, positivity_fallback)
         if U0 is not None:
             self.set_state(U0)
 
     # -- configuration -------------------------------------------------------
-    def set_options(self, precision="fp64", cfl=0.4, fixed_dt=0.0, positivity_fallback=False, nonzero_mean=None):
-        """nonzero_mean: None keeps the current choice (see gpweno_options)."""
+    def set_options(self, precision="fp64", cfl=0.4, fixed_dt=0.0, positivity_fallback=False, nonzero_mean=None,
+                    flux_corr_terms=None):
+        """nonzero_mean, flux_corr_terms: None keeps the current choice (see gpweno_options)."""
         if nonzero_mean is not None:
             self.nonzero_mean = bool(nonzero_mean)
+        if flux_corr_terms is not None:
+            self.flux_corr_terms = int(flux_corr_terms)
         o = _Options()
         o.precision = {"fp64": FP64, "fp32": FP32}[precision]
         o.cfl = cfl
@@ -208,8 +229,9 @@ class Solver:
         o.positivity_fallback = 1 if positivity_fallback else 0
         o.stream = self.stream.cuda_stream
         o.nonzero_mean = 1 if self.nonzero_mean else 0
-        self.precision = precision
+        o.flux_corr_terms = self.flux_corr_terms
         _check(lib().gpweno_set_options(self._ctx, ctypes.byref(o)), self._ctx)
+        self.precision = precision
 
     # -- state ---------------------------------------------------------------
     def set_state(self, U, t=0.0, nsteps=0):
@@ -235,8 +257,15 @@ class Solver:
         return host.numpy()
 
     # -- time stepping ---------------------------------------------------------
-    def step(self, t_final):
-        _check(lib().gpweno_step(self._ctx, t_final), self._ctx)
+    def step(self, t_final, wait=False):
+        """One step toward t_final. wait=False enqueues it and returns None;
+        wait=True blocks and returns the dt the step took (0 if it did not run)."""
+        if not wait:
+            _check(lib().gpweno_step(self._ctx, t_final, None), self._ctx)
+            return None
+        dt = ctypes.c_double()
+        _check(lib().gpweno_step(self._ctx, t_final, ctypes.byref(dt)), self._ctx)
+        return dt.value
 
     def set_end(self, t_final, step_limit=-1):
         """End time and absolute step limit honoured by batched execution (enqueued)."""
@@ -258,6 +287,32 @@ class Solver:
         n = ctypes.c_long()
         _check(lib().gpweno_get_time(self._ctx, ctypes.byref(t), ctypes.byref(dt), ctypes.byref(n)), self._ctx)
         return t.value, dt.value, n.value
+
+    def failure(self):
+        """Blocking: (failed, smallest flagged cell index or -1)."""
+        f, cell = ctypes.c_int(), ctypes.c_long()
+        _check(lib().gpweno_get_failure(self._ctx, ctypes.byref(f), ctypes.byref(cell)), self._ctx)
+        return bool(f.value), cell.value
+
+    def tables(self, dir=0):
+        """The tables this context uses along axis dir: 'w' (2, n, n) with rows
+        x_* = +1/2 and -1/2, 'gamma' (2, n), 'P' (n, n) (None for WENO-JS), where
+        n = R + 1 (3 for GP-AO's sub-stencils)."""
+        n = 3 if self.scheme == "gp-ao" else self.R + 1
+        w, g, P = np.zeros((2, n, n)), np.zeros((2, n)), np.zeros((n, n))
+        ptr = lambda a: a.ctypes.data_as(_dp)  # noqa: E731
+        js = self.scheme == "weno-js"
+        _check(lib().gpweno_get_tables(self._ctx, dir, ptr(w), ptr(g), None if js else ptr(P)), self._ctx)
+        return {"w": w, "gamma": g, "P": None if js else P}
+
+    def table_residual(self):
+        r = ctypes.c_double()
+        _check(lib().gpweno_table_residual(self._ctx, ctypes.byref(r)), self._ctx)
+        return r.value
+
+    def debug_poison(self, cell):
+        """Test hook: make cell `cell` of the state non-physical (enqueued)."""
+        _check(lib().gpweno_debug_poison(self._ctx, int(cell)), self._ctx)
 
     def synchronize(self):
         self.stream.synchronize()

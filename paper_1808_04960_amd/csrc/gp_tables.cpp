@@ -293,24 +293,26 @@ bool kernel_rows(int N, q128 sig, double *P /* [N][N] */, double *cN) {
 // worth using), so the tolerance is 1e-6 relative.
 constexpr double MIRROR_TOL = 1e-6;
 
-bool mirror_agrees(int n, const q128 *wp, const q128 *wm) {  // one stencil of n nodes
-    q128 scale = 0;
+// Largest relative difference between the two solves: |w_- - mirror(w_+)| over
+// the largest |w_+| of one stencil of n nodes.
+q128 mirror_residual(int n, const q128 *wp, const q128 *wm) {
+    q128 scale = 0, r = 0;
     for (int j = 0; j < n; ++j) scale = fmaxq(scale, fabsq(wp[j]));
-    for (int j = 0; j < n; ++j)
-        if (!(fabsq(wm[j] - wp[n - 1 - j]) <= (q128)MIRROR_TOL * scale)) return false;
-    return true;
+    for (int j = 0; j < n; ++j) r = fmaxq(r, fabsq(wm[j] - wp[n - 1 - j]) / scale);
+    return r;
 }
 
-bool mirror_agrees(int R, const q128 wp[4][4], const q128 wm[4][4], const q128 *gp, const q128 *gm) {
-    q128 scale = 0;
+// The same over every sub-stencil's weights (relative to the largest |w_+|) and
+// the linear weights (absolute: the gammas sum to about 1).
+q128 mirror_residual(int R, const q128 wp[4][4], const q128 wm[4][4], const q128 *gp, const q128 *gm) {
+    q128 scale = 0, r = 0;
     for (int m = 0; m <= R; ++m)
         for (int j = 0; j <= R; ++j) scale = fmaxq(scale, fabsq(wp[m][j]));
     for (int m = 0; m <= R; ++m) {
-        if (!(fabsq(gm[m] - gp[R - m]) <= (q128)MIRROR_TOL)) return false;  // sum of gamma is about 1
-        for (int j = 0; j <= R; ++j)
-            if (!(fabsq(wm[m][j] - wp[R - m][R - j]) <= (q128)MIRROR_TOL * scale)) return false;
+        r = fmaxq(r, fabsq(gm[m] - gp[R - m]));
+        for (int j = 0; j <= R; ++j) r = fmaxq(r, fabsq(wm[m][j] - wp[R - m][R - j]) / scale);
     }
-    return true;
+    return r;
 }
 
 }  // namespace
@@ -322,7 +324,9 @@ int gpw_build_ao_tables(double ell_over_dx, double sigma_over_dx, GpAoTablesF64 
     q128 w7p[NMAX], w7m[NMAX], w5p[NMAX], w5m[NMAX];
     if (!full_weights(3, ell, (q128)0.5, w7p) || !full_weights(3, ell, (q128)-0.5, w7m)) return -2;
     if (!full_weights(2, ell, (q128)0.5, w5p) || !full_weights(2, ell, (q128)-0.5, w5m)) return -2;
-    if (!mirror_agrees(7, w7p, w7m) || !mirror_agrees(5, w5p, w5m)) return -5;
+    const q128 res = fmaxq(mirror_residual(7, w7p, w7m), mirror_residual(5, w5p, w5m));
+    if (!(res <= (q128)MIRROR_TOL)) return -5;
+    out->mirror_residual = (double)res;
     for (int j = 0; j < 7; ++j) {
         out->w7_plus[j] = (double)w7p[j];
         out->w7_minus[j] = (double)w7m[j];
@@ -432,7 +436,8 @@ int gpw_build_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx
         if (!poly_weights_for_point(R, (q128)0.5, wp, gp)) return -2;
         if (!poly_weights_for_point(R, (q128)-0.5, wm, gm)) return -2;
     }
-    if (!mirror_agrees(R, wp, wm, gp, gm)) return -5;
+    const q128 res = mirror_residual(R, wp, wm, gp, gm);
+    if (!(res <= (q128)MIRROR_TOL)) return -5;
     if (scheme == GPW_SCHEME_WENO_JS) {
         // factor each B_m = V diag(lambda) V^T; rows sqrt(lambda_i) v_i in order of
         // decreasing lambda. B_m is positive semi-definite of rank R (its null
@@ -483,5 +488,6 @@ int gpw_build_tables(int scheme, int R, double ell_over_dx, double sigma_over_dx
             out->gw_plus[m][j] = (double)(gp[m] * wp[m][j]);
         }
     }
+    out->mirror_residual = (double)res;
     return 0;
 }

@@ -15,6 +15,10 @@ struct GpTablesF64 {
     //   R = 3: rows 0, 1: Ps[i][0] s_0 + Ps[i][1] s_1;  rows 2, 3: Ps[i][0] d_0 + Ps[i][1] d_1.
     double Ps[4][2];
     double gw_plus[4][4];  // gam_plus[m] * w_plus[m][j], rounded once from binary128
+    // largest relative difference between w_minus / gam_minus solved directly and
+    // the mirror image of w_plus / gam_plus: zero in exact arithmetic, so it
+    // measures how far the binary128 solves drift as K loses conditioning
+    double mirror_residual;
 };
 
 // Interpolation schemes (values of gpweno_scheme).
@@ -29,6 +33,7 @@ struct GpAoTablesF64 {
     double w5_plus[5], w5_minus[5];
     double P7[7][7], P5[5][5], P3[3][3];
     double c[3];           // N = 7, 5, 3
+    double mirror_residual;  // as GpTablesF64::mirror_residual, for the 7- and 5-point weights
 };
 
 // Same return codes as gpw_build_tables (-4 does not occur).

@@ -9,7 +9,7 @@
 // writes U^{n+1} in place, reduces its CFL speed for the next step, and its
 // last block advances t and the step count.
 // Because dt, t and the stop condition live on the device, a run replays a
-// captured HIP graph of several steps and synchronises once per replay.
+// sequence of captured HIP graph replays and synchronises once per sequence.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,9 +28,16 @@
 
 namespace {
 
-constexpr int TOUT = 58;            // cells produced per 64-cell run
 constexpr int NPART = 1024;         // partial sums of the conservation reduction
-constexpr int GRAPH_STEPS = 32;     // steps per captured graph
+// Steps per captured graph. A run of n steps replays them largest first (the
+// binary digits of n below 32), so it launches exactly the steps it asks for
+// with at most six replays per 63 steps.
+constexpr int NGRAPH = 6;
+constexpr int GRAPH_STEPS[NGRAPH] = {32, 16, 8, 4, 2, 1};
+// Steps enqueued between two reads of the control block in gpweno_run.
+constexpr long long RUN_CHUNK = 256;
+// A float64 context needs tables accurate to this (gpweno_table_residual).
+constexpr double FP64_TABLE_RESIDUAL = 1e-13;
 
 thread_local std::string g_tls_error = "";
 
@@ -49,6 +56,12 @@ struct gpweno_ctx {
     GpAoTablesF64 ao64[3];          // adaptive-order GP only
     gpw::Tab<double> tabd[3];
     gpw::Tab<float> tabf[3];
+    double residual = 0.0;          // largest mirror residual of the tables over the axes
+    // the step state as last read from the device (t, dt, step count) and
+    // whether it is known to hold (set_time makes it exact; a step or batch run
+    // outdates it). gpweno_run uses it only to size its first chunk of steps.
+    gpw::StepRec shadow{0.0, 0.0, 0, 0};
+    bool shadow_ok = false;
     int device;
     gpw::Ctl* d_ctl = nullptr;
     gpw::Ctl* h_ctl = nullptr;      // pinned mirror
@@ -58,7 +71,7 @@ struct gpweno_ctx {
     double* U2 = nullptr;
     double* dU = nullptr;
     double* partials = nullptr;
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph[NGRAPH] = {};  // GRAPH_STEPS[i] steps each
     std::string err;
 };
 
@@ -86,18 +99,22 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 hipStream_t user_stream(const gpweno_ctx* c) { return static_cast<hipStream_t>(c->opt.stream); }
 
 void drop_graph(gpweno_ctx* c) {
-    if (c->graph) {
-        (void)hipGraphExecDestroy(c->graph);
-        c->graph = nullptr;
+    for (auto& g : c->graph) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
     }
 }
+
+// Terms of the flux correction, and the cells a 64-lane run produces with them.
+int corr_terms(const gpweno_ctx* c) { return c->opt.flux_corr_terms; }
+int run_cells(const gpweno_ctx* c) { return gpw::run_out(corr_terms(c)); }
 
 template <typename Real>
 gpw::SweepArgs<Real> base_args(const gpweno_ctx* c, int dir) {
     gpw::SweepArgs<Real> a;
     std::memset(&a, 0, sizeof a);
     for (int d = 0; d < 3; ++d) a.n[d] = d < c->grid.ndim ? c->grid.n[d] : 1;
-    a.nseg = (a.n[dir] + TOUT - 1) / TOUT;
+    a.nseg = (a.n[dir] + run_cells(c) - 1) / run_cells(c);
     a.ncell = c->ncell;
     a.inv_dx = 1.0 / c->dx[dir];
     for (int d = 0; d < 3; ++d) a.inv_dx_all[d] = d < c->grid.ndim ? 1.0 / c->dx[d] : 0.0;
@@ -135,18 +152,18 @@ bool general_bc(const gpweno_grid& g, int dir) {
 int launch(gpweno_ctx* c, int dir, const double* in, const double* un, double* acc, double* out, int stage,
            bool fin, bool first, bool step_start, hipStream_t s) {
     const bool fp32 = c->opt.precision == GPWENO_FP32;
+    const gpw::LaunchSel k{dir, c->R, fin, indicator_kind(c), general_bc(c->grid, dir), corr_terms(c), false};
     hipError_t e;
     if (fp32) {
         auto a = base_args<float>(c, dir);
         a.U = in; a.Un = un; a.dU = acc; a.Uout = out;
         a.first = first; a.stage = stage; a.step_start = step_start;
-        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, true, fin, indicator_kind(c), general_bc(c->grid, dir), &a, s);
+        e = gpw::launch_sweep(c->grid.ndim, true, k, &a, 0, s);
     } else {
         auto a = base_args<double>(c, dir);
         a.U = in; a.Un = un; a.dU = acc; a.Uout = out;
         a.first = first; a.stage = stage; a.step_start = step_start;
-        e = gpw::launch_sweep(c->grid.ndim, dir, c->R, false, fin, indicator_kind(c), general_bc(c->grid, dir), &a,
-                              s);
+        e = gpw::launch_sweep(c->grid.ndim, false, k, &a, 0, s);
     }
     if (e != hipSuccess) return fail(c, GPWENO_EHIP, "sweep launch (dir %d): %s", dir, hipGetErrorString(e));
     return GPWENO_OK;
@@ -184,14 +201,14 @@ int check_err(gpweno_ctx* c) {
     return GPWENO_OK;
 }
 
-// Captures GRAPH_STEPS steps on the private stream (capture records, it does
+// Captures GRAPH_STEPS[i] steps on the private stream (capture records, it does
 // not execute); the graph is launched on the caller's stream.
-int ensure_graph(gpweno_ctx* c) {
-    if (c->graph) return GPWENO_OK;
+int ensure_graph(gpweno_ctx* c, int i) {
+    if (c->graph[i]) return GPWENO_OK;
     hipStream_t s = c->own_stream;
     HIP_TRY(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     int st = GPWENO_OK;
-    for (int k = 0; k < GRAPH_STEPS && st == GPWENO_OK; ++k) st = enqueue_step(c, s);
+    for (int k = 0; k < GRAPH_STEPS[i] && st == GPWENO_OK; ++k) st = enqueue_step(c, s);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (st) {
@@ -199,18 +216,37 @@ int ensure_graph(gpweno_ctx* c) {
         return st;
     }
     if (e != hipSuccess) return fail(c, GPWENO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&c->graph[i], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
-        c->graph = nullptr;
+        c->graph[i] = nullptr;
         return fail(c, GPWENO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
     return GPWENO_OK;
 }
 
+// Enqueues exactly n steps as graph replays, largest graphs first.
+int enqueue_graph_steps(gpweno_ctx* c, long long n, hipStream_t s) {
+    for (int i = 0; i < NGRAPH; ++i) {
+        const long long reps = n / GRAPH_STEPS[i];
+        n -= reps * GRAPH_STEPS[i];
+        if (reps == 0) continue;
+        int st = ensure_graph(c, i);
+        if (st) return st;
+        for (long long r = 0; r < reps; ++r) HIP_TRY(c, hipGraphLaunch(c->graph[i], s));
+    }
+    return GPWENO_OK;
+}
+
+// Ghost cells per side a sweep reads: the stencil radius R, the NC face fluxes
+// either side of a face that the correction takes, and the face of the
+// difference. A reflecting side mirrors that many distinct interior cells.
+int ghost_depth(int R, int nc) { return R + 1 + nc; }
+
 bool valid_options(const gpweno_options* o) {
     return o && (o->precision == GPWENO_FP64 || o->precision == GPWENO_FP32) && o->cfl > 0 &&
-           std::isfinite(o->cfl) && o->fixed_dt >= 0 && std::isfinite(o->fixed_dt);
+           std::isfinite(o->cfl) && o->fixed_dt >= 0 && std::isfinite(o->fixed_dt) &&
+           (o->flux_corr_terms == 2 || o->flux_corr_terms == 3);
 }
 
 bool valid_scheme(int scheme) {
@@ -285,6 +321,23 @@ int gpweno_compute_tables(int scheme, int R, double ell_over_dx, double sigma_ov
     if (gam_plus) std::memcpy(gam_plus, t.gam_plus, sizeof t.gam_plus);
     if (gam_minus) std::memcpy(gam_minus, t.gam_minus, sizeof t.gam_minus);
     if (P) std::memcpy(P, t.P, sizeof t.P);
+    return GPWENO_OK;
+}
+
+int gpweno_compute_table_residual(int scheme, int R, double ell_over_dx, double sigma_over_dx, double* residual) {
+    if (!residual) return fail(nullptr, GPWENO_EINVAL, "NULL residual");
+    if (!valid_scheme(scheme)) return fail(nullptr, GPWENO_EINVAL, "unknown scheme %d", scheme);
+    if (R < 1 || R > 3) return fail(nullptr, GPWENO_EINVAL, "R must be 1, 2 or 3 (got %d)", R);
+    if (scheme == GPWENO_WENO_JS && R > 2) return fail(nullptr, GPWENO_EINVAL, "WENO-JS needs R = 1 or 2");
+    if (scheme == GPWENO_GP_AO && R < 2) return fail(nullptr, GPWENO_EINVAL, "GP-AO needs R = 2 or 3");
+    if (!(ell_over_dx > 0) || !std::isfinite(ell_over_dx) || !(sigma_over_dx > 0) || !std::isfinite(sigma_over_dx))
+        return fail(nullptr, GPWENO_EINVAL, "length scales must be positive and finite");
+    GpTablesF64 t;
+    GpAoTablesF64 ao;
+    int st = scheme == GPWENO_GP_AO ? build_ao(ell_over_dx, sigma_over_dx, &t, &ao)
+                                    : gpw_build_tables(scheme, R, ell_over_dx, sigma_over_dx, &t);
+    if (st) return fail(nullptr, GPWENO_EINVAL, "table construction failed (%d)", st);
+    *residual = scheme == GPWENO_GP_AO ? std::max(t.mirror_residual, ao.mirror_residual) : t.mirror_residual;
     return GPWENO_OK;
 }
 
@@ -376,21 +429,25 @@ int gpweno_init_scheme(const gpweno_grid* grid, int scheme, int R, double ell, d
         }
         fill_tab(c->tabd[d], c->tab64[d]);
         fill_tab(c->tabf[d], c->tab64[d]);
+        c->residual = std::max(c->residual, c->tab64[d].mirror_residual);
         if (scheme == GPWENO_GP_AO) {
             fill_ao(c->tabd[d].ao, c->ao64[d]);
             fill_ao(c->tabf[d].ao, c->ao64[d]);
+            c->residual = std::max(c->residual, c->ao64[d].mirror_residual);
         }
     }
     if (c->ncell > (1ll << 40)) {
         delete c;
         return fail(nullptr, GPWENO_EINVAL, "grid too large");
     }
-    c->opt.precision = GPWENO_FP64;
+    // tables too badly conditioned for float64 parity run in float32 only
+    c->opt.precision = c->residual > FP64_TABLE_RESIDUAL ? GPWENO_FP32 : GPWENO_FP64;
     c->opt.cfl = 0.4;
     c->opt.fixed_dt = 0.0;
     c->opt.positivity_fallback = 0;
     c->opt.stream = nullptr;
     c->opt.nonzero_mean = 0;
+    c->opt.flux_corr_terms = 2;
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipMalloc(&c->d_ctl, sizeof(gpw::Ctl));
     if (e == hipSuccess) e = hipHostMalloc(&c->h_ctl, sizeof(gpw::Ctl), hipHostMallocDefault);
@@ -409,9 +466,24 @@ int gpweno_init_scheme(const gpweno_grid* grid, int scheme, int R, double ell, d
 int gpweno_set_options(gpweno_ctx* c, const gpweno_options* o) {
     if (!c) return fail(nullptr, GPWENO_EINVAL, "NULL context");
     if (!valid_options(o)) return fail(c, GPWENO_EINVAL, "invalid options");
+    if (o->precision == GPWENO_FP64 && c->residual > FP64_TABLE_RESIDUAL)
+        return fail(c, GPWENO_EINVAL,
+                    "the tables hold only %.1e relative accuracy (ell/dx too large for R = %d): GPWENO_FP32 only",
+                    c->residual, c->R);
+    if (o->flux_corr_terms == 3) {
+        const bool gp_zero_mean = (c->scheme == GPWENO_GP_WENO || c->scheme == GPWENO_WENO_GP) && !o->nonzero_mean;
+        if (!gp_zero_mean)
+            return fail(c, GPWENO_EINVAL, "flux_corr_terms = 3 needs GP-WENO or WENO-GP with zero-mean indicators");
+    }
+    for (int d = 0; d < c->grid.ndim; ++d)
+        if ((c->grid.bc[d][0] == GPWENO_BC_REFLECT || c->grid.bc[d][1] == GPWENO_BC_REFLECT) &&
+            c->grid.n[d] < ghost_depth(c->R, o->flux_corr_terms))
+            return fail(c, GPWENO_EINVAL, "axis %d: a reflecting side needs n >= %d", d,
+                        ghost_depth(c->R, o->flux_corr_terms));
     const bool changes_graph = o->precision != c->opt.precision ||
                                o->positivity_fallback != c->opt.positivity_fallback || o->stream != c->opt.stream ||
-                               (o->nonzero_mean != 0) != (c->opt.nonzero_mean != 0);
+                               (o->nonzero_mean != 0) != (c->opt.nonzero_mean != 0) ||
+                               o->flux_corr_terms != c->opt.flux_corr_terms;
     const bool changes_rule = o->cfl != c->opt.cfl || o->fixed_dt != c->opt.fixed_dt;
     c->opt = *o;
     if (changes_graph) drop_graph(c);
@@ -422,10 +494,9 @@ int gpweno_set_options(gpweno_ctx* c, const gpweno_options* o) {
                                             gpw::current_rec(*c->h_ctl).nsteps, c->opt.cfl, c->opt.fixed_dt,
                                             user_stream(c));
         if (e != hipSuccess) return fail(c, GPWENO_EHIP, "set_time launch: %s", hipGetErrorString(e));
-        const int n[3] = {c->grid.n[0], c->grid.n[1], c->grid.n[2]};
         const double ix[3] = {1.0 / c->dx[0], c->grid.ndim > 1 ? 1.0 / c->dx[1] : 0.0,
                               c->grid.ndim > 2 ? 1.0 / c->dx[2] : 0.0};
-        e = gpw::launch_speed(c->grid.ndim, c->state, c->ncell, n, ix, c->gamma, c->d_ctl, user_stream(c));
+        e = gpw::launch_speed(c->grid.ndim, c->state, c->ncell, ix, c->gamma, c->d_ctl, user_stream(c));
         if (e != hipSuccess) return fail(c, GPWENO_EHIP, "speed launch: %s", hipGetErrorString(e));
     }
     return GPWENO_OK;
@@ -452,10 +523,11 @@ int gpweno_set_time(gpweno_ctx* c, double t, long nsteps) {
     hipStream_t s = user_stream(c);
     hipError_t e = gpw::launch_set_time(c->d_ctl, t, nsteps, c->opt.cfl, c->opt.fixed_dt, s);
     if (e != hipSuccess) return fail(c, GPWENO_EHIP, "set_time launch: %s", hipGetErrorString(e));
-    const int n[3] = {c->grid.n[0], c->grid.n[1], c->grid.n[2]};
+    c->shadow = gpw::StepRec{t, 0.0, (long long)nsteps, 0};
+    c->shadow_ok = true;
     const double ix[3] = {1.0 / c->dx[0], c->grid.ndim > 1 ? 1.0 / c->dx[1] : 0.0,
                           c->grid.ndim > 2 ? 1.0 / c->dx[2] : 0.0};
-    e = gpw::launch_speed(c->grid.ndim, c->state, c->ncell, n, ix, c->gamma, c->d_ctl, s);
+    e = gpw::launch_speed(c->grid.ndim, c->state, c->ncell, ix, c->gamma, c->d_ctl, s);
     if (e != hipSuccess) return fail(c, GPWENO_EHIP, "speed launch: %s", hipGetErrorString(e));
     return GPWENO_OK;
 }
@@ -482,13 +554,26 @@ int gpweno_bind(gpweno_ctx* c, double* d_state, void* d_workspace) {
     return gpweno_set_time(c, 0.0, 0);
 }
 
-int gpweno_step(gpweno_ctx* c, double t_final) {
+int gpweno_step(gpweno_ctx* c, double t_final, double* dt_out) {
     if (!c) return fail(nullptr, GPWENO_EINVAL, "NULL context");
     if (!c->state) return fail(c, GPWENO_ESTATE, "no state bound");
     hipStream_t s = user_stream(c);
+    long long before = 0;
+    int st;
+    if (dt_out) {
+        *dt_out = 0.0;
+        if ((st = read_ctl(c, s))) return st;
+        before = gpw::current_rec(*c->h_ctl).nsteps;
+    }
     hipError_t e = gpw::launch_set_run(c->d_ctl, t_final, LLONG_MAX, s);
     if (e != hipSuccess) return fail(c, GPWENO_EHIP, "set_run launch: %s", hipGetErrorString(e));
-    return enqueue_step(c, s);
+    c->shadow_ok = false;
+    if ((st = enqueue_step(c, s))) return st;
+    if (!dt_out) return GPWENO_OK;
+    if ((st = read_ctl(c, s))) return st;
+    const gpw::StepRec& r = gpw::current_rec(*c->h_ctl);
+    if (r.nsteps > before) *dt_out = r.dt;
+    return check_err(c);
 }
 
 int gpweno_run(gpweno_ctx* c, double t_final, long max_steps, long* nsteps_out, double* t_out) {
@@ -496,29 +581,49 @@ int gpweno_run(gpweno_ctx* c, double t_final, long max_steps, long* nsteps_out, 
     if (!c->state) return fail(c, GPWENO_ESTATE, "no state bound");
     if (nsteps_out) *nsteps_out = 0;
     hipStream_t s = user_stream(c);
-    int st = read_ctl(c, s);
-    if (st) return st;
-    if ((st = check_err(c))) return st;
-    const long long start = gpw::current_rec(*c->h_ctl).nsteps;
-    const long long limit = max_steps < 0 ? LLONG_MAX : start + max_steps;
-    hipError_t e = gpw::launch_set_run(c->d_ctl, t_final, limit, s);
+    // the limit counts from the step count the device holds when the run starts
+    hipError_t e = gpw::launch_set_run_rel(c->d_ctl, t_final, max_steps < 0 ? -1 : (long long)max_steps, s);
     if (e != hipSuccess) return fail(c, GPWENO_EHIP, "set_run launch: %s", hipGetErrorString(e));
-    while (gpw::current_rec(*c->h_ctl).t < t_final && gpw::current_rec(*c->h_ctl).nsteps < limit) {
-        const gpw::StepRec before = gpw::current_rec(*c->h_ctl);
-        if ((st = ensure_graph(c))) return st;
-        HIP_TRY(c, hipGraphLaunch(c->graph, s));
+    // steps per chunk: what remains of the step limit, and no more than the last
+    // known dt says remain to t_final, so that hardly any enqueued step finds the
+    // run already over; one read of the control block per chunk
+    long long remaining = max_steps < 0 ? LLONG_MAX : (long long)max_steps;
+    gpw::StepRec last = c->shadow;
+    bool known = c->shadow_ok;
+    double t_prev = 0.0;
+    long long n_prev = 0;
+    bool first = true;
+    int st = GPWENO_OK;
+    for (;;) {
+        long long plan = std::min(remaining, RUN_CHUNK);
+        if (known && last.dt > 0) {
+            const double est = (t_final - last.t) / last.dt;
+            if (est < (double)plan) plan = std::max(1ll, (long long)est);
+        }
+        if ((st = enqueue_graph_steps(c, plan, s))) return st;
         if ((st = read_ctl(c, s))) return st;
+        const gpw::Ctl& h = *c->h_ctl;
+        last = gpw::current_rec(h);
+        known = true;
+        c->shadow = last;
+        c->shadow_ok = true;
         if ((st = check_err(c))) break;
-        // a replay that moves neither the step count nor the time cannot finish
-        const gpw::StepRec& after = gpw::current_rec(*c->h_ctl);
-        if (after.nsteps == before.nsteps || !(after.t > before.t)) {
-            st = fail(c, GPWENO_ESTATE, "run stalled at step %lld, t = %.17g (time step %.3g)", after.nsteps, after.t,
-                      after.dt);
+        if (!(last.t < t_final) || last.nsteps >= h.step_limit) break;
+        // a chunk that moves neither the step count nor the time cannot finish
+        const double t_before = first ? h.run_t0 : t_prev;
+        const long long n_before = first ? h.run_start : n_prev;
+        if (last.nsteps == n_before || !(last.t > t_before)) {
+            st = fail(c, GPWENO_ESTATE, "run stalled at step %lld, t = %.17g (time step %.3g)", last.nsteps, last.t,
+                      last.dt);
             break;
         }
+        remaining = h.step_limit - last.nsteps;
+        t_prev = last.t;
+        n_prev = last.nsteps;
+        first = false;
     }
-    if (nsteps_out) *nsteps_out = (long)(gpw::current_rec(*c->h_ctl).nsteps - start);
-    if (t_out) *t_out = gpw::current_rec(*c->h_ctl).t;
+    if (nsteps_out) *nsteps_out = (long)(last.nsteps - c->h_ctl->run_start);
+    if (t_out) *t_out = last.t;
     return st;
 }
 
@@ -560,6 +665,7 @@ int gpweno_step_kernel(gpweno_ctx* c, int k) {
     if (!c) return fail(nullptr, GPWENO_EINVAL, "NULL context");
     if (!c->state) return fail(c, GPWENO_ESTATE, "no state bound");
     if (k < 0 || k >= 3 * c->grid.ndim) return fail(c, GPWENO_EINVAL, "k must be in [0, 3 ndim)");
+    c->shadow_ok = false;
     return launch_step_kernel(c, k, user_stream(c));
 }
 
@@ -572,6 +678,56 @@ int gpweno_conserved_sums(gpweno_ctx* c, double* out) {
     int st = read_ctl(c, s);
     if (st) return st;
     for (int k = 0; k < c->nv; ++k) out[k] = c->h_ctl->sums[k];
+    return GPWENO_OK;
+}
+
+int gpweno_get_failure(gpweno_ctx* c, int* failed, long* bad_cell) {
+    if (!c) return fail(nullptr, GPWENO_EINVAL, "NULL context");
+    int st = read_ctl(c, user_stream(c));
+    if (st) return st;
+    const bool f = c->h_ctl->err != 0;
+    if (failed) *failed = f ? 1 : 0;
+    if (bad_cell) *bad_cell = f ? (long)c->h_ctl->bad_cell : -1;
+    return GPWENO_OK;
+}
+
+int gpweno_get_tables(const gpweno_ctx* c, int dir, double* w_sub, double* gam, double* P) {
+    if (!c) return fail(nullptr, GPWENO_EINVAL, "NULL context");
+    gpweno_ctx* cm = const_cast<gpweno_ctx*>(c);  // the error text only
+    if (dir < 0 || dir >= c->grid.ndim) return fail(cm, GPWENO_EINVAL, "dir must be in [0, ndim)");
+    if (P && c->scheme == GPWENO_WENO_JS)
+        return fail(cm, GPWENO_EINVAL, "WENO-JS indicators differ per sub-stencil: pass P = NULL");
+    const GpTablesF64& t = c->tab64[dir];
+    const int n = (c->scheme == GPWENO_GP_AO ? 2 : c->R) + 1;  // GP-AO: its 3-point sub-stencils
+    for (int m = 0; m < n; ++m) {
+        if (gam) {
+            gam[m] = t.gam_plus[m];
+            gam[n + m] = t.gam_minus[m];
+        }
+        for (int j = 0; j < n; ++j) {
+            if (w_sub) {
+                w_sub[m * n + j] = t.w_plus[m][j];
+                w_sub[n * n + m * n + j] = t.w_minus[m][j];
+            }
+            if (P) P[m * n + j] = t.P[0][m][j];
+        }
+    }
+    return GPWENO_OK;
+}
+
+int gpweno_table_residual(const gpweno_ctx* c, double* residual) {
+    if (!c || !residual) return fail(const_cast<gpweno_ctx*>(c), GPWENO_EINVAL, "NULL argument");
+    *residual = c->residual;
+    return GPWENO_OK;
+}
+
+int gpweno_debug_poison(gpweno_ctx* c, long cell) {
+    if (!c) return fail(nullptr, GPWENO_EINVAL, "NULL context");
+    if (!c->state) return fail(c, GPWENO_ESTATE, "no state bound");
+    if (cell < 0 || (long long)cell >= c->ncell) return fail(c, GPWENO_EINVAL, "cell %ld out of range", cell);
+    c->shadow_ok = false;
+    hipError_t e = gpw::launch_poison(c->state, c->nv, c->ncell, (long long)cell, user_stream(c));
+    if (e != hipSuccess) return fail(c, GPWENO_EHIP, "poison launch: %s", hipGetErrorString(e));
     return GPWENO_OK;
 }
 
@@ -613,20 +769,22 @@ struct BatchGroup {
 // problem runs the same kernels in a batch as alone, so its result is bitwise
 // the same.
 bool same_kernels(const gpweno_ctx* a, const gpweno_ctx* b) {
-    if (indicator_kind(a) != indicator_kind(b)) return false;
+    if (indicator_kind(a) != indicator_kind(b) || corr_terms(a) != corr_terms(b)) return false;
     for (int d = 0; d < a->grid.ndim; ++d)
         if (general_bc(a->grid, d) != general_bc(b->grid, d)) return false;
     return true;
 }
 
+// Same tables along every axis (each batched launch covers one direction and
+// takes that direction's tables, so a problem with non-square cells batches
+// with the problems whose per-axis tables equal its own).
 bool same_tables(const gpweno_ctx* a, const gpweno_ctx* b) {
     if (a->scheme != b->scheme) return false;
-    for (int d = 0; d < a->grid.ndim; ++d)
+    for (int d = 0; d < a->grid.ndim; ++d) {
         if (std::memcmp(&a->tab64[d], &b->tab64[d], sizeof(GpTablesF64)) != 0) return false;
-    // the batched kernel takes one table set per launch; problems whose axes
-    // carry different tables (non-square cells) form their own groups
-    for (int d = 1; d < a->grid.ndim; ++d)
-        if (std::memcmp(&a->tab64[d], &a->tab64[0], sizeof(GpTablesF64)) != 0) return false;
+        if (a->scheme == GPWENO_GP_AO && std::memcmp(&a->ao64[d], &b->ao64[d], sizeof(GpAoTablesF64)) != 0)
+            return false;
+    }
     return true;
 }
 
@@ -679,6 +837,7 @@ void batch_drop_graph(gpweno_batch* b) {
 int batch_launch(gpweno_batch* b, const BatchGroup& g, int k, hipStream_t s) {
     const int stage = k / g.ndim + 1, j = k % g.ndim, dir = sweep_dir(g.ndim, j);
     const bool fin = j == g.ndim - 1;
+    const gpw::LaunchSel sel{dir, g.R, fin, indicator_kind(g.proto), g.bcg[dir], corr_terms(g.proto), true};
     hipError_t e;
     if (g.fp32) {
         gpw::BatchArgs<float> a;
@@ -688,9 +847,8 @@ int batch_launch(gpweno_batch* b, const BatchGroup& g, int k, hipStream_t s) {
         a.first = j == 0;
         a.stage = stage;
         a.step_start = k == 0;
-        a.tab = g.proto->tabf[0];
-        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, true, fin, indicator_kind(g.proto), g.bcg[dir], &a,
-                                    g.blocks[dir], s);
+        a.tab = g.proto->tabf[dir];
+        e = gpw::launch_sweep(g.ndim, true, sel, &a, g.blocks[dir], s);
     } else {
         gpw::BatchArgs<double> a;
         std::memset(&a, 0, sizeof a);
@@ -699,9 +857,8 @@ int batch_launch(gpweno_batch* b, const BatchGroup& g, int k, hipStream_t s) {
         a.first = j == 0;
         a.stage = stage;
         a.step_start = k == 0;
-        a.tab = g.proto->tabd[0];
-        e = gpw::launch_sweep_batch(g.ndim, dir, g.R, false, fin, indicator_kind(g.proto), g.bcg[dir], &a,
-                                    g.blocks[dir], s);
+        a.tab = g.proto->tabd[dir];
+        e = gpw::launch_sweep(g.ndim, false, sel, &a, g.blocks[dir], s);
     }
     if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "batched sweep launch: %s", hipGetErrorString(e));
     return GPWENO_OK;
@@ -729,6 +886,7 @@ int gpweno_set_end(gpweno_ctx* c, double t_final, long step_limit) {
     hipError_t e = gpw::launch_set_run(c->d_ctl, t_final, step_limit < 0 ? LLONG_MAX : (long long)step_limit,
                                        user_stream(c));
     if (e != hipSuccess) return fail(c, GPWENO_EHIP, "set_run launch: %s", hipGetErrorString(e));
+    c->shadow_ok = false;   // batched runs advance the state without this context
     return GPWENO_OK;
 }
 
@@ -786,12 +944,6 @@ int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stre
         }
         g->members.push_back(i);
     }
-    // per-axis tables must agree inside a problem for the batched kernel
-    for (const auto& g : b->groups)
-        for (int m : g.members)
-            if (!same_tables(b->set[m], b->set[m]))
-                return bfail(b, GPWENO_EINVAL, "context %d has different GP tables per axis (non-square "
-                                              "cells); batched execution needs equal tables", m);
     // descriptors and block owners
     std::vector<gpw::ProbDesc> desc;
     std::vector<unsigned short> owner;
@@ -803,7 +955,7 @@ int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stre
             for (size_t j = 0; j < g.members.size(); ++j) {
                 const gpweno_ctx* c = b->set[g.members[j]];
                 int nn[3] = {c->grid.n[0], c->grid.n[1], c->grid.n[2]};
-                const int nseg = (nn[dir] + TOUT - 1) / TOUT;
+                const int nseg = (nn[dir] + run_cells(c) - 1) / run_cells(c);
                 nblk[j] = gpw::sweep_blocks(g.ndim, dir, g.fp32, nn, nseg);
                 b0[j] = total;
                 total += nblk[j];
@@ -825,7 +977,7 @@ int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stre
                     P.Uout = outs[stage - 1];
                     P.ctl = c->d_ctl;
                     for (int d = 0; d < 3; ++d) P.n[d] = c->grid.n[d];
-                    P.nseg = (c->grid.n[dir] + TOUT - 1) / TOUT;
+                    P.nseg = (c->grid.n[dir] + run_cells(c) - 1) / run_cells(c);
                     P.ncell = c->ncell;
                     P.inv_dx = 1.0 / c->dx[dir];
                     for (int d = 0; d < 3; ++d) P.inv_dx_all[d] = d < c->grid.ndim ? 1.0 / c->dx[d] : 0.0;

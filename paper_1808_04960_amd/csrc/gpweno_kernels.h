@@ -6,6 +6,16 @@
 
 namespace gpw {
 
+constexpr int WAVE = 64;
+
+// A sweep maps a run of 64 consecutive cells of a pencil onto the lanes of a
+// wave. With NC terms of the flux correction (face fluxes NC faces either side
+// of a face, plus one face for the difference), lanes run_left(NC) ..
+// run_left(NC) + run_out(NC) - 1 produce output: 58 cells per run for NC = 2,
+// 56 for NC = 3.
+__host__ __device__ constexpr int run_left(int nc) { return nc + 1; }
+__host__ __device__ constexpr int run_out(int nc) { return WAVE - 2 * (nc + 1); }
+
 // Control block in device memory. Every sweep of a step derives the step's dt
 // and its go/no-go decision from it, so a captured sequence of steps needs no
 // host involvement and no separate time-step kernel, and closing a step needs
@@ -44,6 +54,8 @@ struct Ctl {
     double cfl;             // CFL number
     double fixed_dt;        // > 0: fixed time step
     long long step_limit;   // a step starts only while nsteps < step_limit
+    long long run_start;    // step count when the current run was set up
+    double run_t0;          // time when the current run was set up
     int err;                // 1: a stage produced rho <= 0, p <= 0 or NaN
     int pad;
     long long bad_cell;     // smallest cell index of such a failure
@@ -144,24 +156,39 @@ struct BatchStatus {
     int pad;
 };
 
-// Launchers (defined in gpweno_kernels.hip). fin: the sweep finishes an RK
-// stage (last direction of stages 1..3); otherwise it accumulates into dU.
-// ik: smoothness-indicator kind. 0: GP, Tab::P[0] serves every sub-stencil;
-// 1: a factor per sub-stencil (Jiang-Shu, R = 1, 2); 2: GP on the data minus the
-// centre cell's value (non-zero mean); 3: adaptive-order GP (R = 2, 3).
-// bcg: the sweep axis has a non-periodic side (the kernel reads bc[]); the
-// periodic-only kernels skip that logic and its registers.
-hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, int ik, bool bcg, const void* args,
-                        hipStream_t s);
+// Which sweep kernel to launch: direction, stencil radius, whether it finishes
+// an RK stage (last direction of stages 1..3; otherwise it accumulates into
+// dU), the smoothness-indicator kind (0: GP, Tab::P[0] serves every
+// sub-stencil; 1: a factor per sub-stencil, Jiang-Shu, R = 1, 2; 2: GP on the
+// data minus the centre cell's value, non-zero mean; 3: adaptive-order GP,
+// R = 2, 3), whether the sweep axis has a non-periodic side (the kernel reads
+// bc[]; the periodic-only kernels skip that logic and its registers), the
+// number of flux-correction terms (2, or 3 for indicator kind 0), and whether
+// it is the batched kernel (args is a BatchArgs, blocks its grid) or the
+// single-problem one (args is a SweepArgs, the grid follows from it).
+struct LaunchSel {
+    int dir;
+    int R;
+    bool fin;
+    int ik;
+    bool bcg;
+    int nc;
+    bool batch;
+};
+
+// Launchers (defined in gpweno_kernels.hip).
+hipError_t launch_sweep(int ndim, bool fp32, const LaunchSel& k, const void* args, long long blocks, hipStream_t s);
 hipError_t launch_set_run(Ctl* ctl, double t_final, long long step_limit, hipStream_t s);
+// Sets up a run of at most max_steps more steps (max_steps < 0: no limit) from
+// the current step count, read on the device, so the host need not wait for it.
+hipError_t launch_set_run_rel(Ctl* ctl, double t_final, long long max_steps, hipStream_t s);
 long long sweep_blocks(int ndim, int dir, bool fp32, const int n[3], int nseg);
-hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, int ik, bool bcg, const void* args, long long blocks,
-                              hipStream_t s);
 hipError_t launch_gather_status(Ctl* const* ctls, int nprob, BatchStatus* out, hipStream_t s);
 hipError_t launch_set_time(Ctl* ctl, double t, long long nsteps, double cfl, double fixed_dt, hipStream_t s);
-hipError_t launch_speed(int ndim, const double* U, long long ncell, const int n[3], const double inv_dx[3],
-                        double gamma, Ctl* ctl, hipStream_t s);
+hipError_t launch_speed(int ndim, const double* U, long long ncell, const double inv_dx[3], double gamma, Ctl* ctl,
+                        hipStream_t s);
 hipError_t launch_sums(int nv, const double* U, long long ncell, double* partials, int npart, Ctl* ctl,
                        hipStream_t s);
+hipError_t launch_poison(double* U, int nv, long long ncell, long long cell, hipStream_t s);
 
 }  // namespace gpw

@@ -5,24 +5,12 @@
 namespace gpw {
 
 // sweep instances, one translation unit per dimension and precision
-hipError_t launch_sweep_1d_f32(int dir, int R, bool fin, int ik, bool bcg, const void* args, hipStream_t s);
-hipError_t launch_sweep_batch_1d_f32(int dir, int R, bool fin, int ik, bool bcg, const void* args,
-                                      long long blocks, hipStream_t s);
-hipError_t launch_sweep_1d_f64(int dir, int R, bool fin, int ik, bool bcg, const void* args, hipStream_t s);
-hipError_t launch_sweep_batch_1d_f64(int dir, int R, bool fin, int ik, bool bcg, const void* args,
-                                      long long blocks, hipStream_t s);
-hipError_t launch_sweep_2d_f32(int dir, int R, bool fin, int ik, bool bcg, const void* args, hipStream_t s);
-hipError_t launch_sweep_batch_2d_f32(int dir, int R, bool fin, int ik, bool bcg, const void* args,
-                                      long long blocks, hipStream_t s);
-hipError_t launch_sweep_2d_f64(int dir, int R, bool fin, int ik, bool bcg, const void* args, hipStream_t s);
-hipError_t launch_sweep_batch_2d_f64(int dir, int R, bool fin, int ik, bool bcg, const void* args,
-                                      long long blocks, hipStream_t s);
-hipError_t launch_sweep_3d_f32(int dir, int R, bool fin, int ik, bool bcg, const void* args, hipStream_t s);
-hipError_t launch_sweep_batch_3d_f32(int dir, int R, bool fin, int ik, bool bcg, const void* args,
-                                      long long blocks, hipStream_t s);
-hipError_t launch_sweep_3d_f64(int dir, int R, bool fin, int ik, bool bcg, const void* args, hipStream_t s);
-hipError_t launch_sweep_batch_3d_f64(int dir, int R, bool fin, int ik, bool bcg, const void* args,
-                                      long long blocks, hipStream_t s);
+hipError_t launch_sweep_1d_f32(const LaunchSel& k, const void* args, long long blocks, hipStream_t s);
+hipError_t launch_sweep_1d_f64(const LaunchSel& k, const void* args, long long blocks, hipStream_t s);
+hipError_t launch_sweep_2d_f32(const LaunchSel& k, const void* args, long long blocks, hipStream_t s);
+hipError_t launch_sweep_2d_f64(const LaunchSel& k, const void* args, long long blocks, hipStream_t s);
+hipError_t launch_sweep_3d_f32(const LaunchSel& k, const void* args, long long blocks, hipStream_t s);
+hipError_t launch_sweep_3d_f64(const LaunchSel& k, const void* args, long long blocks, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Time-step control and reductions
@@ -32,6 +20,15 @@ __global__ void set_run_kernel(Ctl* c, double t_final, long long step_limit) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     c->t_final = t_final;
     c->step_limit = step_limit;
+}
+
+__global__ void set_run_rel_kernel(Ctl* c, double t_final, long long max_steps) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const StepRec& r = c->rec[0].nsteps > c->rec[1].nsteps ? c->rec[0] : c->rec[1];
+    c->t_final = t_final;
+    c->run_start = r.nsteps;
+    c->run_t0 = r.t;
+    c->step_limit = max_steps < 0 || max_steps > LLONG_MAX - r.nsteps ? LLONG_MAX : r.nsteps + max_steps;
 }
 
 __global__ void set_time_kernel(Ctl* c, double t, long long nsteps, double cfl, double fixed_dt) {
@@ -56,32 +53,29 @@ __global__ void set_time_kernel(Ctl* c, double t, long long nsteps, double cfl, 
 }
 
 // CFL speed max_i sum_d (|u_d| + c)/dx_d of a state, with the physical check.
+// Each cell's speed is formed by cell_speed, the function the finishing sweep
+// of stage 3 applies to the state it writes, so a state gets the same dt here
+// (after gpweno_bind / gpweno_set_time) as when a step produced it: a run
+// resumed from a saved state retraces the uninterrupted run bit for bit.
 template <int NDIM>
-__global__ void __launch_bounds__(256) speed_kernel(const double* __restrict__ U, long long ncell, int n0, int n1,
-                                                    double ix0, double ix1, double ix2, double gamma, Ctl* ctl) {
+__global__ void __launch_bounds__(256) speed_kernel(const double* __restrict__ U, long long ncell, double ix0,
+                                                    double ix1, double ix2, double gamma, Ctl* ctl) {
     constexpr int NV = 2 + NDIM;
     __shared__ unsigned long long sred[4];
     const double ix[3] = {ix0, ix1, ix2};
     unsigned long long smax = 0;
     for (long long cell = blockIdx.x * (long long)blockDim.x + threadIdx.x; cell < ncell;
          cell += (long long)gridDim.x * blockDim.x) {
-        const double rho = U[cell];
-        double ke = 0.0, s = 0.0, vel[3] = {0.0, 0.0, 0.0};
+        double o[NV];
 #pragma unroll
-        for (int d = 0; d < NDIM; ++d) {
-            const double m = U[(1 + d) * ncell + cell];
-            vel[d] = m / rho;
-            ke += vel[d] * m;
-        }
-        const double p = (gamma - 1.0) * (U[(NV - 1) * ncell + cell] - 0.5 * ke);
-        if (!(rho > 0.0) || !(p > 0.0)) {
+        for (int k = 0; k < NV; ++k) o[k] = U[k * ncell + cell];
+        bool ok;
+        const double s = cell_speed<NDIM>(o, gamma, ix, ok, true);
+        if (!ok) {
             atomicOr(&ctl->err, 1);
             atomicMin(&ctl->bad_cell, cell);
         }
-        const double c = sqrt(gamma * p / rho);
-#pragma unroll
-        for (int d = 0; d < NDIM; ++d) s += (fabs(vel[d]) + c) * ix[d];
-        const unsigned long long bits = (s != s) ? 0x7ff8000000000000ull : (unsigned long long)__double_as_longlong(s);
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(s);
         smax = bits > smax ? bits : smax;
     }
     smax = wave_max_u64(smax);
@@ -93,8 +87,13 @@ __global__ void __launch_bounds__(256) speed_kernel(const double* __restrict__ U
         const long long n = ctl->rec[0].nsteps > ctl->rec[1].nsteps ? ctl->rec[0].nsteps : ctl->rec[1].nsteps;
         atomicMax(&ctl->xcd[blockIdx.x & 7u].speed[n & 1], m);
     }
-    (void)n0;
-    (void)n1;
+}
+
+// Test hook: density and total energy of one cell set to -1.
+__global__ void poison_kernel(double* U, int nv, long long ncell, long long cell) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    U[cell] = -1.0;
+    U[(long long)(nv - 1) * ncell + cell] = -1.0;
 }
 
 // Deterministic float64 sums: fixed per-thread strides, fixed tree per block,
@@ -126,32 +125,14 @@ __global__ void sums_final_kernel(const double* __restrict__ partials, int npart
 }
 
 
-hipError_t launch_sweep(int ndim, int dir, int R, bool fp32, bool fin, int ik, bool bcg, const void* args,
-                        hipStream_t s) {
+hipError_t launch_sweep(int ndim, bool fp32, const LaunchSel& k, const void* args, long long blocks, hipStream_t s) {
     switch (ndim) {
-        case 1: return fp32 ? launch_sweep_1d_f32(dir, R, fin, ik, bcg, args, s) : launch_sweep_1d_f64(dir, R, fin, ik, bcg, args, s);
-        case 2: return fp32 ? launch_sweep_2d_f32(dir, R, fin, ik, bcg, args, s) : launch_sweep_2d_f64(dir, R, fin, ik, bcg, args, s);
-        case 3: return fp32 ? launch_sweep_3d_f32(dir, R, fin, ik, bcg, args, s) : launch_sweep_3d_f64(dir, R, fin, ik, bcg, args, s);
+        case 1: return fp32 ? launch_sweep_1d_f32(k, args, blocks, s) : launch_sweep_1d_f64(k, args, blocks, s);
+        case 2: return fp32 ? launch_sweep_2d_f32(k, args, blocks, s) : launch_sweep_2d_f64(k, args, blocks, s);
+        case 3: return fp32 ? launch_sweep_3d_f32(k, args, blocks, s) : launch_sweep_3d_f64(k, args, blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
-
-hipError_t launch_sweep_batch(int ndim, int dir, int R, bool fp32, bool fin, int ik, bool bcg, const void* args,
-                              long long blocks, hipStream_t s) {
-    switch (ndim) {
-        case 1:
-            return fp32 ? launch_sweep_batch_1d_f32(dir, R, fin, ik, bcg, args, blocks, s)
-                        : launch_sweep_batch_1d_f64(dir, R, fin, ik, bcg, args, blocks, s);
-        case 2:
-            return fp32 ? launch_sweep_batch_2d_f32(dir, R, fin, ik, bcg, args, blocks, s)
-                        : launch_sweep_batch_2d_f64(dir, R, fin, ik, bcg, args, blocks, s);
-        case 3:
-            return fp32 ? launch_sweep_batch_3d_f32(dir, R, fin, ik, bcg, args, blocks, s)
-                        : launch_sweep_batch_3d_f64(dir, R, fin, ik, bcg, args, blocks, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
 
 // ---- batched launches --------------------------------------------------------
 long long sweep_blocks(int ndim, int dir, bool fp32, const int n[3], int nseg) {
@@ -186,22 +167,32 @@ hipError_t launch_set_run(Ctl* ctl, double t_final, long long step_limit, hipStr
     return hipGetLastError();
 }
 
+hipError_t launch_set_run_rel(Ctl* ctl, double t_final, long long max_steps, hipStream_t s) {
+    hipLaunchKernelGGL(set_run_rel_kernel, dim3(1), dim3(64), 0, s, ctl, t_final, max_steps);
+    return hipGetLastError();
+}
+
 hipError_t launch_set_time(Ctl* ctl, double t, long long nsteps, double cfl, double fixed_dt, hipStream_t s) {
     hipLaunchKernelGGL(set_time_kernel, dim3(1), dim3(64), 0, s, ctl, t, nsteps, cfl, fixed_dt);
     return hipGetLastError();
 }
 
-hipError_t launch_speed(int ndim, const double* U, long long ncell, const int n[3], const double inv_dx[3],
-                        double gamma, Ctl* ctl, hipStream_t s) {
+hipError_t launch_speed(int ndim, const double* U, long long ncell, const double inv_dx[3], double gamma, Ctl* ctl,
+                        hipStream_t s) {
     long long blocks = (ncell + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     const dim3 g((unsigned)blocks), b(256);
     switch (ndim) {
-        case 1: hipLaunchKernelGGL(speed_kernel<1>, g, b, 0, s, U, ncell, n[0], n[1], inv_dx[0], inv_dx[1], inv_dx[2], gamma, ctl); break;
-        case 2: hipLaunchKernelGGL(speed_kernel<2>, g, b, 0, s, U, ncell, n[0], n[1], inv_dx[0], inv_dx[1], inv_dx[2], gamma, ctl); break;
-        case 3: hipLaunchKernelGGL(speed_kernel<3>, g, b, 0, s, U, ncell, n[0], n[1], inv_dx[0], inv_dx[1], inv_dx[2], gamma, ctl); break;
+        case 1: hipLaunchKernelGGL(speed_kernel<1>, g, b, 0, s, U, ncell, inv_dx[0], inv_dx[1], inv_dx[2], gamma, ctl); break;
+        case 2: hipLaunchKernelGGL(speed_kernel<2>, g, b, 0, s, U, ncell, inv_dx[0], inv_dx[1], inv_dx[2], gamma, ctl); break;
+        case 3: hipLaunchKernelGGL(speed_kernel<3>, g, b, 0, s, U, ncell, inv_dx[0], inv_dx[1], inv_dx[2], gamma, ctl); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_poison(double* U, int nv, long long ncell, long long cell, hipStream_t s) {
+    hipLaunchKernelGGL(poison_kernel, dim3(1), dim3(64), 0, s, U, nv, ncell, cell);
     return hipGetLastError();
 }
 

@@ -9,9 +9,10 @@
 //     states of its cell (stencil of 2R+1 cells read from LDS), the wave then
 //     forms face fluxes, corrected fluxes and flux differences exchanging
 //     neighbouring lanes' values with DPP wave shifts. The flux correction
-//     needs face fluxes two faces either side and the difference one more
-//     face, so lanes 3..60 produce output: a run yields 58 cells, and
-//     consecutive runs overlap by 6 cells.
+//     needs face fluxes NC faces either side (NC = 2: alpha and beta; 3: also
+//     the sixth difference) and the difference one more face, so lanes
+//     NC+1 .. 62-NC produce output: a run yields 58 cells (56 with NC = 3),
+//     and consecutive runs overlap by 6 (8) cells.
 //   * A block holds several pencils (one wave each) and the same run segment.
 //     The input tile [2+ndim fields][pencils][64 + 2R cells] is loaded once
 //     from HBM (ghost positions: periodic image, outflow copy or mirror image),
@@ -42,9 +43,6 @@
 
 namespace gpw {
 
-constexpr int WAVE = 64;
-constexpr int LEFT = 3;             // first output lane of a run
-constexpr int TOUT = WAVE - 6;      // outputs per run
 
 // Pencils (waves) per block: 4 rows in x sweeps, 4 adjacent x columns in y/z
 // sweeps. Four-wave blocks fill the register-limited wave slots of a compute
@@ -98,7 +96,7 @@ template <> inline __device__ __forceinline__ double frsq<double>(double x) {
 // Value of the neighbouring lane across the whole wave, by DPP wave shifts
 // (wave_shr:1 / wave_shl:1): lane_prev gives lane l the value of lane l-1,
 // lane_next the value of lane l+1; the lane without a neighbour gets 0 (its
-// result is never used: a run's outputs come from lanes 3..60). One VALU move,
+// result is never used: a run's outputs come from lanes NC+1 .. 62-NC). One VALU move,
 // which the compiler can fold into the consuming instruction, instead of a
 // permute through the LDS crossbar.
 inline __device__ __forceinline__ float lane_prev(float x) {
@@ -622,9 +620,11 @@ __device__ __forceinline__ void hllc(const Real (&qL)[2 + NDIM], const Real (&qR
     for (int k = 0; k < NV; ++k) F[k] = sup ? FK[k] : fma(S, Us[k] - UK[k], FK[k]);
 }
 
-template <int NDIM, int DIR, int R, typename Real>
+template <int NDIM, int DIR, int R, typename Real, int NC>
 struct SweepCfg {
     static constexpr int NV = 2 + NDIM;
+    static constexpr int LEFT = run_left(NC);  // first output lane of a run
+    static constexpr int TOUT = run_out(NC);   // outputs per run
     static constexpr int SLEN = WAVE + 2 * R;
     static constexpr int PITCH = SLEN | 1;
     static constexpr int WPB = sweep_wpb(NDIM, DIR, sizeof(Real) == 4);  // pencils (waves) per block
@@ -682,6 +682,34 @@ __device__ __forceinline__ void put(double* p, double v) {
     else *p = v;
 }
 
+// Physical check and CFL speed sum_d (|u_d| + c)/dx_d of one cell's conserved
+// values o (ix: 1/dx per axis). ok: rho > 0 and p > 0 (false for NaN). The sound
+// speed comes from the reciprocal square root (to an ulp or two); a cell whose
+// speed is NaN reads as infinitely fast. The finishing sweep of stage 3 and the
+// CFL-speed kernel both call this, so they give a state the same speed.
+template <int NDIM>
+__device__ __forceinline__ double cell_speed(const double (&o)[2 + NDIM], double gamma, const double* ix, bool& ok,
+                                             bool want_speed) {
+    constexpr int NV = 2 + NDIM;
+    const double rho = o[0];
+    const double irho = frcp(rho);
+    double ke = 0.0, vel[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int dd = 0; dd < NDIM; ++dd) {
+        vel[dd] = o[1 + dd] * irho;
+        ke += vel[dd] * o[1 + dd];
+    }
+    const double p = (gamma - 1.0) * (o[NV - 1] - 0.5 * ke);
+    ok = rho > 0.0 && p > 0.0;
+    if (!want_speed) return 0.0;
+    const double c2 = gamma * p * irho;
+    const double c = c2 * frsq(c2);
+    double s = 0.0;
+#pragma unroll
+    for (int dd = 0; dd < NDIM; ++dd) s += (fabs(vel[dd]) + c) * ix[dd];
+    return (s != s) ? (double)INFINITY : s;
+}
+
 // Finish one cell. FIN = false: accumulate the direction's contribution into
 // dU. FIN = true (last direction of an RK stage): form the stage output
 // (SSP-RK3, Shu-Osher form), check it is physical and, in stage 3, track the
@@ -709,29 +737,13 @@ __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long 
         put<NT>(&a.Uout[k * nc + cell], out);
         o[k] = out;
     }
-    const double rho = o[0];
-    const double irho = frcp(rho);
-    double ke = 0.0, vel[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int dd = 0; dd < NDIM; ++dd) {
-        vel[dd] = o[1 + dd] * irho;
-        ke += vel[dd] * o[1 + dd];
-    }
-    const double p = (a.gamma - 1.0) * (o[NV - 1] - 0.5 * ke);
-    if (!(rho > 0.0) || !(p > 0.0)) {
+    bool ok;
+    const double s = cell_speed<NDIM>(o, a.gamma, a.inv_dx_all, ok, a.stage == 3);
+    if (!ok) {
         atomicOr(&a.ctl->err, 1);
         atomicMin(&a.ctl->bad_cell, cell);
     }
-    if (a.stage == 3) {
-        // sound speed from the reciprocal square root (to an ulp or two); a
-        // non-physical cell (flagged above) reads as an infinite speed
-        const double c2 = a.gamma * p * irho;
-        const double c = c2 * frsq(c2);
-        double s = 0.0;
-#pragma unroll
-        for (int dd = 0; dd < NDIM; ++dd) s += (fabs(vel[dd]) + c) * a.inv_dx_all[dd];
-        spd = (s != s) ? (double)INFINITY : s;
-    }
+    if (a.stage == 3) spd = s;
 }
 
 // XCD-aware block order. Workgroups are dealt to the 8 XCDs round-robin by
@@ -747,11 +759,12 @@ inline __device__ __forceinline__ long long xcd_logical_block() {
 }
 
 // One block of a sweep: logical block L of the problem's blocks.
-template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG, int NC>
 __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long long L, unsigned char* smem,
                                             unsigned long long* sred) {
-    using C = SweepCfg<NDIM, DIR, R, Real>;
+    using C = SweepCfg<NDIM, DIR, R, Real, NC>;
     constexpr int NV = C::NV, WPB = C::WPB, PITCH = C::PITCH, SLEN = C::SLEN, THREADS = C::THREADS;
+    constexpr int LEFT = C::LEFT, TOUT = C::TOUT;
     // float64 sweeps request their epilogue operands (and, in x sweeps, their
     // own cell's conserved values) after the reconstruction rather than before
     // it: held through it, those registers cost the float64 finishing sweep an
@@ -943,11 +956,15 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
 #pragma unroll
         for (int k = 0; k < NV; ++k) qR[k] = lane_next(qm[k]);
         hllc<NDIM, Real>(qp, qR, g, inv_gm1, F);
-        // f^ = F + alpha (F_{-1} - 2F + F_{+1}) + beta (F_{-2} - 4F_{-1} + 6F - 4F_{+1} + F_{+2}),
-        // alpha = -1/24, beta = 3/640, gathered by neighbour distance
-        const Real c0 = Real(1.0 + 2.0 / 24.0 + 18.0 / 640.0);  // 1 - 2 alpha + 6 beta
-        const Real c1 = Real(-1.0 / 24.0 - 12.0 / 640.0);       // alpha - 4 beta
-        const Real c2 = Real(3.0 / 640.0);                      // beta
+        // f^ = F + alpha (F_{-1} - 2F + F_{+1}) + beta (F_{-2} - 4F_{-1} + 6F - 4F_{+1} + F_{+2})
+        //       [+ g (F_{-3} - 6F_{-2} + 15F_{-1} - 20F + 15F_{+1} - 6F_{+2} + F_{+3})],
+        // alpha = -1/24, beta = 3/640, g = -5/7168 (NC = 3 only), gathered by
+        // neighbour distance
+        constexpr double AL = -1.0 / 24.0, BE = 3.0 / 640.0, G6 = NC == 3 ? -5.0 / 7168.0 : 0.0;
+        const Real c0 = Real(1.0 - 2.0 * AL + 6.0 * BE - 20.0 * G6);
+        const Real c1 = Real(AL - 4.0 * BE + 15.0 * G6);
+        const Real c2 = Real(BE - 6.0 * G6);
+        const Real c3 = Real(G6);
         // This lane's face is x_{i+1/2} of cell i. At a reflecting wall the mirror
         // ghosts make the fluxes of mass, tangential momentum and energy vanish
         // (and the correction terms with them, by antisymmetry) up to rounding;
@@ -959,7 +976,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
         for (int k = 0; k < NV; ++k) {
             const Real fm1 = lane_prev(F[k]), fm2 = lane_prev(fm1);
             const Real fp1 = lane_next(F[k]), fp2 = lane_next(fp1);
-            const Real fh = (wall && k != 1) ? Real(0) : fma(c0, F[k], fma(c1, fm1 + fp1, c2 * (fm2 + fp2)));
+            Real far = c2 * (fm2 + fp2);
+            if constexpr (NC == 3) far = fma(c3, lane_prev(fm2) + lane_next(fp2), far);
+            const Real fh = (wall && k != 1) ? Real(0) : fma(c0, F[k], fma(c1, fm1 + fp1, far));
             const Real fhm = lane_prev(fh);
             dcons[cons_slot<NDIM, DIR>(k)] = -((double)fh - (double)fhm) * a.inv_dx;
         }
@@ -1008,13 +1027,13 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     }
 }
 
-template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
-__global__ void __launch_bounds__((SweepCfg<NDIM, DIR, R, Real>::THREADS))
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG, int NC>
+__global__ void __launch_bounds__((SweepCfg<NDIM, DIR, R, Real, NC>::THREADS))
 sweep_kernel(const SweepArgs<Real> a) {
-    using C = SweepCfg<NDIM, DIR, R, Real>;
+    using C = SweepCfg<NDIM, DIR, R, Real, NC>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
     __shared__ unsigned long long sred[C::WPB];
-    sweep_block<NDIM, DIR, R, Real, FIN, IK, BCG>(a, xcd_logical_block(), smem, sred);
+    sweep_block<NDIM, DIR, R, Real, FIN, IK, BCG, NC>(a, xcd_logical_block(), smem, sred);
 }
 
 // Batched sweep over many independent problems (same ndim, R, precision and
@@ -1022,10 +1041,10 @@ sweep_kernel(const SweepArgs<Real> a) {
 // the problem of logical block L. Every block runs exactly the code of the
 // single-problem sweep on its own problem's data, so a problem's result does
 // not depend on what else is in the batch.
-template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
-__global__ void __launch_bounds__((SweepCfg<NDIM, DIR, R, Real>::THREADS))
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG, int NC>
+__global__ void __launch_bounds__((SweepCfg<NDIM, DIR, R, Real, NC>::THREADS))
 sweep_batch_kernel(const BatchArgs<Real> ba) {
-    using C = SweepCfg<NDIM, DIR, R, Real>;
+    using C = SweepCfg<NDIM, DIR, R, Real, NC>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
     __shared__ unsigned long long sred[C::WPB];
     const long long Lg = xcd_logical_block();
@@ -1055,15 +1074,24 @@ sweep_batch_kernel(const BatchArgs<Real> ba) {
     a.stage = ba.stage;
     a.step_start = ba.step_start;
     a.tab = ba.tab;
-    sweep_block<NDIM, DIR, R, Real, FIN, IK, BCG>(a, Lg - P.block0, smem, sred);
+    sweep_block<NDIM, DIR, R, Real, FIN, IK, BCG, NC>(a, Lg - P.block0, smem, sred);
 }
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
-hipError_t launch_one(const void* args, hipStream_t s) {
-    using C = SweepCfg<NDIM, DIR, R, Real>;
+// A launch of kernel K: the single-problem sweep (grid from the problem's
+// geometry) or the batched sweep (grid given by the caller).
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG, int NC>
+hipError_t launch_one(const void* args, long long blocks, bool batch, hipStream_t s) {
+    using C = SweepCfg<NDIM, DIR, R, Real, NC>;
+    if (batch) {
+        const BatchArgs<Real>& a = *static_cast<const BatchArgs<Real>*>(args);
+        if (blocks <= 0 || blocks > INT_MAX) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((sweep_batch_kernel<NDIM, DIR, R, Real, FIN, IK, BCG, NC>), dim3((unsigned)blocks),
+                           dim3(C::THREADS), 0, s, a);
+        return hipGetLastError();
+    }
     const SweepArgs<Real>& a = *static_cast<const SweepArgs<Real>*>(args);
     long long groups;
     if (DIR == 0) {
@@ -1072,114 +1100,65 @@ hipError_t launch_one(const void* args, hipStream_t s) {
         const long long nxb = (a.n[0] + C::WPB - 1) / C::WPB;
         groups = nxb * (DIR == 1 ? a.n[2] : a.n[1]);
     }
-    const long long blocks = groups * a.nseg;
+    blocks = groups * a.nseg;
     if (blocks <= 0 || blocks > INT_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sweep_kernel<NDIM, DIR, R, Real, FIN, IK, BCG>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s, a);
+    hipLaunchKernelGGL((sweep_kernel<NDIM, DIR, R, Real, FIN, IK, BCG, NC>), dim3((unsigned)blocks), dim3(C::THREADS),
+                       0, s, a);
     return hipGetLastError();
 }
 
 // A finishing kernel exists only for x, the last direction of a stage.
-template <int NDIM, int R, typename Real, int IK, bool BCG>
-hipError_t launch_dir(int dir, bool fin, const void* args, hipStream_t s) {
-    if (fin) {
-        if (dir != 0) return hipErrorInvalidValue;
-        return launch_one<NDIM, 0, R, Real, true, IK, BCG>(args, s);
+template <int NDIM, int R, typename Real, int IK, bool BCG, int NC>
+hipError_t launch_dir(const LaunchSel& k, const void* args, long long blocks, hipStream_t s) {
+    if (k.fin) {
+        if (k.dir != 0) return hipErrorInvalidValue;
+        return launch_one<NDIM, 0, R, Real, true, IK, BCG, NC>(args, blocks, k.batch, s);
     }
-    if (dir == 0) return launch_one<NDIM, 0, R, Real, false, IK, BCG>(args, s);
-    if (NDIM >= 2 && dir == 1) return launch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false, IK, BCG>(args, s);
-    if (NDIM == 3 && dir == 2) return launch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false, IK, BCG>(args, s);
+    if (k.dir == 0) return launch_one<NDIM, 0, R, Real, false, IK, BCG, NC>(args, blocks, k.batch, s);
+    if (NDIM >= 2 && k.dir == 1)
+        return launch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false, IK, BCG, NC>(args, blocks, k.batch, s);
+    if (NDIM == 3 && k.dir == 2)
+        return launch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false, IK, BCG, NC>(args, blocks, k.batch, s);
     return hipErrorInvalidValue;
 }
 
-template <int NDIM, int R, typename Real, int IK>
-hipError_t launch_bcg(int dir, bool fin, bool bcg, const void* args, hipStream_t s) {
-    return bcg ? launch_dir<NDIM, R, Real, IK, true>(dir, fin, args, s)
-               : launch_dir<NDIM, R, Real, IK, false>(dir, fin, args, s);
+template <int NDIM, int R, typename Real, int IK, int NC>
+hipError_t launch_bcg(const LaunchSel& k, const void* args, long long blocks, hipStream_t s) {
+    return k.bcg ? launch_dir<NDIM, R, Real, IK, true, NC>(k, args, blocks, s)
+                 : launch_dir<NDIM, R, Real, IK, false, NC>(k, args, blocks, s);
 }
 
 // Indicator kinds: 0 for R = 1..3, 1 (Jiang-Shu) for R = 1, 2, 2 for R = 1..3,
-// 3 (adaptive order) for R = 2, 3.
-template <int NDIM, typename Real, int IK>
-hipError_t launch_rk(int dir, int R, bool fin, bool bcg, const void* args, hipStream_t s) {
-    switch (R) {
+// 3 (adaptive order) for R = 2, 3. The three-term flux correction exists for
+// indicator kind 0 only.
+template <int NDIM, typename Real, int IK, int NC>
+hipError_t launch_rk(const LaunchSel& k, const void* args, long long blocks, hipStream_t s) {
+    switch (k.R) {
         case 1:
-            if constexpr (IK != 3) return launch_bcg<NDIM, 1, Real, IK>(dir, fin, bcg, args, s);
+            if constexpr (IK != 3) return launch_bcg<NDIM, 1, Real, IK, NC>(k, args, blocks, s);
             return hipErrorInvalidValue;
-        case 2: return launch_bcg<NDIM, 2, Real, IK>(dir, fin, bcg, args, s);
+        case 2: return launch_bcg<NDIM, 2, Real, IK, NC>(k, args, blocks, s);
         case 3:
-            if constexpr (IK != 1) return launch_bcg<NDIM, 3, Real, IK>(dir, fin, bcg, args, s);
+            if constexpr (IK != 1) return launch_bcg<NDIM, 3, Real, IK, NC>(k, args, blocks, s);
             return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
 
 template <int NDIM, typename Real>
-hipError_t launch_r(int dir, int R, bool fin, int ik, bool bcg, const void* args, hipStream_t s) {
-    switch (ik) {
-        case 0: return launch_rk<NDIM, Real, 0>(dir, R, fin, bcg, args, s);
-        case 1: return launch_rk<NDIM, Real, 1>(dir, R, fin, bcg, args, s);
-        case 2: return launch_rk<NDIM, Real, 2>(dir, R, fin, bcg, args, s);
-        case 3: return launch_rk<NDIM, Real, 3>(dir, R, fin, bcg, args, s);
+hipError_t launch_r(const LaunchSel& k, const void* args, long long blocks, hipStream_t s) {
+    if (k.nc == 3) {
+        if (k.ik != 0) return hipErrorInvalidValue;
+        return launch_rk<NDIM, Real, 0, 3>(k, args, blocks, s);
+    }
+    if (k.nc != 2) return hipErrorInvalidValue;
+    switch (k.ik) {
+        case 0: return launch_rk<NDIM, Real, 0, 2>(k, args, blocks, s);
+        case 1: return launch_rk<NDIM, Real, 1, 2>(k, args, blocks, s);
+        case 2: return launch_rk<NDIM, Real, 2, 2>(k, args, blocks, s);
+        case 3: return launch_rk<NDIM, Real, 3, 2>(k, args, blocks, s);
         default: return hipErrorInvalidValue;
     }
 }
-
-
-template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG>
-hipError_t launch_batch_one(const void* args, long long blocks, hipStream_t s) {
-    using C = SweepCfg<NDIM, DIR, R, Real>;
-    const BatchArgs<Real>& a = *static_cast<const BatchArgs<Real>*>(args);
-    if (blocks <= 0 || blocks > INT_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sweep_batch_kernel<NDIM, DIR, R, Real, FIN, IK, BCG>), dim3((unsigned)blocks), dim3(C::THREADS), 0, s,
-                       a);
-    return hipGetLastError();
-}
-
-template <int NDIM, int R, typename Real, int IK, bool BCG>
-hipError_t launch_batch_dir(int dir, bool fin, const void* args, long long blocks, hipStream_t s) {
-    if (fin) {
-        if (dir != 0) return hipErrorInvalidValue;
-        return launch_batch_one<NDIM, 0, R, Real, true, IK, BCG>(args, blocks, s);
-    }
-    if (dir == 0) return launch_batch_one<NDIM, 0, R, Real, false, IK, BCG>(args, blocks, s);
-    if (NDIM >= 2 && dir == 1)
-        return launch_batch_one<NDIM, (NDIM >= 2 ? 1 : 0), R, Real, false, IK, BCG>(args, blocks, s);
-    if (NDIM == 3 && dir == 2)
-        return launch_batch_one<NDIM, (NDIM == 3 ? 2 : 0), R, Real, false, IK, BCG>(args, blocks, s);
-    return hipErrorInvalidValue;
-}
-
-template <int NDIM, int R, typename Real, int IK>
-hipError_t launch_batch_bcg(int dir, bool fin, bool bcg, const void* args, long long blocks, hipStream_t s) {
-    return bcg ? launch_batch_dir<NDIM, R, Real, IK, true>(dir, fin, args, blocks, s)
-               : launch_batch_dir<NDIM, R, Real, IK, false>(dir, fin, args, blocks, s);
-}
-
-template <int NDIM, typename Real, int IK>
-hipError_t launch_batch_rk(int dir, int R, bool fin, bool bcg, const void* args, long long blocks, hipStream_t s) {
-    switch (R) {
-        case 1:
-            if constexpr (IK != 3) return launch_batch_bcg<NDIM, 1, Real, IK>(dir, fin, bcg, args, blocks, s);
-            return hipErrorInvalidValue;
-        case 2: return launch_batch_bcg<NDIM, 2, Real, IK>(dir, fin, bcg, args, blocks, s);
-        case 3:
-            if constexpr (IK != 1) return launch_batch_bcg<NDIM, 3, Real, IK>(dir, fin, bcg, args, blocks, s);
-            return hipErrorInvalidValue;
-        default: return hipErrorInvalidValue;
-    }
-}
-
-template <int NDIM, typename Real>
-hipError_t launch_batch_r(int dir, int R, bool fin, int ik, bool bcg, const void* args, long long blocks,
-                          hipStream_t s) {
-    switch (ik) {
-        case 0: return launch_batch_rk<NDIM, Real, 0>(dir, R, fin, bcg, args, blocks, s);
-        case 1: return launch_batch_rk<NDIM, Real, 1>(dir, R, fin, bcg, args, blocks, s);
-        case 2: return launch_batch_rk<NDIM, Real, 2>(dir, R, fin, bcg, args, blocks, s);
-        case 3: return launch_batch_rk<NDIM, Real, 3>(dir, R, fin, bcg, args, blocks, s);
-        default: return hipErrorInvalidValue;
-    }
-}
-
 
 }  // namespace gpw

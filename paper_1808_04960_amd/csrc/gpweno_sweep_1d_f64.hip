@@ -4,13 +4,8 @@
 
 namespace gpw {
 
-hipError_t launch_sweep_1d_f64(int dir, int R, bool fin, int ik, bool bcg, const void* args, hipStream_t s) {
-    return launch_r<1, double>(dir, R, fin, ik, bcg, args, s);
-}
-
-hipError_t launch_sweep_batch_1d_f64(int dir, int R, bool fin, int ik, bool bcg, const void* args,
-                                        long long blocks, hipStream_t s) {
-    return launch_batch_r<1, double>(dir, R, fin, ik, bcg, args, blocks, s);
+hipError_t launch_sweep_1d_f64(const LaunchSel& k, const void* args, long long blocks, hipStream_t s) {
+    return launch_r<1, double>(k, args, blocks, s);
 }
 
 }  // namespace gpw

@@ -4,13 +4,8 @@
 
 namespace gpw {
 
-hipError_t launch_sweep_2d_f32(int dir, int R, bool fin, int ik, bool bcg, const void* args, hipStream_t s) {
-    return launch_r<2, float>(dir, R, fin, ik, bcg, args, s);
-}
-
-hipError_t launch_sweep_batch_2d_f32(int dir, int R, bool fin, int ik, bool bcg, const void* args,
-                                        long long blocks, hipStream_t s) {
-    return launch_batch_r<2, float>(dir, R, fin, ik, bcg, args, blocks, s);
+hipError_t launch_sweep_2d_f32(const LaunchSel& k, const void* args, long long blocks, hipStream_t s) {
+    return launch_r<2, float>(k, args, blocks, s);
 }
 
 }  // namespace gpw

@@ -109,8 +109,12 @@ def test_init_scheme_validates(L):
 
 
 def test_null_context_is_rejected(L):
-    assert L.gpweno_step(None, 1.0) == gw.EINVAL
+    assert L.gpweno_step(None, 1.0, None) == gw.EINVAL
     assert L.gpweno_run(None, 1.0, -1, None, None) == gw.EINVAL
+    assert L.gpweno_get_tables(None, 0, None, None, None) == gw.EINVAL
+    assert L.gpweno_table_residual(None, None) == gw.EINVAL
+    assert L.gpweno_debug_poison(None, 0) == gw.EINVAL
+    assert L.gpweno_get_failure(None, None, None) == gw.EINVAL
     assert L.gpweno_state_count(None) == 0
     assert L.gpweno_workspace_bytes(None) == 0
     L.gpweno_destroy(None)
@@ -176,3 +180,35 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
         gw.lib()
     with pytest.raises(gw.GpwenoError, match="is not built"):
         gw.compute_tables(2, 12.0, 3.0)
+
+
+@pytest.mark.parametrize("ell", [12.0, 40.0, 60.0, 80.0, 120.0])
+def test_table_residual_bounds_the_table_error(ell):
+    """The mirror residual (the two binary128 solves at x_* = +-1/2, which agree in
+    exact arithmetic) measures how accurate the R = 3 tables are as K of Eq.
+    (kmat) loses conditioning with ell/dx: against the 60-digit oracle tables,
+    the linear weights are off by at most 10x the residual plus float64
+    rounding, and the sub-stencil weights (a 4x4 solve) stay correctly rounded.
+    At 80 dx the residual is above the float64 threshold of a context (1e-13)
+    and the error there is indeed far above float64 rounding."""
+    from oracle.tables import gp_tables
+    res = gw.compute_table_residual(3, ell, 3.0)
+    t = gw.compute_tables(3, ell, 3.0)
+    o = gp_tables(3, ell, 3.0)
+    g_err = float(np.abs(t["gamma+"][:4] - np.asarray(o["gamma+"], dtype=float)[:4]).max())
+    w_ref = np.asarray(o["w+"], dtype=float)[:4, :4]
+    assert g_err <= 10 * res + 4e-16
+    np.testing.assert_allclose(t["w+"][:4, :4], w_ref, rtol=2e-16, atol=0)
+    if ell <= 40.0:
+        assert res < 1e-15 and g_err < 1e-15
+    if ell >= 80.0:
+        assert res > 1e-13 and g_err > 1e-13
+
+
+def test_residual_grows_with_ell_and_stays_small_for_r_up_to_two():
+    r3 = [gw.compute_table_residual(3, e, 3.0) for e in (12.0, 40.0, 60.0, 80.0, 192.0)]
+    assert all(a < b for a, b in zip(r3, r3[1:]))
+    assert r3[2] > 1e-13 > gw.compute_table_residual(3, 51.2, 3.0)
+    for R in (1, 2):
+        assert gw.compute_table_residual(R, 192.0, 3.0) < 1e-15
+    assert gw.compute_table_residual(2, 80.0, 3.0, scheme="gp-ao") > 1e-13

@@ -25,6 +25,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU containers
 
 import paper_1808_04960_amd as gw  # noqa: E402
 from test_gpu_parity import EPS, flux_bound, rel_l1  # noqa: E402
+from parity_bounds import rhs_cell_excess  # noqa: E402
 
 
 def announce(msg):
@@ -52,8 +53,10 @@ def test_rhs_with_boundaries_matches_oracle(ndim, R, prec):
     got = s.rhs(U)
     err = float(np.abs(got - ref).sum())
     bound = 16 * EPS[prec] * flux_bound(g, U)
-    announce(f"  abs L1 {err:.3e}  bound {bound:.3e}  rel L1 {rel_l1(got, ref):.3e}")
+    cell = rhs_cell_excess(g, U, got, ref, prec, R)
+    announce(f"  abs L1 {err:.3e}  bound {bound:.3e}  rel L1 {rel_l1(got, ref):.3e}  worst cell {cell:.2f}")
     assert err < bound
+    assert cell <= 1.0
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])

@@ -1,0 +1,138 @@
+"""Full-length parity at the benchmark-scale workloads, both precisions, in the
+launch configuration the benchmark times (gpweno_run, graph replays):
+
+  C2  2D isentropic vortex 512^2, GP-R2, to t = 10 (one period, 6903 steps);
+  C3  2D Kelvin-Helmholtz 2048 x 1024, GP-R3, 200 steps;
+  C4  3D density wave 256^3 and 3D isentropic vortex 256^3, GP-R2, 50 steps.
+
+The oracle's states for C2 and C4 were written by
+tests/golden/make_oracle_references.py, which calls only the CPU oracle (C4 in
+the reduced forms its symmetries allow: the wave as a function of (i+j+k) mod
+256, the vortex as one z-slice; for the wave the stored deviation of the whole
+oracle state from that function is added to the measured distance, so the bound
+holds against the oracle's own state). C3's oracle runs here, on the host's
+cores (a few minutes).
+
+Bars: relative L1 1e-12 (float64) and 1e-5 (float32), the same step count and
+end time, and the per-cell state bound of parity_bounds.
+"""
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from parity_bounds import state_cell_excess
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1808_04960_amd as gw  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def announce(msg):
+    print(f"[gpu-fulllength] {msg}", file=sys.stderr, flush=True)
+
+
+def reference(name):
+    with np.load(os.path.join(GOLDEN, f"oracle_{name}.npz"), allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def gpu_run(g, U, R, prec, t_final, max_steps):
+    dx = g.dx[0]
+    s = gw.Solver(g, R, 12 * dx, 3 * dx, precision=prec, U0=U)
+    t0 = time.perf_counter()
+    n, t = s.run(t_final, max_steps=max_steps)
+    el = time.perf_counter() - t0
+    Ug = s.get_state()
+    s.close()
+    return Ug, n, t, el
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c2_vortex_full_period(prec):
+    ref = reference("vortex2d_512")
+    g, U = inputs.isentropic_vortex_2d(512)
+    announce(f"C2 512^2 to t = 10, {prec}")
+    Ug, n, t, el = gpu_run(g, U, 2, prec, 10.0, -1)
+    Uo = ref["U"]
+    err = float(np.abs(Ug - Uo).sum() / np.abs(Uo).sum())
+    cell = state_cell_excess(g, U, Ug, Uo, prec, t, n)
+    announce(f"  {n} steps in {el:.2f} s, rel L1 vs oracle {err:.3e}, worst cell {cell:.3f}")
+    assert n == int(ref["nsteps"]) and abs(t - float(ref["t"])) <= 1e-12
+    assert err < TOL[prec]
+    assert cell <= 1.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c4_wave_50_steps(prec):
+    ref = reference("wave3d_256")
+    g, U = inputs.density_wave_3d(256)
+    announce(f"C4 wave 256^3, 50 steps, {prec}")
+    Ug, n, t, el = gpu_run(g, U, 2, prec, 1e9, 50)
+    N = 256
+    s = (np.arange(N)[:, None, None] + np.arange(N)[None, :, None] + np.arange(N)[None, None, :]) % N
+    f = ref["f"]
+    num = 0.0
+    worst = np.zeros(g.nv)
+    for k in range(g.nv):
+        d = np.abs(Ug[k] - f[k][s])
+        num += float(d.sum())
+        worst[k] = float(d.max())
+    # distance to the oracle's whole state <= distance to its reduced form +
+    # the reduced form's distance to the whole state
+    err = (num + float(ref["dev_l1"])) / float(ref["norm_l1"])
+    Uref = np.stack([f[k][s] for k in range(g.nv)])
+    cell = state_cell_excess(g, U, Ug, Uref, prec, t, n)
+    announce(f"  {n} steps in {el:.2f} s, rel L1 vs oracle <= {err:.3e}, worst cell {cell:.3f} "
+             f"(reference deviation max {float(ref['dev_max']):.1e})")
+    assert n == int(ref["nsteps"]) == 50 and abs(t - float(ref["t"])) <= 1e-13 * float(ref["t"])
+    assert err < TOL[prec]
+    assert cell <= 1.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_c4_vortex_50_steps(prec):
+    ref = reference("vortex3d_256")
+    g, U = inputs.isentropic_vortex_3d(256)
+    announce(f"C4 vortex 256^3 (w = 0), 50 steps, {prec}")
+    Ug, n, t, el = gpu_run(g, U, 2, prec, 1e9, 50)
+    sl = ref["slice"]
+    Uref = np.broadcast_to(sl[:, None], Ug.shape)
+    err = float(np.abs(Ug - Uref).sum() / np.abs(Uref).sum())
+    cell = state_cell_excess(g, U, Ug, np.ascontiguousarray(Uref), prec, t, n)
+    announce(f"  {n} steps in {el:.2f} s, rel L1 vs oracle {err:.3e}, worst cell {cell:.3f}")
+    assert n == int(ref["nsteps"]) == 50 and abs(t - float(ref["t"])) <= 1e-13 * float(ref["t"])
+    assert err < TOL[prec]
+    assert cell <= 1.0
+    assert np.all(Ug[3] == 0.0)   # w stays exactly zero
+
+
+@pytest.mark.timeout(1200)
+def test_c3_kelvin_helmholtz_200_steps():
+    """Both precisions against one oracle run of 200 steps on the host."""
+    g, U = inputs.kelvin_helmholtz_2d(2048, 1024)
+    dx = g.dx[0]
+    announce(f"C3 2048x1024 R3, 200 steps: oracle on {oracle.threads()} threads")
+    t0 = time.perf_counter()
+    Uo = U.copy()
+    t_o, n_o = oracle.OracleSolver(g, 3, 12 * dx, 3 * dx).run(Uo, 1e9, max_steps=200)
+    announce(f"  oracle: {n_o} steps in {time.perf_counter() - t0:.0f} s")
+    for prec in ("fp64", "fp32"):
+        Ug, n, t, el = gpu_run(g, U, 3, prec, 1e9, 200)
+        err = float(np.abs(Ug - Uo).sum() / np.abs(Uo).sum())
+        cell = state_cell_excess(g, U, Ug, Uo, prec, t, n)
+        announce(f"  {prec}: {n} steps in {el:.2f} s, rel L1 vs oracle {err:.3e}, worst cell {cell:.3f}")
+        assert n == n_o == 200 and abs(t - t_o) <= 1e-13 * t_o
+        assert err < TOL[prec]
+        assert cell <= 1.0

@@ -16,6 +16,7 @@ import pytest
 
 import inputs
 import oracle
+from parity_bounds import EPS as _EPS, local_flux_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -112,6 +113,9 @@ def test_fullsize_rhs_sampled(name, prec):
         err = float(np.abs(got - ref).sum())
         bound = 16 * EPS[prec] * flux_scale(bg, interior(Ub, g.ndim, G, size))
         assert err < bound, (starts, err, bound)
+        # per cell: 32 eps of the largest face flux within reach (parity_bounds)
+        cell_scale = interior(local_flux_scale(bg, Ub, R + 3)[None], g.ndim, G, size)
+        assert np.all(np.abs(got - ref) <= 32 * _EPS[prec] * cell_scale), starts
 
 
 @pytest.mark.parametrize("name", list(CONFIGS))
@@ -144,4 +148,10 @@ def test_fullsize_step_sampled(name, prec, tol):
         got = interior(extract(U1, idx), g.ndim, G, size)
         num += float(np.abs(got - ref).sum())
         den += float(np.abs(ref).sum())
+        # per cell: one step moves each cell by dt L, so the right-hand-side
+        # bound times dt (the three stages' weights sum to one), plus float64
+        # rounding of the stage combinations
+        S = float(local_flux_scale(bg, Ub, 3 * (R + 3)).max())
+        umax = np.abs(ref).reshape(g.nv, -1).max(axis=1)[(slice(None),) + (None,) * g.ndim]
+        assert np.all(np.abs(got - ref) <= 32 * _EPS[prec] * dt_gpu * S + 8 * _EPS["fp64"] * umax), starts
     assert num / den < tol, num / den

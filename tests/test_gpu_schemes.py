@@ -29,6 +29,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU containers
 
 import paper_1808_04960_amd as gw  # noqa: E402
 from test_gpu_parity import EPS, GRIDS, flux_bound, rel_l1  # noqa: E402
+from parity_bounds import local_flux_scale, rhs_cell_excess, state_cell_excess  # noqa: E402
 
 
 def announce(msg):
@@ -55,8 +56,8 @@ def test_scheme_rhs_matches_oracle(scheme, R, ndim, prec):
     o = oracle.OracleSolver(g, R, 12 * dx, 3 * dx, scheme=scheme)
     ref = o.rhs(U)
     rng = np.random.default_rng(7)
-    pert = max(float(np.abs(o.rhs(U * (1.0 + EPS[prec] * rng.uniform(-1, 1, U.shape))) - ref).sum())
-               for _ in range(3))
+    perts = [np.abs(o.rhs(U * (1.0 + EPS[prec] * rng.uniform(-1, 1, U.shape))) - ref) for _ in range(3)]
+    pert = max(float(p.sum()) for p in perts)
     s = gw.Solver(g, R, 12 * dx, 3 * dx, precision=prec, U0=U, scheme=scheme)
     got = s.rhs(U)
     err = float(np.abs(got - ref).sum())
@@ -64,6 +65,9 @@ def test_scheme_rhs_matches_oracle(scheme, R, ndim, prec):
     announce(f"  abs L1 {err:.3e}  rounding bound {bound:.3e}  oracle perturbed {pert:.3e}  "
              f"rel L1 {rel_l1(got, ref):.3e}")
     assert err < bound + 4 * pert
+    # per cell: the cell's rounding bound plus 4x the oracle's own response there
+    cell_bound = 32 * EPS[prec] * local_flux_scale(g, U, R + 3)[None] + 4 * np.maximum.reduce(perts)
+    assert np.all(np.abs(got - ref) <= cell_bound)
 
 
 def _vortex_dt(g, U, R, dx):
@@ -108,13 +112,20 @@ def test_scheme_vortex_period_matches_oracle(scheme, prec, tol):
     if scheme == "weno-gp":
         announce(f"  rel L1 vs oracle {err:.3e}")
         assert err < tol
+        assert state_cell_excess(g, U, Ug, Uo, prec, 20.0, nst) <= 1.0
         return
     rng = np.random.default_rng(3)
     spread = 0.0
+    spread_cell = np.zeros(g.nv)
     for _ in range(2):
         Up = U * (1.0 + EPS[prec] * rng.uniform(-1, 1, U.shape))
         o.run_fixed(Up, dt, nst)
         spread = max(spread, rel_l1(Up, Uo))
+        spread_cell = np.maximum(spread_cell, np.abs(Up - Uo).reshape(g.nv, -1).max(axis=1))
+    # per cell: no cell further from the oracle than the same multiple of the
+    # oracle's own worst-cell spread (per field)
+    worst = np.abs(Ug - Uo).reshape(g.nv, -1).max(axis=1)
+    assert np.all(worst <= (4 if prec == "fp64" else 10) * spread_cell)
     l1_g = float(np.mean(np.abs(Ug[0] - U[0])))
     l1_o = float(np.mean(np.abs(Uo[0] - U[0])))
     announce(f"  rel L1 vs oracle {err:.3e}, oracle spread {spread:.3e}, density L1 {l1_g:.6e} vs {l1_o:.6e}")
@@ -250,8 +261,10 @@ def test_gp_ao_rhs_matches_oracle(R, ndim, prec):
     got = s.rhs(U)
     err = float(np.abs(got - ref).sum())
     bound = 16 * EPS[prec] * flux_bound(g, U)
-    announce(f"  abs L1 {err:.3e}  bound {bound:.3e}  rel L1 {rel_l1(got, ref):.3e}")
+    cell = rhs_cell_excess(g, U, got, ref, prec, R)
+    announce(f"  abs L1 {err:.3e}  bound {bound:.3e}  rel L1 {rel_l1(got, ref):.3e}  worst cell {cell:.2f}")
     assert err < bound
+    assert cell <= 1.0
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
@@ -276,8 +289,10 @@ def test_gp_ao_vortex_matches_oracle(prec, tol):
     Uo = U.copy()
     oracle.OracleSolver(g, 3, 12 * dx, 1.8 * dx, scheme="gp-ao").run(Uo, 10.0, max_steps=30)
     s = gw.Solver(g, 3, 12 * dx, 1.8 * dx, precision=prec, U0=U, scheme="gp-ao")
-    n, _ = s.run(10.0, max_steps=30)
+    n, t = s.run(10.0, max_steps=30)
     assert n == 30
-    err = rel_l1(s.get_state(), Uo)
+    Ug = s.get_state()
+    err = rel_l1(Ug, Uo)
     announce(f"gp-ao vortex {prec}: rel L1 vs oracle {err:.3e}")
     assert err < tol
+    assert state_cell_excess(g, U, Ug, Uo, prec, t, n) <= 1.0
