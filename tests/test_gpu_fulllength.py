@@ -37,6 +37,9 @@ import paper_1808_04960_amd as gw  # noqa: E402
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 TOL = {"fp64": 1e-12, "fp32": 1e-5}
+# end time of a run of a fixed step count: every dt comes from the CFL speed of
+# a state that carries the sweep's rounding (float32: about 1e-7 relative)
+T_TOL = {"fp64": 1e-13, "fp32": 1e-6}
 
 
 def announce(msg):
@@ -96,7 +99,7 @@ def test_c4_wave_50_steps(prec):
     cell = state_cell_excess(g, U, Ug, Uref, prec, t, n)
     announce(f"  {n} steps in {el:.2f} s, rel L1 vs oracle <= {err:.3e}, worst cell {cell:.3f} "
              f"(reference deviation max {float(ref['dev_max']):.1e})")
-    assert n == int(ref["nsteps"]) == 50 and abs(t - float(ref["t"])) <= 1e-13 * float(ref["t"])
+    assert n == int(ref["nsteps"]) == 50 and abs(t - float(ref["t"])) <= T_TOL[prec] * float(ref["t"])
     assert err < TOL[prec]
     assert cell <= 1.0
 
@@ -112,7 +115,7 @@ def test_c4_vortex_50_steps(prec):
     err = float(np.abs(Ug - Uref).sum() / np.abs(Uref).sum())
     cell = state_cell_excess(g, U, Ug, np.ascontiguousarray(Uref), prec, t, n)
     announce(f"  {n} steps in {el:.2f} s, rel L1 vs oracle {err:.3e}, worst cell {cell:.3f}")
-    assert n == int(ref["nsteps"]) == 50 and abs(t - float(ref["t"])) <= 1e-13 * float(ref["t"])
+    assert n == int(ref["nsteps"]) == 50 and abs(t - float(ref["t"])) <= T_TOL[prec] * float(ref["t"])
     assert err < TOL[prec]
     assert cell <= 1.0
     assert np.all(Ug[3] == 0.0)   # w stays exactly zero
@@ -133,6 +136,6 @@ def test_c3_kelvin_helmholtz_200_steps():
         err = float(np.abs(Ug - Uo).sum() / np.abs(Uo).sum())
         cell = state_cell_excess(g, U, Ug, Uo, prec, t, n)
         announce(f"  {prec}: {n} steps in {el:.2f} s, rel L1 vs oracle {err:.3e}, worst cell {cell:.3f}")
-        assert n == n_o == 200 and abs(t - t_o) <= 1e-13 * t_o
+        assert n == n_o == 200 and abs(t - t_o) <= T_TOL[prec] * t_o
         assert err < TOL[prec]
         assert cell <= 1.0
