@@ -12,6 +12,11 @@ Admission is first-in first-out: a request that does not fit blocks the ones
 behind it (no starvation of large problems). A request larger than the whole
 budget is rejected.
 
+Failures stay with their request: one the device flags as non-physical, one
+whose admission raises (e.g. invalid parameters, an allocation failure), and
+one the batch refuses when the set changes, each end as "failed" with their
+footprint released, while the others keep running.
+
 Executors:
   ``GpuExecutor`` -- the device path (``Solver`` + ``Batch``);
   ``SimExecutor`` -- a modelled executor on a virtual clock, used to test the
@@ -46,6 +51,7 @@ class Job:
     steps_done: int = 0
     handle: object = None
     result: object = None
+    error: str = ""
 
     @property
     def latency(self) -> float:
@@ -114,7 +120,13 @@ class Server:
             changed = False
             while waiting and len(active) < self.max_slots and used + waiting[0].footprint <= self.budget:
                 j = waiting.pop(0)
-                j.handle = ex.admit(j.req)
+                try:
+                    j.handle = ex.admit(j.req)
+                except Exception as e:  # noqa: BLE001 - the request fails, the server goes on
+                    j.status = "failed"
+                    j.error = repr(e)
+                    j.finished = ex.now() - t0
+                    continue
                 j.status = "active"
                 j.admitted = ex.now() - t0
                 used += j.footprint
@@ -123,7 +135,9 @@ class Server:
             peak_bytes = max(peak_bytes, used)
             peak_active = max(peak_active, len(active))
             if changed:
-                ex.set_active([j.handle for j in active])
+                active, refused = self._set_active(active)
+                for j in refused:
+                    used -= self._fail(j, ex.now() - t0)
             if not active:
                 if pending:
                     ex.idle_until(t0 + pending[0].req.arrival)
@@ -144,9 +158,43 @@ class Server:
                     retired.append(j)
             if retired:
                 active = [j for j in active if j.handle is not None]
-                ex.set_active([j.handle for j in active])
+                active, refused = self._set_active(active)
+                for j in refused:
+                    used -= self._fail(j, ex.now() - t0)
         makespan = max((j.finished for j in jobs), default=0.0) - first_arrival
         return Report(jobs, makespan, cell_updates, peak_bytes, peak_active, ticks)
+
+    def _set_active(self, active):
+        """Hands the active jobs to the executor. If it refuses the set, the jobs
+        are added back one at a time: those it refuses alone are returned as
+        refused, the rest form the new set (an executor that refuses even
+        that raises)."""
+        try:
+            self.ex.set_active([j.handle for j in active])
+            return active, []
+        except Exception:  # noqa: BLE001 - find the job(s) it refuses
+            pass
+        ok, refused = [], []
+        for j in active:
+            try:
+                self.ex.set_active([h.handle for h in ok] + [j.handle])
+                ok.append(j)
+            except Exception as e:  # noqa: BLE001
+                j.error = repr(e)
+                refused.append(j)
+        self.ex.set_active([j.handle for j in ok])
+        return ok, refused
+
+    def _fail(self, j, now):
+        """Ends an active job as failed; returns the footprint it released."""
+        try:
+            self.ex.retire(j.handle, False)
+        except Exception:  # noqa: BLE001 - its resources go with the handle
+            pass
+        j.handle = None
+        j.status = "failed"
+        j.finished = now
+        return j.footprint
 
 
 class GpuExecutor:
@@ -214,11 +262,17 @@ class SimExecutor:
         req: object
         steps: int = 0
 
-    def __init__(self, rate=5e9, fail_rids=()):
+    def __init__(self, rate=5e9, fail_rids=(), admit_raises=(), set_refuses=()):
+        """fail_rids: requests the device flags non-physical after their first
+        step; admit_raises: requests whose admission raises; set_refuses:
+        requests whose handle the batch refuses (set_active raises while it is
+        in the set)."""
         self.t = 0.0
         self.rate = float(rate)
         self.active = []
         self.fail_rids = set(fail_rids)
+        self.admit_raises = set(admit_raises)
+        self.set_refuses = set(set_refuses)
         self.admitted = []
 
     def now(self):
@@ -231,10 +285,14 @@ class SimExecutor:
         return footprint_bytes(req.grid)
 
     def admit(self, req):
+        if req.rid in self.admit_raises:
+            raise RuntimeError(f"admission of request {req.rid} failed")
         self.admitted.append(req.rid)
         return SimExecutor.Handle(req)
 
     def set_active(self, handles):
+        if any(h.req.rid in self.set_refuses for h in handles):
+            raise RuntimeError("batch refused the set")
         self.active = list(handles)
 
     def advance(self, k):

@@ -36,6 +36,10 @@ class _Recorder(SimExecutor):
         self.max_used = 0
         self.max_active = 0
 
+    def set_active(self, handles):
+        super().set_active(handles)   # raises for a set the executor refuses
+        self.ever_active = getattr(self, "ever_active", set()) | {h.req.rid for h in self.active}
+
     def advance(self, k):
         used = sum(footprint_bytes(h.req.grid) for h in self.active)
         self.max_used = max(self.max_used, used)
@@ -128,3 +132,29 @@ def test_latency_percentiles():
     assert s["p50_ms"] == pytest.approx(np.percentile(lat, 50) * 1e3)
     assert s["p99_ms"] == pytest.approx(np.percentile(lat, 99) * 1e3)
     assert s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_a_request_whose_admission_raises_fails_alone():
+    """Admission raising (e.g. invalid parameters or an allocation failure) ends
+    that request as failed, takes no memory, and the loop serves the rest."""
+    reqs = [_Req(i, 0.001 * i, 64, 12) for i in range(6)]
+    ex = _Recorder(rate=1e9, admit_raises={2})
+    rep = Server(ex, hbm_budget=footprint_bytes(reqs[0].grid) * 2, max_slots=4, steps_per_tick=4).run(reqs)
+    st = {j.req.rid: j.status for j in rep.jobs}
+    assert st == {0: "done", 1: "done", 2: "failed", 3: "done", 4: "done", 5: "done"}
+    assert "admission of request 2" in rep.jobs[2].error
+    assert ex.max_used <= footprint_bytes(reqs[0].grid) * 2
+    assert rep.summary()["failed"] == 1
+
+
+def test_a_request_the_batch_refuses_fails_alone():
+    """The batch refusing a set (e.g. the device-side tables of one member) is
+    traced to the member it refuses alone: that request fails, its footprint is
+    released, and the set is rebuilt from the others, which finish."""
+    reqs = [_Req(i, 0.0, 64, 16) for i in range(5)]
+    ex = _Recorder(rate=1e9, set_refuses={3})
+    rep = Server(ex, hbm_budget=footprint_bytes(reqs[0].grid) * 5, max_slots=8, steps_per_tick=4).run(reqs)
+    st = {j.req.rid: j.status for j in rep.jobs}
+    assert st == {0: "done", 1: "done", 2: "done", 3: "failed", 4: "done"}
+    assert rep.jobs[3].steps_done == 0 and "refused" in rep.jobs[3].error
+    assert 3 not in ex.ever_active and {0, 1, 2, 4} <= ex.ever_active
