@@ -323,21 +323,37 @@ typedef struct gpweno_batch gpweno_batch;
 int gpweno_batch_create(gpweno_batch **out);
 
 /* Sets the batch's problems: n (<= 4096) distinct bound contexts on the batch's
- * device. Waits for the stream, then uploads the launch descriptors (the
- * batch owns its device buffers and grows them as needed) and drops the
- * captured step graph. The contexts must stay alive and bound until they are
- * removed by the next gpweno_batch_set. n = 0 empties the batch.
- * Errors: EINVAL (NULL, repeated or unbound context, mixed devices), ENOMEM, EHIP. */
+ * device, of at most 64 kinds. Enqueued: the batch's device work tables (the
+ * problems' descriptors and block owners) are written by stream-ordered copies
+ * from a pinned staging ring, so launches enqueued before the call still see
+ * the old set and later ones the new; the host does not wait for the stream
+ * (except when the tables outgrow their capacity, which doubles, or when the
+ * previous call used another stream). The captured step graph reads the
+ * tables through fixed addresses and keeps serving the new set while its kinds
+ * of problems stay the same. The contexts must stay alive and bound until they
+ * are removed by a later gpweno_batch_set and that set's launches have begun
+ * (destroying a context synchronises its stream). n = 0 empties the batch.
+ * Errors: EINVAL (NULL, repeated or unbound context, mixed devices, too many
+ * kinds), ENOMEM, EHIP. */
 int gpweno_batch_set(gpweno_batch *b, gpweno_ctx *const *ctxs, int n, void *stream);
 
 /* Enqueues nsteps batched steps (nsteps >= 1) on stream by replaying a captured
- * graph of one batched step. Errors: EINVAL, EHIP. */
+ * graph of one batched step (captured on first use, and again only when the
+ * set's kinds of problems or its size have changed beyond what the graph
+ * serves). Every launch has a fixed grid whose blocks loop over the set's
+ * logical blocks. Errors: EINVAL, EHIP. */
 int gpweno_batch_run(gpweno_batch *b, int nsteps, void *stream);
 
 /* Blocking: for every problem of the set, in set order, its time, last dt, step
  * count and error flag (1: non-physical state) into host arrays of length n
  * (each nullable). Errors: EINVAL, EHIP. */
 int gpweno_batch_status(gpweno_batch *b, double *t, double *dt, long *nsteps, int *err, void *stream);
+
+/* Number of times the batch has captured its step graph (instrumentation; -1
+ * for NULL). A set change that keeps the kinds of problems (dimension, R,
+ * precision, scheme, boundary kinds, tables) and sizes within a factor of a
+ * few of the captured ones does not add one. */
+long gpweno_batch_captures(const gpweno_batch *b);
 
 /* Waits for the batch's last stream and frees its resources. NULL is ignored. */
 void gpweno_batch_destroy(gpweno_batch *b);

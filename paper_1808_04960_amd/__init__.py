@@ -88,6 +88,8 @@ def lib():
         L.gpweno_batch_set.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, vp]
         L.gpweno_batch_run.argtypes = [vp, ctypes.c_int, vp]
         L.gpweno_batch_status.argtypes = [vp, _dp, _dp, ctypes.POINTER(ctypes.c_long), ctypes.POINTER(ctypes.c_int), vp]
+        L.gpweno_batch_captures.argtypes = [vp]
+        L.gpweno_batch_captures.restype = ctypes.c_long
         L.gpweno_batch_destroy.argtypes = [vp]
         L.gpweno_batch_destroy.restype = None
         L.gpweno_batch_last_error.argtypes = [vp]
@@ -234,15 +236,24 @@ class Solver:
         self.precision = precision
 
     # -- state ---------------------------------------------------------------
-    def set_state(self, U, t=0.0, nsteps=0):
-        """Copies U (numpy or torch, float64, shape (nv, *grid.shape)) into the device state."""
+    def set_state(self, U, t=0.0, nsteps=0, upload_stream=None):
+        """Copies U (numpy or torch, float64, shape (nv, *grid.shape)) into the device state.
+        upload_stream: copy from pinned host memory on that stream and make this
+        solver's stream wait for it, without the host waiting for work already
+        enqueued on the solver's stream (the serving loop admits problems so)."""
         torch = self._torch
         src = torch.as_tensor(np.ascontiguousarray(U) if isinstance(U, np.ndarray) else U, dtype=torch.float64)
         if tuple(src.shape) != self.shape:
             raise GpwenoError(EINVAL, f"state shape {tuple(src.shape)} != {self.shape}")
-        torch.cuda.current_stream(self.device).synchronize()
-        with torch.cuda.stream(self.stream):
-            self.state.copy_(src)
+        if upload_stream is not None:
+            staged = src.pin_memory() if src.device.type == "cpu" else src
+            with torch.cuda.stream(upload_stream):
+                self.state.copy_(staged, non_blocking=True)
+            self.stream.wait_stream(upload_stream)
+        else:
+            torch.cuda.current_stream(self.device).synchronize()
+            with torch.cuda.stream(self.stream):
+                self.state.copy_(src)
         if not self._bound:
             _check(lib().gpweno_bind(self._ctx, ctypes.c_void_p(self.state.data_ptr()),
                                      ctypes.c_void_p(self.workspace.data_ptr())), self._ctx)
@@ -384,6 +395,10 @@ class Batch:
         _bcheck(lib().gpweno_batch_status(self._b, t.ctypes.data_as(_dp), dt.ctypes.data_as(_dp), ns, er,
                                           ctypes.c_void_p(self.stream.cuda_stream)), self._b)
         return t[:n], dt[:n], np.array(ns[:n], dtype=np.int64), np.array(er[:n], dtype=np.int32)
+
+    def captures(self):
+        """Times the batch has captured its step graph."""
+        return lib().gpweno_batch_captures(self._b)
 
     def close(self):
         if self._b:

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
@@ -41,7 +42,54 @@ constexpr double FP64_TABLE_RESIDUAL = 1e-13;
 
 thread_local std::string g_tls_error = "";
 
+// Control blocks (device) and their pinned host mirrors come from a pool per
+// device, allocated in chunks and never returned, so that creating and
+// destroying contexts (a serving loop admits and retires problems all the
+// time) calls no hipMalloc or hipFree, which would synchronise the device.
+constexpr int CTL_CHUNK = 64;
+
+struct CtlPool {
+    std::vector<gpw::Ctl*> dev, host;
+};
+
+std::mutex g_pool_mu;
+std::vector<CtlPool> g_pools;
+
+hipError_t ctl_acquire(int device, gpw::Ctl** d, gpw::Ctl** h) {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if ((int)g_pools.size() <= device) g_pools.resize(device + 1);
+    CtlPool& p = g_pools[device];
+    if (p.dev.empty()) {
+        gpw::Ctl *dc = nullptr, *hc = nullptr;
+        hipError_t e = hipMalloc(&dc, sizeof(gpw::Ctl) * CTL_CHUNK);
+        if (e != hipSuccess) return e;
+        e = hipHostMalloc(&hc, sizeof(gpw::Ctl) * CTL_CHUNK, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            (void)hipFree(dc);
+            return e;
+        }
+        for (int i = CTL_CHUNK - 1; i >= 0; --i) {
+            p.dev.push_back(dc + i);
+            p.host.push_back(hc + i);
+        }
+    }
+    *d = p.dev.back();
+    *h = p.host.back();
+    p.dev.pop_back();
+    p.host.pop_back();
+    return hipSuccess;
+}
+
+void ctl_release(int device, gpw::Ctl* d, gpw::Ctl* h) {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (device < 0 || device >= (int)g_pools.size() || !d || !h) return;
+    g_pools[device].dev.push_back(d);
+    g_pools[device].host.push_back(h);
+}
+
+
 }  // namespace
+
 
 struct gpweno_ctx {
     gpweno_grid grid;
@@ -225,14 +273,17 @@ int ensure_graph(gpweno_ctx* c, int i) {
     return GPWENO_OK;
 }
 
-// Enqueues exactly n steps as graph replays, largest graphs first.
+// Enqueues exactly n steps as graph replays, largest graphs first. Every size
+// is captured the first time any is needed, so that a later run of another
+// length does not capture (a few milliseconds) while it is timed.
 int enqueue_graph_steps(gpweno_ctx* c, long long n, hipStream_t s) {
+    for (int i = 0; i < NGRAPH; ++i) {
+        int st = ensure_graph(c, i);
+        if (st) return st;
+    }
     for (int i = 0; i < NGRAPH; ++i) {
         const long long reps = n / GRAPH_STEPS[i];
         n -= reps * GRAPH_STEPS[i];
-        if (reps == 0) continue;
-        int st = ensure_graph(c, i);
-        if (st) return st;
         for (long long r = 0; r < reps; ++r) HIP_TRY(c, hipGraphLaunch(c->graph[i], s));
     }
     return GPWENO_OK;
@@ -449,10 +500,10 @@ int gpweno_init_scheme(const gpweno_grid* grid, int scheme, int R, double ell, d
     c->opt.nonzero_mean = 0;
     c->opt.flux_corr_terms = 2;
     hipError_t e = hipGetDevice(&c->device);
-    if (e == hipSuccess) e = hipMalloc(&c->d_ctl, sizeof(gpw::Ctl));
-    if (e == hipSuccess) e = hipHostMalloc(&c->h_ctl, sizeof(gpw::Ctl), hipHostMallocDefault);
+    if (e == hipSuccess) e = ctl_acquire(c->device, &c->d_ctl, &c->h_ctl);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipMemset(c->d_ctl, 0, sizeof(gpw::Ctl));
+    if (e == hipSuccess) e = hipMemsetAsync(c->d_ctl, 0, sizeof(gpw::Ctl), c->own_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->own_stream);
     if (e != hipSuccess) {
         int code = fail(nullptr, GPWENO_EHIP, "device set-up: %s", hipGetErrorString(e));
         gpweno_destroy(c);
@@ -739,8 +790,7 @@ void gpweno_destroy(gpweno_ctx* c) {
     if (c->own_stream) (void)hipStreamSynchronize(c->own_stream);
     drop_graph(c);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
-    if (c->d_ctl) (void)hipFree(c->d_ctl);
-    if (c->h_ctl) (void)hipHostFree(c->h_ctl);
+    ctl_release(c->device, c->d_ctl, c->h_ctl);
     delete c;
 }
 
@@ -752,41 +802,51 @@ void gpweno_destroy(gpweno_ctx* c) {
 namespace {
 
 constexpr int BATCH_MAX = 4096;
+constexpr int BATCH_MAX_GROUPS = 64;
+constexpr int DIR_PER_GROUP = 9;            // 3 stages x up to 3 directions
+constexpr int STAGING = 4;                  // pinned staging buffers in the ring
+constexpr long long GRID_MIN = 64, GRID_MAX = 2048;
 
-// Problems sharing one kernel instantiation and one set of tables (same scheme).
+// Problems sharing one kernel instantiation per launch and one set of tables.
 struct BatchGroup {
-    int ndim = 0, R = 0;
+    int ndim = 0, R = 0, ik = 0, nc = 2;
     bool fp32 = false;
-    const gpweno_ctx* proto = nullptr;      // supplies the tables
-    std::vector<int> members;               // indices into the set
-    long long blocks[3] = {0, 0, 0};        // per direction
     bool bcg[3] = {false, false, false};    // the members' axis has a non-periodic side
+    gpw::Tab<float> tabf[3];                // the group's tables (kernel arguments)
+    gpw::Tab<double> tabd[3];
+    std::vector<int> members;               // indices into the set
+    long long blocks[3] = {0, 0, 0};        // logical blocks per direction
     size_t owner_off[3] = {0, 0, 0};        // element offsets into the owner table
     size_t desc_off[3][3] = {};             // [stage-1][dir] offsets into the descriptor table
 };
 
-// Same kernel instantiation per axis: periodic-only or general boundaries. A
-// problem runs the same kernels in a batch as alone, so its result is bitwise
-// the same.
-bool same_kernels(const gpweno_ctx* a, const gpweno_ctx* b) {
-    if (indicator_kind(a) != indicator_kind(b) || corr_terms(a) != corr_terms(b)) return false;
-    for (int d = 0; d < a->grid.ndim; ++d)
-        if (general_bc(a->grid, d) != general_bc(b->grid, d)) return false;
-    return true;
-}
-
-// Same tables along every axis (each batched launch covers one direction and
-// takes that direction's tables, so a problem with non-square cells batches
-// with the problems whose per-axis tables equal its own).
-bool same_tables(const gpweno_ctx* a, const gpweno_ctx* b) {
-    if (a->scheme != b->scheme) return false;
-    for (int d = 0; d < a->grid.ndim; ++d) {
-        if (std::memcmp(&a->tab64[d], &b->tab64[d], sizeof(GpTablesF64)) != 0) return false;
-        if (a->scheme == GPWENO_GP_AO && std::memcmp(&a->ao64[d], &b->ao64[d], sizeof(GpAoTablesF64)) != 0)
+// Kernel kind and tables of a group: the kernel instantiation of every launch
+// (dimension, R, precision, indicator kind, flux-correction terms, periodic or
+// general boundaries per axis) and the tables it receives, per axis. A problem
+// runs the same kernels with the same arguments in a batch as alone, so its
+// result is bitwise the same; a problem with non-square cells batches with
+// those whose per-axis tables equal its own. A captured graph serves every set
+// whose groups have the same kinds, in the same order.
+bool same_kind(const BatchGroup& a, const BatchGroup& b) {
+    if (a.ndim != b.ndim || a.R != b.R || a.fp32 != b.fp32 || a.ik != b.ik || a.nc != b.nc) return false;
+    for (int d = 0; d < a.ndim; ++d) {
+        if (a.bcg[d] != b.bcg[d]) return false;
+        if (a.fp32 ? std::memcmp(&a.tabf[d], &b.tabf[d], sizeof(gpw::Tab<float>)) != 0
+                   : std::memcmp(&a.tabd[d], &b.tabd[d], sizeof(gpw::Tab<double>)) != 0)
             return false;
     }
     return true;
 }
+
+// Blocks of a batched launch's grid for a given count of logical blocks: a power
+// of two, so that a graph captured for one set serves sets of similar size.
+long long grid_for(long long blocks) {
+    long long g = GRID_MIN;
+    while (g < blocks && g < GRID_MAX) g <<= 1;
+    return g;
+}
+
+size_t align_up(size_t b) { return (b + 255) & ~size_t(255); }
 
 }  // namespace
 
@@ -796,6 +856,10 @@ struct gpweno_batch {
     hipStream_t last_stream = nullptr;
     std::vector<gpweno_ctx*> set;
     std::vector<BatchGroup> groups;
+    // device work tables: per group and step position a BatchDir (fixed
+    // addresses, which the captured graph's launches hold), the descriptors and
+    // block owners they point to (grown as needed), the members' control blocks
+    gpw::BatchDir* d_dir = nullptr;
     gpw::ProbDesc* d_desc = nullptr;
     size_t desc_cap = 0;
     unsigned short* d_owner = nullptr;
@@ -803,7 +867,17 @@ struct gpweno_batch {
     gpw::Ctl** d_ctls = nullptr;
     gpw::BatchStatus* d_status = nullptr;
     gpw::BatchStatus* h_status = nullptr;
+    // pinned staging ring for the stream-ordered table uploads
+    unsigned char* staging[STAGING] = {};
+    size_t staging_cap[STAGING] = {};
+    hipEvent_t staging_done[STAGING] = {};
+    bool staging_used[STAGING] = {};
+    int staging_next = 0;
+    // captured batched step and what it was captured for
     hipGraphExec_t graph = nullptr;
+    std::vector<BatchGroup> graph_groups;
+    std::vector<long long> graph_grids;     // per group and step position
+    long long recaptures = 0;
     std::string err;
 };
 
@@ -831,48 +905,111 @@ void batch_drop_graph(gpweno_batch* b) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
     }
+    b->graph_groups.clear();
+    b->graph_grids.clear();
 }
 
-// One batched launch: position k of the step sequence for group g.
-int batch_launch(gpweno_batch* b, const BatchGroup& g, int k, hipStream_t s) {
+// One batched launch: step position k for group g (its work table entry
+// d_dir[g * DIR_PER_GROUP + k]), with the given grid.
+int batch_launch(gpweno_batch* b, int gi, const BatchGroup& g, int k, long long grid, hipStream_t s) {
     const int stage = k / g.ndim + 1, j = k % g.ndim, dir = sweep_dir(g.ndim, j);
     const bool fin = j == g.ndim - 1;
-    const gpw::LaunchSel sel{dir, g.R, fin, indicator_kind(g.proto), g.bcg[dir], corr_terms(g.proto), true};
+    const gpw::LaunchSel sel{dir, g.R, fin, g.ik, g.bcg[dir], g.nc, true};
+    const gpw::BatchDir* D = b->d_dir + (size_t)gi * DIR_PER_GROUP + k;
     hipError_t e;
     if (g.fp32) {
         gpw::BatchArgs<float> a;
         std::memset(&a, 0, sizeof a);
-        a.probs = b->d_desc + g.desc_off[stage - 1][dir];
-        a.owner = b->d_owner + g.owner_off[dir];
+        a.dir = D;
         a.first = j == 0;
         a.stage = stage;
         a.step_start = k == 0;
-        a.tab = g.proto->tabf[dir];
-        e = gpw::launch_sweep(g.ndim, true, sel, &a, g.blocks[dir], s);
+        a.tab = g.tabf[dir];
+        e = gpw::launch_sweep(g.ndim, true, sel, &a, grid, s);
     } else {
         gpw::BatchArgs<double> a;
         std::memset(&a, 0, sizeof a);
-        a.probs = b->d_desc + g.desc_off[stage - 1][dir];
-        a.owner = b->d_owner + g.owner_off[dir];
+        a.dir = D;
         a.first = j == 0;
         a.stage = stage;
         a.step_start = k == 0;
-        a.tab = g.proto->tabd[dir];
-        e = gpw::launch_sweep(g.ndim, false, sel, &a, g.blocks[dir], s);
+        a.tab = g.tabd[dir];
+        e = gpw::launch_sweep(g.ndim, false, sel, &a, grid, s);
     }
     if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "batched sweep launch: %s", hipGetErrorString(e));
     return GPWENO_OK;
 }
 
-int batch_enqueue_step(gpweno_batch* b, hipStream_t s) {
+// The grid of every launch of the captured step, group by group.
+std::vector<long long> batch_grids(const std::vector<BatchGroup>& groups) {
+    std::vector<long long> out;
+    for (const auto& g : groups)
+        for (int k = 0; k < 3 * g.ndim; ++k) out.push_back(grid_for(g.blocks[sweep_dir(g.ndim, k % g.ndim)]));
+    return out;
+}
+
+// Whether the captured graph serves the current groups: the same kinds in the
+// same order, and launch grids within a factor of 8 below or 4 above what the
+// current blocks would pick (the launches loop over their logical blocks, so
+// any grid is correct; the margin only keeps grids near the work).
+bool graph_serves(const gpweno_batch* b) {
+    if (!b->graph || b->graph_groups.size() != b->groups.size()) return false;
+    for (size_t i = 0; i < b->groups.size(); ++i)
+        if (!same_kind(b->graph_groups[i], b->groups[i])) return false;
+    const std::vector<long long> want = batch_grids(b->groups);
+    for (size_t i = 0; i < want.size(); ++i)
+        if (want[i] > 4 * b->graph_grids[i] || 8 * want[i] < b->graph_grids[i]) return false;
+    return true;
+}
+
+int batch_capture(gpweno_batch* b) {
+    batch_drop_graph(b);
+    const std::vector<long long> grids = batch_grids(b->groups);
+    BHIP_TRY(b, hipStreamBeginCapture(b->own_stream, hipStreamCaptureModeThreadLocal));
+    int st = GPWENO_OK;
     int kmax = 0;
     for (const auto& g : b->groups) kmax = std::max(kmax, 3 * g.ndim);
-    for (int k = 0; k < kmax; ++k)
-        for (const auto& g : b->groups)
-            if (k < 3 * g.ndim) {
-                int st = batch_launch(b, g, k, s);
-                if (st) return st;
-            }
+    for (int k = 0; k < kmax && st == GPWENO_OK; ++k) {
+        size_t gk = 0;
+        for (size_t gi = 0; gi < b->groups.size() && st == GPWENO_OK; ++gi) {
+            const BatchGroup& g = b->groups[gi];
+            if (k < 3 * g.ndim) st = batch_launch(b, (int)gi, g, k, grids[gk + k], b->own_stream);
+            gk += 3 * g.ndim;
+        }
+    }
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(b->own_stream, &gr);
+    if (st) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return st;
+    }
+    if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->graph, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (e != hipSuccess) {
+        b->graph = nullptr;
+        return bfail(b, GPWENO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    b->graph_groups = b->groups;
+    b->graph_grids = grids;
+    ++b->recaptures;
+    return GPWENO_OK;
+}
+
+// Grows a device table to hold n elements. The old table may still be read by
+// launches in flight, so growing waits for the stream first (capacities double,
+// so this happens a logarithmic number of times).
+template <typename T>
+int grow(gpweno_batch* b, T** buf, size_t* cap, size_t n, hipStream_t s) {
+    if (n <= *cap) return GPWENO_OK;
+    size_t c = std::max<size_t>(2 * *cap, 1024);
+    while (c < n) c *= 2;
+    BHIP_TRY(b, hipStreamSynchronize(s));
+    if (*buf) (void)hipFree(*buf);
+    *buf = nullptr;
+    *cap = 0;
+    BHIP_TRY(b, hipMalloc(buf, sizeof(T) * c));
+    *cap = c;
     return GPWENO_OK;
 }
 
@@ -897,9 +1034,15 @@ int gpweno_batch_create(gpweno_batch** out) {
     if (!b) return bfail(nullptr, GPWENO_ENOMEM, "out of host memory");
     hipError_t e = hipGetDevice(&b->device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&b->d_dir, sizeof(gpw::BatchDir) * BATCH_MAX_GROUPS * DIR_PER_GROUP);
     if (e == hipSuccess) e = hipMalloc(&b->d_ctls, sizeof(gpw::Ctl*) * BATCH_MAX);
     if (e == hipSuccess) e = hipMalloc(&b->d_status, sizeof(gpw::BatchStatus) * BATCH_MAX);
     if (e == hipSuccess) e = hipHostMalloc(&b->h_status, sizeof(gpw::BatchStatus) * BATCH_MAX, hipHostMallocDefault);
+    for (int i = 0; i < STAGING && e == hipSuccess; ++i)
+        e = hipEventCreateWithFlags(&b->staging_done[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_dir, 0, sizeof(gpw::BatchDir) * BATCH_MAX_GROUPS * DIR_PER_GROUP,
+                                            b->own_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->own_stream);
     if (e != hipSuccess) {
         int code = bfail(nullptr, GPWENO_EHIP, "batch set-up: %s", hipGetErrorString(e));
         gpweno_batch_destroy(b);
@@ -919,41 +1062,58 @@ int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stre
             if (ctxs[j] == ctxs[i]) return bfail(b, GPWENO_EINVAL, "context %d repeated", i);
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    // the previous launches may still read the descriptor tables
-    BHIP_TRY(b, hipStreamSynchronize(s));
+    // work already enqueued on another stream must finish before this one
+    // rewrites the tables it reads
     if (b->last_stream && b->last_stream != s) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
-    batch_drop_graph(b);
-    b->set.assign(ctxs, ctxs + n);
-    b->groups.clear();
+    // groups, in the order their kinds first appear; kinds the captured graph
+    // already has keep their place so that the graph keeps serving the set
+    std::vector<BatchGroup> groups;
+    for (const auto& g : b->graph_groups) {
+        BatchGroup h = g;
+        h.members.clear();
+        groups.push_back(h);
+    }
     for (int i = 0; i < n; ++i) {
         const gpweno_ctx* c = ctxs[i];
-        const bool fp32 = c->opt.precision == GPWENO_FP32;
+        BatchGroup cand;
+        cand.ndim = c->grid.ndim;
+        cand.R = c->R;
+        cand.fp32 = c->opt.precision == GPWENO_FP32;
+        cand.ik = indicator_kind(c);
+        cand.nc = corr_terms(c);
+        for (int d = 0; d < 3; ++d) {
+            cand.bcg[d] = d < c->grid.ndim && general_bc(c->grid, d);
+            cand.tabf[d] = c->tabf[d];
+            cand.tabd[d] = c->tabd[d];
+        }
         BatchGroup* g = nullptr;
-        for (auto& h : b->groups)
-            if (h.ndim == c->grid.ndim && h.R == c->R && h.fp32 == fp32 && same_tables(h.proto, c) &&
-                same_kernels(h.proto, c))
+        for (auto& h : groups)
+            if (same_kind(h, cand)) {
                 g = &h;
+                break;
+            }
         if (!g) {
-            b->groups.emplace_back();
-            g = &b->groups.back();
-            g->ndim = c->grid.ndim;
-            g->R = c->R;
-            g->fp32 = fp32;
-            g->proto = c;
-            for (int d = 0; d < c->grid.ndim; ++d) g->bcg[d] = general_bc(c->grid, d);
+            if ((int)groups.size() >= BATCH_MAX_GROUPS)
+                return bfail(b, GPWENO_EINVAL, "more than %d kinds of problems in one batch", BATCH_MAX_GROUPS);
+            groups.push_back(cand);
+            g = &groups.back();
         }
         g->members.push_back(i);
     }
-    // descriptors and block owners
+    // a kind with no member left keeps its place only while the graph has it;
+    // drop empty groups at the end, and every empty group if the graph must be
+    // recaptured anyway
+    while (!groups.empty() && groups.back().members.empty()) groups.pop_back();
+    // descriptors, block owners and the work-table entries
     std::vector<gpw::ProbDesc> desc;
     std::vector<unsigned short> owner;
-    for (auto& g : b->groups) {
+    for (auto& g : groups) {
         for (int dir = 0; dir < g.ndim; ++dir) {
             g.owner_off[dir] = owner.size();
             long long total = 0;
             std::vector<long long> nblk(g.members.size()), b0(g.members.size());
             for (size_t j = 0; j < g.members.size(); ++j) {
-                const gpweno_ctx* c = b->set[g.members[j]];
+                const gpweno_ctx* c = ctxs[g.members[j]];
                 int nn[3] = {c->grid.n[0], c->grid.n[1], c->grid.n[2]};
                 const int nseg = (nn[dir] + run_cells(c) - 1) / run_cells(c);
                 nblk[j] = gpw::sweep_blocks(g.ndim, dir, g.fp32, nn, nseg);
@@ -966,7 +1126,7 @@ int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stre
             for (int stage = 1; stage <= 3; ++stage) {
                 g.desc_off[stage - 1][dir] = desc.size();
                 for (size_t j = 0; j < g.members.size(); ++j) {
-                    gpweno_ctx* c = b->set[g.members[j]];
+                    gpweno_ctx* c = ctxs[g.members[j]];
                     gpw::ProbDesc P;
                     std::memset(&P, 0, sizeof P);
                     const double* ins[3] = {c->state, c->U1, c->U2};
@@ -993,27 +1153,56 @@ int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stre
             }
         }
     }
-    if (desc.size() > b->desc_cap) {
-        if (b->d_desc) (void)hipFree(b->d_desc);
-        b->d_desc = nullptr;
-        b->desc_cap = 0;
-        BHIP_TRY(b, hipMalloc(&b->d_desc, sizeof(gpw::ProbDesc) * desc.size()));
-        b->desc_cap = desc.size();
-    }
-    if (owner.size() > b->owner_cap) {
-        if (b->d_owner) (void)hipFree(b->d_owner);
-        b->d_owner = nullptr;
-        b->owner_cap = 0;
-        BHIP_TRY(b, hipMalloc(&b->d_owner, sizeof(unsigned short) * owner.size()));
-        b->owner_cap = owner.size();
+    int st;
+    if ((st = grow(b, &b->d_desc, &b->desc_cap, desc.size(), s))) return st;
+    if ((st = grow(b, &b->d_owner, &b->owner_cap, owner.size(), s))) return st;
+    std::vector<gpw::BatchDir> dirs((size_t)BATCH_MAX_GROUPS * DIR_PER_GROUP);
+    std::memset(dirs.data(), 0, sizeof(gpw::BatchDir) * dirs.size());
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        const BatchGroup& g = groups[gi];
+        for (int k = 0; k < 3 * g.ndim; ++k) {
+            const int stage = k / g.ndim + 1, dir = sweep_dir(g.ndim, k % g.ndim);
+            gpw::BatchDir& D = dirs[gi * DIR_PER_GROUP + k];
+            D.probs = b->d_desc + g.desc_off[stage - 1][dir];
+            D.owner = b->d_owner + g.owner_off[dir];
+            D.nblocks = g.members.empty() ? 0 : g.blocks[dir];
+        }
     }
     std::vector<gpw::Ctl*> ctls(n);
     for (int i = 0; i < n; ++i) ctls[i] = ctxs[i]->d_ctl;
+    // stage everything in one pinned buffer of the ring and copy it in stream
+    // order: launches enqueued before this call still read the old tables
+    const size_t o_desc = 0, o_owner = align_up(o_desc + sizeof(gpw::ProbDesc) * desc.size());
+    const size_t o_dir = align_up(o_owner + sizeof(unsigned short) * owner.size());
+    const size_t o_ctl = align_up(o_dir + sizeof(gpw::BatchDir) * dirs.size());
+    const size_t bytes = align_up(o_ctl + sizeof(gpw::Ctl*) * ctls.size());
+    const int slot = b->staging_next;
+    b->staging_next = (slot + 1) % STAGING;
+    if (b->staging_used[slot]) BHIP_TRY(b, hipEventSynchronize(b->staging_done[slot]));
+    if (bytes > b->staging_cap[slot]) {
+        if (b->staging[slot]) (void)hipHostFree(b->staging[slot]);
+        b->staging[slot] = nullptr;
+        b->staging_cap[slot] = 0;
+        const size_t c = std::max(bytes, (size_t)1 << 16);
+        BHIP_TRY(b, hipHostMalloc(&b->staging[slot], c, hipHostMallocDefault));
+        b->staging_cap[slot] = c;
+    }
+    unsigned char* h = b->staging[slot];
+    if (!desc.empty()) std::memcpy(h + o_desc, desc.data(), sizeof(gpw::ProbDesc) * desc.size());
+    if (!owner.empty()) std::memcpy(h + o_owner, owner.data(), sizeof(unsigned short) * owner.size());
+    std::memcpy(h + o_dir, dirs.data(), sizeof(gpw::BatchDir) * dirs.size());
+    if (n) std::memcpy(h + o_ctl, ctls.data(), sizeof(gpw::Ctl*) * ctls.size());
     if (!desc.empty())
-        BHIP_TRY(b, hipMemcpy(b->d_desc, desc.data(), sizeof(gpw::ProbDesc) * desc.size(), hipMemcpyHostToDevice));
+        BHIP_TRY(b, hipMemcpyAsync(b->d_desc, h + o_desc, sizeof(gpw::ProbDesc) * desc.size(), hipMemcpyHostToDevice, s));
     if (!owner.empty())
-        BHIP_TRY(b, hipMemcpy(b->d_owner, owner.data(), sizeof(unsigned short) * owner.size(), hipMemcpyHostToDevice));
-    if (n) BHIP_TRY(b, hipMemcpy(b->d_ctls, ctls.data(), sizeof(gpw::Ctl*) * n, hipMemcpyHostToDevice));
+        BHIP_TRY(b, hipMemcpyAsync(b->d_owner, h + o_owner, sizeof(unsigned short) * owner.size(),
+                                   hipMemcpyHostToDevice, s));
+    BHIP_TRY(b, hipMemcpyAsync(b->d_dir, h + o_dir, sizeof(gpw::BatchDir) * dirs.size(), hipMemcpyHostToDevice, s));
+    if (n) BHIP_TRY(b, hipMemcpyAsync(b->d_ctls, h + o_ctl, sizeof(gpw::Ctl*) * n, hipMemcpyHostToDevice, s));
+    BHIP_TRY(b, hipEventRecord(b->staging_done[slot], s));
+    b->staging_used[slot] = true;
+    b->set.assign(ctxs, ctxs + n);
+    b->groups = std::move(groups);
     b->last_stream = s;
     return GPWENO_OK;
 }
@@ -1023,22 +1212,23 @@ int gpweno_batch_run(gpweno_batch* b, int nsteps, void* stream) {
     if (nsteps < 1) return bfail(b, GPWENO_EINVAL, "nsteps must be >= 1");
     if (b->set.empty()) return GPWENO_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (!b->graph) {
-        BHIP_TRY(b, hipStreamBeginCapture(b->own_stream, hipStreamCaptureModeThreadLocal));
-        int st = batch_enqueue_step(b, b->own_stream);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(b->own_stream, &g);
-        if (st) {
-            if (g) (void)hipGraphDestroy(g);
-            return st;
+    if (b->last_stream && b->last_stream != s) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
+    if (!graph_serves(b)) {
+        // the captured step's kinds or grids no longer fit: capture anew with
+        // only the kinds the set has (the graph holds no table address but the
+        // fixed work-table entries, so a set change alone never needs this)
+        std::vector<BatchGroup> kept;
+        for (auto& g : b->groups)
+            if (!g.members.empty()) kept.push_back(g);
+        if (kept.size() != b->groups.size()) {
+            std::vector<gpweno_ctx*> set = b->set;
+            b->graph_groups.clear();
+            b->groups.clear();
+            int st = gpweno_batch_set(b, set.data(), (int)set.size(), stream);
+            if (st) return st;
         }
-        if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-        e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) {
-            b->graph = nullptr;
-            return bfail(b, GPWENO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-        }
+        int st = batch_capture(b);
+        if (st) return st;
     }
     for (int i = 0; i < nsteps; ++i) BHIP_TRY(b, hipGraphLaunch(b->graph, s));
     b->last_stream = s;
@@ -1063,6 +1253,8 @@ int gpweno_batch_status(gpweno_batch* b, double* t, double* dt, long* nsteps, in
     return GPWENO_OK;
 }
 
+long gpweno_batch_captures(const gpweno_batch* b) { return b ? (long)b->recaptures : -1; }
+
 void gpweno_batch_destroy(gpweno_batch* b) {
     if (!b) return;
     if (b->last_stream) (void)hipStreamSynchronize(b->last_stream);
@@ -1070,9 +1262,14 @@ void gpweno_batch_destroy(gpweno_batch* b) {
     batch_drop_graph(b);
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_owner) (void)hipFree(b->d_owner);
+    if (b->d_dir) (void)hipFree(b->d_dir);
     if (b->d_ctls) (void)hipFree(b->d_ctls);
     if (b->d_status) (void)hipFree(b->d_status);
     if (b->h_status) (void)hipHostFree(b->h_status);
+    for (int i = 0; i < STAGING; ++i) {
+        if (b->staging[i]) (void)hipHostFree(b->staging[i]);
+        if (b->staging_done[i]) (void)hipEventDestroy(b->staging_done[i]);
+    }
     if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
     delete b;
 }

@@ -138,10 +138,18 @@ struct ProbDesc {
     long long block0;   // its first logical block
 };
 
+// Work table of one batched launch (device memory, rewritten by the host with
+// stream-ordered copies when the set of problems changes).
+struct BatchDir {
+    const ProbDesc* probs;         // descriptors of the group's problems for this launch
+    const unsigned short* owner;   // problem index of every logical block
+    long long nblocks;             // logical blocks of the launch
+    long long pad;
+};
+
 template <typename Real>
 struct BatchArgs {
-    const ProbDesc* probs;
-    const unsigned short* owner;  // problem index of every logical block
+    const BatchDir* dir;   // the launch's work table
     int first;
     int stage;
     int step_start;

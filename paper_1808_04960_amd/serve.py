@@ -8,6 +8,12 @@ and per group of equal R (``gpweno_batch_run``, replayed from a captured graph).
 A problem that reaches its step count is copied back and its memory released,
 which lets the next waiting requests in while the others keep running.
 
+The batch's step graph is captured once per set of problem kinds: admitting or
+retiring a problem rewrites the batch's device work tables with stream-ordered
+copies, and a new problem's initial state is uploaded on a stream of its own,
+so neither waits for the batches in flight. The host waits once per tick, for
+the progress poll.
+
 Admission is first-in first-out: a request that does not fit blocks the ones
 behind it (no starvation of large problems). A request larger than the whole
 budget is rejected.
@@ -209,6 +215,7 @@ class GpuExecutor:
         self.precision = precision
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = torch.cuda.Stream(self.device)
+        self.upload = torch.cuda.Stream(self.device)
         self.batch = Batch(self.stream)
 
     def now(self):
@@ -227,8 +234,10 @@ class GpuExecutor:
 
         dx = req.grid.dx[0]
         s = Solver(req.grid, req.R, 12 * dx, 3 * dx, gamma=req.gamma, precision=self.precision,
-                   positivity_fallback=(req.kind == "quadrant"), U0=req.state(), device=self.device.index,
-                   stream=self.stream)
+                   positivity_fallback=(req.kind == "quadrant"), device=self.device.index, stream=self.stream)
+        # the initial state goes up on a stream of its own; the serving stream
+        # waits for it, the host does not wait for the batches in flight
+        s.set_state(req.state(), upload_stream=self.upload)
         s.set_end(1e30, req.steps)
         return s
 

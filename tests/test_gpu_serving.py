@@ -138,3 +138,45 @@ def test_poisson_stream_small():
     assert s["completed"] == 40 and s["failed"] == 0
     assert rep.peak_bytes <= 256 << 20
     assert s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_set_changes_reuse_the_captured_step_graph():
+    """Problems join and leave between batched runs: the set is rewritten into
+    the batch's device work tables by stream-ordered copies, the captured step
+    graph keeps serving it (one capture for one kind of problem), and every
+    problem's result is bitwise its solo result. A new kind (R = 3) adds one
+    capture."""
+    announce("set changes without recapture")
+    stream = torch.cuda.Stream()
+
+    def mk(n, limit, R=2):
+        g, U = inputs.isentropic_vortex_2d(n)
+        dx = g.dx[0]
+        s = gw.Solver(g, R, 12 * dx, 3 * dx, precision="fp32", U0=U, stream=stream)
+        s.set_end(1e30, limit)
+        return s, (g, U, R, limit)
+
+    a0, ia0 = mk(64, 5)
+    a1, ia1 = mk(80, 15)
+    a2, ia2 = mk(96, 10)
+    b = gw.Batch(stream)
+    b.set([a0, a1, a2])
+    b.run(5)
+    c0, ic0 = mk(72, 10)
+    b.set([a1, a2, c0])          # a0 finished and left, c0 joined
+    b.run(5)
+    b.set([a1, c0])              # a2 finished and left
+    b.run(5)
+    assert b.captures() == 1
+    d3, id3 = mk(64, 4, R=3)     # a new kind of problem
+    b.set([a1, c0, d3])
+    b.run(4)
+    assert b.captures() == 2
+    _, _, ns, err = b.status()
+    assert list(ns) == [15, 10, 4] and not err.any()
+    for s, (g, U, R, limit) in ((a0, ia0), (a1, ia1), (a2, ia2), (c0, ic0), (d3, id3)):
+        ref = gw.Solver(g, R, 12 * g.dx[0], 3 * g.dx[0], precision="fp32", U0=U)
+        ref.run(1e30, max_steps=limit)
+        assert s.time()[2] == limit
+        assert np.array_equal(s.get_state(), ref.get_state()), (g.n, R)
+    b.close()
