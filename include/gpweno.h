@@ -225,6 +225,28 @@ int gpweno_rhs(gpweno_ctx *ctx, const double *d_U, double *d_L);
  * d_U and d_L must not overlap. Errors: EINVAL. */
 int gpweno_rhs_dir(gpweno_ctx *ctx, int dir, const double *d_U, double *d_L, int accumulate);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): gpweno_step (dt_out
+ * NULL, enqueued) for a state the caller passes, d_state (device pointer, the
+ * layout of gpweno_bind, updated in place), with the two RK stage states and
+ * the direction accumulator in a scratch area the library holds in device
+ * memory instead of a bound workspace. It allocates nothing (no hipMalloc,
+ * hipFree or allocating library call). The CFL time step comes from d_state
+ * (its speed is reduced first, into the context's control block), and the
+ * context's time and step count advance as with gpweno_step; its bound state
+ * and workspace, if any, are not touched. The scratch is 64 MiB per device
+ * (GPWENO_NOALLOC_SCRATCH_BYTES): 2 + (ndim > 1) arrays of nv * ncells float64,
+ * each rounded up to 256 bytes, must fit, e.g. 2D grids up to about 699,000
+ * cells, 3D up to about 559,000; a larger grid returns EINVAL. Every call on a
+ * device shares that device's one scratch area and keeps the last call's
+ * contents (no part needs to start at zero): calls that overlap on one device
+ * (other streams, other threads) race. The context must have been created on
+ * the device the call runs on. Errors: EINVAL (NULL or misaligned state,
+ * grid too large), EHIP (the scratch address could not be taken at
+ * gpweno_init). */
+#define GPWENO_NOALLOC_SCRATCH_BYTES (64u << 20)
+int gpweno_step_noalloc(gpweno_ctx *ctx, double *d_state, double t_final);
+
 /* Blocking: float64 sums over all cells of each conserved field of the bound
  * state, written to host out[nv], by a deterministic device reduction. */
 int gpweno_conserved_sums(gpweno_ctx *ctx, double *out);

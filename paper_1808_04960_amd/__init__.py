@@ -76,6 +76,7 @@ def lib():
         L.gpweno_compute_table_residual.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                                     _dp]
         L.gpweno_debug_poison.argtypes = [vp, ctypes.c_long]
+        L.gpweno_step_noalloc.argtypes = [vp, vp, ctypes.c_double]
         L.gpweno_rhs.argtypes = [vp, vp, vp]
         L.gpweno_rhs_dir.argtypes = [vp, ctypes.c_int, vp, vp, ctypes.c_int]
         L.gpweno_step_kernel.argtypes = [vp, ctypes.c_int]
@@ -277,6 +278,16 @@ class Solver:
         dt = ctypes.c_double()
         _check(lib().gpweno_step(self._ctx, t_final, ctypes.byref(dt)), self._ctx)
         return dt.value
+
+    def step_noalloc(self, t_final, state=None):
+        """One step (enqueued) of `state` (a float64 device tensor of this
+        problem's shape; default: this solver's own state) through the entry
+        point that allocates nothing: stage states and accumulator in the
+        library's fixed device scratch instead of this solver's workspace."""
+        st = self.state if state is None else state
+        if tuple(st.shape) != self.shape or st.dtype != self._torch.float64 or not st.is_contiguous():
+            raise GpwenoError(EINVAL, "state must be a contiguous float64 tensor of the problem's shape")
+        _check(lib().gpweno_step_noalloc(self._ctx, ctypes.c_void_p(st.data_ptr()), t_final), self._ctx)
 
     def set_end(self, t_final, step_limit=-1):
         """End time and absolute step limit honoured by batched execution (enqueued)."""

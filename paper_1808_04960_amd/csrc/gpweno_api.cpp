@@ -87,9 +87,38 @@ void ctl_release(int device, gpw::Ctl* d, gpw::Ctl* h) {
     g_pools[device].host.push_back(h);
 }
 
+// Scratch of gpweno_step_noalloc, the entry point for callers that cannot
+// allocate: the two RK stage states and the direction accumulator of one step,
+// in a fixed device array that every GPU the library runs on holds until the
+// process ends. Host code reaches it only through the per-device address
+// hipGetSymbolAddress returns (taken once per device in gpweno_init_scheme,
+// with that device current); the array's name is not a device address on the
+// host.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
 
 }  // namespace
 
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::once_flag g_scratch_once[NOALLOC_MAX_DEVICES];
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+hipError_t g_scratch_err[NOALLOC_MAX_DEVICES] = {};
+
+// Once per device, with that device current.
+void scratch_setup(int dev) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return;
+    std::call_once(g_scratch_once[dev], [dev] {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_err[dev] = e;
+        g_scratch_ptr[dev] = e == hipSuccess ? p : nullptr;
+    });
+}
+
+}  // namespace
 
 struct gpweno_ctx {
     gpweno_grid grid;
@@ -500,6 +529,7 @@ int gpweno_init_scheme(const gpweno_grid* grid, int scheme, int R, double ell, d
     c->opt.nonzero_mean = 0;
     c->opt.flux_corr_terms = 2;
     hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) scratch_setup(c->device);
     if (e == hipSuccess) e = ctl_acquire(c->device, &c->d_ctl, &c->h_ctl);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMemsetAsync(c->d_ctl, 0, sizeof(gpw::Ctl), c->own_stream);
@@ -729,6 +759,42 @@ int gpweno_conserved_sums(gpweno_ctx* c, double* out) {
     int st = read_ctl(c, s);
     if (st) return st;
     for (int k = 0; k < c->nv; ++k) out[k] = c->h_ctl->sums[k];
+    return GPWENO_OK;
+}
+
+int gpweno_step_noalloc(gpweno_ctx* c, double* d_state, double t_final) {
+    if (!c) return fail(nullptr, GPWENO_EINVAL, "NULL context");
+    if (!d_state || ((uintptr_t)d_state & 7)) return fail(c, GPWENO_EINVAL, "state must be non-NULL and 8-byte aligned");
+    const size_t st = align256(sizeof(double) * (size_t)c->nv * (size_t)c->ncell);
+    const size_t need = 2 * st + (c->grid.ndim > 1 ? st : 0);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        return fail(c, GPWENO_EINVAL, "this grid needs %zu bytes of step scratch; the library holds %zu per device",
+                    need, NOALLOC_SCRATCH_BYTES);
+    if (c->device < 0 || c->device >= NOALLOC_MAX_DEVICES || !g_scratch_ptr[c->device])
+        return fail(c, GPWENO_EHIP, "step scratch address of device %d unavailable: %s", c->device,
+                    c->device >= 0 && c->device < NOALLOC_MAX_DEVICES ? hipGetErrorString(g_scratch_err[c->device])
+                                                                      : "device index out of range");
+    char* w = static_cast<char*>(g_scratch_ptr[c->device]);
+    double* U1 = reinterpret_cast<double*>(w);
+    double* U2 = reinterpret_cast<double*>(w + st);
+    double* dU = c->grid.ndim > 1 ? reinterpret_cast<double*>(w + 2 * st) : nullptr;
+    hipStream_t s = user_stream(c);
+    hipError_t e = gpw::launch_step_prep(c->d_ctl, c->opt.cfl, c->opt.fixed_dt, t_final, s);
+    if (e != hipSuccess) return fail(c, GPWENO_EHIP, "step prep launch: %s", hipGetErrorString(e));
+    const double ix[3] = {1.0 / c->dx[0], c->grid.ndim > 1 ? 1.0 / c->dx[1] : 0.0,
+                          c->grid.ndim > 2 ? 1.0 / c->dx[2] : 0.0};
+    e = gpw::launch_speed(c->grid.ndim, d_state, c->ncell, ix, c->gamma, c->d_ctl, s);
+    if (e != hipSuccess) return fail(c, GPWENO_EHIP, "speed launch: %s", hipGetErrorString(e));
+    c->shadow_ok = false;
+    const int ndim = c->grid.ndim;
+    const double* ins[3] = {d_state, U1, U2};
+    double* outs[3] = {U1, U2, d_state};
+    for (int k = 0; k < 3 * ndim; ++k) {
+        const int stage = k / ndim + 1, j = k % ndim;
+        int st2 = launch(c, sweep_dir(ndim, j), ins[stage - 1], d_state, dU, outs[stage - 1], stage, j == ndim - 1,
+                         j == 0, k == 0, s);
+        if (st2) return st2;
+    }
     return GPWENO_OK;
 }
 

@@ -198,5 +198,9 @@ hipError_t launch_speed(int ndim, const double* U, long long ncell, const double
 hipError_t launch_sums(int nv, const double* U, long long ncell, double* partials, int npart, Ctl* ctl,
                        hipStream_t s);
 hipError_t launch_poison(double* U, int nv, long long ncell, long long cell, hipStream_t s);
+// Prepares one step of a state the context is not bound to: sets the time-step
+// rule and the end of the run (no step limit) and clears the CFL-speed slots of
+// the current step, for launch_speed to fill from that state.
+hipError_t launch_step_prep(Ctl* ctl, double cfl, double fixed_dt, double t_final, hipStream_t s);
 
 }  // namespace gpw

@@ -89,6 +89,16 @@ __global__ void __launch_bounds__(256) speed_kernel(const double* __restrict__ U
     }
 }
 
+__global__ void step_prep_kernel(Ctl* c, double cfl, double fixed_dt, double t_final) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const long long n = c->rec[0].nsteps > c->rec[1].nsteps ? c->rec[0].nsteps : c->rec[1].nsteps;
+    c->cfl = cfl;
+    c->fixed_dt = fixed_dt;
+    c->t_final = t_final;
+    c->step_limit = LLONG_MAX;
+    for (int x = 0; x < 8; ++x) c->xcd[x].speed[n & 1] = 0ull;
+}
+
 // Test hook: density and total energy of one cell set to -1.
 __global__ void poison_kernel(double* U, int nv, long long ncell, long long cell) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -188,6 +198,11 @@ hipError_t launch_speed(int ndim, const double* U, long long ncell, const double
         case 3: hipLaunchKernelGGL(speed_kernel<3>, g, b, 0, s, U, ncell, inv_dx[0], inv_dx[1], inv_dx[2], gamma, ctl); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_prep(Ctl* ctl, double cfl, double fixed_dt, double t_final, hipStream_t s) {
+    hipLaunchKernelGGL(step_prep_kernel, dim3(1), dim3(64), 0, s, ctl, cfl, fixed_dt, t_final);
     return hipGetLastError();
 }
 
