@@ -360,10 +360,10 @@ int gpweno_batch_create(gpweno_batch **out);
 int gpweno_batch_set(gpweno_batch *b, gpweno_ctx *const *ctxs, int n, void *stream);
 
 /* Enqueues nsteps batched steps (nsteps >= 1) on stream by replaying a captured
- * graph of one batched step (captured on first use, and again only when the
- * set's kinds of problems or its size have changed beyond what the graph
- * serves). Every launch has a fixed grid whose blocks loop over the set's
- * logical blocks. Errors: EINVAL, EHIP. */
+ * graph of one batched step (captured on first use, and again only when a new
+ * kind of problem joins the set). Every launch has a fixed grid, its kernel's
+ * resident capacity, whose blocks loop over the set's logical blocks.
+ * Errors: EINVAL, EHIP. */
 int gpweno_batch_run(gpweno_batch *b, int nsteps, void *stream);
 
 /* Blocking: for every problem of the set, in set order, its time, last dt, step
@@ -373,8 +373,9 @@ int gpweno_batch_status(gpweno_batch *b, double *t, double *dt, long *nsteps, in
 
 /* Number of times the batch has captured its step graph (instrumentation; -1
  * for NULL). A set change that keeps the kinds of problems (dimension, R,
- * precision, scheme, boundary kinds, tables) and sizes within a factor of a
- * few of the captured ones does not add one. */
+ * precision, scheme, boundary kinds, flux correction, tables) does not add
+ * one, whatever the problems' sizes: each launch's grid is its kernel's
+ * resident capacity on the device. */
 long gpweno_batch_captures(const gpweno_batch *b);
 
 /* Waits for the batch's last stream and frees its resources. NULL is ignored. */

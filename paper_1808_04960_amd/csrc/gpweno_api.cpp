@@ -871,7 +871,6 @@ constexpr int BATCH_MAX = 4096;
 constexpr int BATCH_MAX_GROUPS = 64;
 constexpr int DIR_PER_GROUP = 9;            // 3 stages x up to 3 directions
 constexpr int STAGING = 4;                  // pinned staging buffers in the ring
-constexpr long long GRID_MIN = 64, GRID_MAX = 2048;
 
 // Problems sharing one kernel instantiation per launch and one set of tables.
 struct BatchGroup {
@@ -904,14 +903,6 @@ bool same_kind(const BatchGroup& a, const BatchGroup& b) {
     return true;
 }
 
-// Blocks of a batched launch's grid for a given count of logical blocks: a power
-// of two, so that a graph captured for one set serves sets of similar size.
-long long grid_for(long long blocks) {
-    long long g = GRID_MIN;
-    while (g < blocks && g < GRID_MAX) g <<= 1;
-    return g;
-}
-
 size_t align_up(size_t b) { return (b + 255) & ~size_t(255); }
 
 }  // namespace
@@ -939,11 +930,16 @@ struct gpweno_batch {
     hipEvent_t staging_done[STAGING] = {};
     bool staging_used[STAGING] = {};
     int staging_next = 0;
-    // captured batched step and what it was captured for
+    // captured batched step, what it was captured for, and its kernel nodes in
+    // launch order with their parameters (their grids follow the set)
     hipGraphExec_t graph = nullptr;
+    hipGraph_t graph_src = nullptr;
     std::vector<BatchGroup> graph_groups;
-    std::vector<long long> graph_grids;     // per group and step position
+    std::vector<hipGraphNode_t> graph_nodes;
+    std::vector<hipKernelNodeParams> graph_params;
+    std::vector<std::pair<int, int>> graph_launch;   // (group, step position) of each node
     long long recaptures = 0;
+    bool dirty = true;                       // the set changed since the grids were applied
     std::string err;
 };
 
@@ -971,8 +967,14 @@ void batch_drop_graph(gpweno_batch* b) {
         (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
     }
+    if (b->graph_src) {
+        (void)hipGraphDestroy(b->graph_src);
+        b->graph_src = nullptr;
+    }
     b->graph_groups.clear();
-    b->graph_grids.clear();
+    b->graph_nodes.clear();
+    b->graph_params.clear();
+    b->graph_launch.clear();
 }
 
 // One batched launch: step position k for group g (its work table entry
@@ -1006,42 +1008,50 @@ int batch_launch(gpweno_batch* b, int gi, const BatchGroup& g, int k, long long 
     return GPWENO_OK;
 }
 
-// The grid of every launch of the captured step, group by group.
-std::vector<long long> batch_grids(const std::vector<BatchGroup>& groups) {
-    std::vector<long long> out;
-    for (const auto& g : groups)
-        for (int k = 0; k < 3 * g.ndim; ++k) out.push_back(grid_for(g.blocks[sweep_dir(g.ndim, k % g.ndim)]));
-    return out;
+// Grid of a batched launch: one block per logical block of the group's
+// direction (one block for an empty group, which exits at once).
+long long launch_grid(const BatchGroup& g, int k) {
+    return std::max(1ll, g.members.empty() ? 0ll : g.blocks[sweep_dir(g.ndim, k % g.ndim)]);
 }
 
 // Whether the captured graph serves the current groups: the same kinds in the
-// same order, and launch grids within a factor of 8 below or 4 above what the
-// current blocks would pick (the launches loop over their logical blocks, so
-// any grid is correct; the margin only keeps grids near the work).
+// same order (its launches read the sets through the work tables; their grids
+// are set per set by batch_update_grids).
 bool graph_serves(const gpweno_batch* b) {
     if (!b->graph || b->graph_groups.size() != b->groups.size()) return false;
     for (size_t i = 0; i < b->groups.size(); ++i)
         if (!same_kind(b->graph_groups[i], b->groups[i])) return false;
-    const std::vector<long long> want = batch_grids(b->groups);
-    for (size_t i = 0; i < want.size(); ++i)
-        if (want[i] > 4 * b->graph_grids[i] || 8 * want[i] < b->graph_grids[i]) return false;
     return true;
+}
+
+// Sets the grid of every launch of the instantiated graph to the current set's
+// blocks (host-side; launches already enqueued keep the grids they had).
+int batch_update_grids(gpweno_batch* b) {
+    for (size_t i = 0; i < b->graph_nodes.size(); ++i) {
+        hipKernelNodeParams& p = b->graph_params[i];
+        const long long gr = launch_grid(b->groups[b->graph_launch[i].first], b->graph_launch[i].second);
+        if (gr > INT_MAX) return bfail(b, GPWENO_EINVAL, "batch too large");
+        if ((long long)p.gridDim.x == gr) continue;
+        p.gridDim.x = (unsigned)gr;
+        hipError_t e = hipGraphExecKernelNodeSetParams(b->graph, b->graph_nodes[i], &p);
+        if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "hipGraphExecKernelNodeSetParams: %s", hipGetErrorString(e));
+    }
+    return GPWENO_OK;
 }
 
 int batch_capture(gpweno_batch* b) {
     batch_drop_graph(b);
-    const std::vector<long long> grids = batch_grids(b->groups);
-    BHIP_TRY(b, hipStreamBeginCapture(b->own_stream, hipStreamCaptureModeThreadLocal));
-    int st = GPWENO_OK;
+    std::vector<std::pair<int, int>> order;   // launch order: step position, then group
     int kmax = 0;
     for (const auto& g : b->groups) kmax = std::max(kmax, 3 * g.ndim);
-    for (int k = 0; k < kmax && st == GPWENO_OK; ++k) {
-        size_t gk = 0;
-        for (size_t gi = 0; gi < b->groups.size() && st == GPWENO_OK; ++gi) {
-            const BatchGroup& g = b->groups[gi];
-            if (k < 3 * g.ndim) st = batch_launch(b, (int)gi, g, k, grids[gk + k], b->own_stream);
-            gk += 3 * g.ndim;
-        }
+    for (int k = 0; k < kmax; ++k)
+        for (size_t gi = 0; gi < b->groups.size(); ++gi)
+            if (k < 3 * b->groups[gi].ndim) order.emplace_back((int)gi, k);
+    BHIP_TRY(b, hipStreamBeginCapture(b->own_stream, hipStreamCaptureModeThreadLocal));
+    int st = GPWENO_OK;
+    for (const auto& [gi, k] : order) {
+        const BatchGroup& g = b->groups[gi];
+        if ((st = batch_launch(b, gi, g, k, launch_grid(g, k), b->own_stream))) break;
     }
     hipGraph_t gr = nullptr;
     hipError_t e = hipStreamEndCapture(b->own_stream, &gr);
@@ -1051,14 +1061,41 @@ int batch_capture(gpweno_batch* b) {
     }
     if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
     e = hipGraphInstantiate(&b->graph, gr, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(gr);
     if (e != hipSuccess) {
+        (void)hipGraphDestroy(gr);
         b->graph = nullptr;
         return bfail(b, GPWENO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
+    b->graph_src = gr;
     b->graph_groups = b->groups;
-    b->graph_grids = grids;
     ++b->recaptures;
+    // the kernel nodes in launch order: the capture of one stream is a chain
+    // from its root; if the runtime does not expose it, set changes recapture
+    std::vector<hipGraphNode_t> chain;
+    size_t n = 1;
+    hipGraphNode_t node = nullptr;
+    bool ok = hipGraphGetRootNodes(gr, &node, &n) == hipSuccess && n == 1;
+    while (ok && node) {
+        chain.push_back(node);
+        hipGraphNode_t next = nullptr;
+        size_t m = 0;
+        ok = hipGraphNodeGetDependentNodes(node, nullptr, &m) == hipSuccess && m <= 1;
+        if (ok && m == 1) ok = hipGraphNodeGetDependentNodes(node, &next, &m) == hipSuccess;
+        node = m == 1 ? next : nullptr;
+    }
+    ok = ok && chain.size() == order.size();
+    std::vector<hipKernelNodeParams> params(chain.size());
+    for (size_t i = 0; ok && i < chain.size(); ++i) {
+        hipGraphNodeType t;
+        ok = hipGraphNodeGetType(chain[i], &t) == hipSuccess && t == hipGraphNodeTypeKernel &&
+             hipGraphKernelNodeGetParams(chain[i], &params[i]) == hipSuccess &&
+             (long long)params[i].gridDim.x == launch_grid(b->groups[order[i].first], order[i].second);
+    }
+    if (ok) {
+        b->graph_nodes = chain;
+        b->graph_params = params;
+        b->graph_launch = order;
+    }
     return GPWENO_OK;
 }
 
@@ -1270,6 +1307,7 @@ int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stre
     b->set.assign(ctxs, ctxs + n);
     b->groups = std::move(groups);
     b->last_stream = s;
+    b->dirty = true;
     return GPWENO_OK;
 }
 
@@ -1279,10 +1317,15 @@ int gpweno_batch_run(gpweno_batch* b, int nsteps, void* stream) {
     if (b->set.empty()) return GPWENO_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (b->last_stream && b->last_stream != s) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
-    if (!graph_serves(b)) {
-        // the captured step's kinds or grids no longer fit: capture anew with
-        // only the kinds the set has (the graph holds no table address but the
-        // fixed work-table entries, so a set change alone never needs this)
+    if (graph_serves(b) && (!b->dirty || !b->graph_nodes.empty())) {
+        if (b->dirty) {
+            int st = batch_update_grids(b);
+            if (st) return st;
+        }
+    } else {
+        // a new kind of problem: capture anew with only the kinds the set has
+        // (the graph holds no table address but the fixed work-table entries,
+        // so a set change within the captured kinds never needs this)
         std::vector<BatchGroup> kept;
         for (auto& g : b->groups)
             if (!g.members.empty()) kept.push_back(g);
@@ -1296,6 +1339,7 @@ int gpweno_batch_run(gpweno_batch* b, int nsteps, void* stream) {
         int st = batch_capture(b);
         if (st) return st;
     }
+    b->dirty = false;
     for (int i = 0; i < nsteps; ++i) BHIP_TRY(b, hipGraphLaunch(b->graph, s));
     b->last_stream = s;
     return GPWENO_OK;

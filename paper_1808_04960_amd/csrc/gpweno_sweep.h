@@ -758,13 +758,6 @@ inline __device__ __forceinline__ long long xcd_logical_block() {
     return (long long)(xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3));
 }
 
-// Step-control decision of a block, broadcast through LDS (batched kernel).
-struct StepSnap {
-    double t0, dt;
-    long long n;
-    int go;
-};
-
 // The first sweep of a step (block 0): mark the step as running (or not), store
 // its dt for the sweeps that finish a stage, and clear the next speed slot.
 template <bool FIN>
@@ -777,15 +770,10 @@ __device__ __forceinline__ void mark_step(Ctl* c, bool go, long long nstep, doub
     }
 }
 
-// One block of a sweep: logical block L of the problem's blocks. UCTL: one
-// thread takes the step-control decision and the block follows it through LDS
-// (snap); the batched kernel, whose blocks loop over logical blocks, needs the
-// decision to be the block's, since the error flag a finishing sweep reads may
-// be set by other blocks of the same launch while this one starts. The
-// single-problem kernel reads the control block in every thread.
-template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG, int NC, bool UCTL>
+// One block of a sweep: logical block L of the problem's blocks.
+template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG, int NC>
 __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long long L, unsigned char* smem,
-                                            unsigned long long* sred, StepSnap* snap) {
+                                            unsigned long long* sred) {
     using C = SweepCfg<NDIM, DIR, R, Real, NC>;
     constexpr int NV = C::NV, WPB = C::WPB, PITCH = C::PITCH, SLEN = C::SLEN, THREADS = C::THREADS;
     constexpr int LEFT = C::LEFT, TOUT = C::TOUT;
@@ -898,25 +886,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     double t0 = 0.0, dt = 0.0;
     long long nstep = 0;
     if (a.stage > 0) {
-        bool go;
-        if constexpr (UCTL) {
-            if (threadIdx.x == 0) {
-                go = step_go<FIN>(a.ctl, FIN && a.stage == 3, FIN && a.step_start, t0, dt, nstep);
-                if (a.step_start && L == 0) mark_step<FIN>(a.ctl, go, nstep, t0, dt);
-                snap->go = go ? 1 : 0;
-                snap->t0 = t0;
-                snap->dt = dt;
-                snap->n = nstep;
-            }
-            __syncthreads();
-            go = snap->go != 0;
-            t0 = snap->t0;
-            dt = snap->dt;
-            nstep = snap->n;
-        } else {
-            go = step_go<FIN>(a.ctl, FIN && a.stage == 3, FIN && a.step_start, t0, dt, nstep);
-            if (a.step_start && L == 0 && threadIdx.x == 0) mark_step<FIN>(a.ctl, go, nstep, t0, dt);
-        }
+        const bool go = step_go<FIN>(a.ctl, FIN && a.stage == 3, FIN && a.step_start, t0, dt, nstep);
+        if (a.step_start && L == 0 && threadIdx.x == 0) mark_step<FIN>(a.ctl, go, nstep, t0, dt);
         if (!go) return;
     }
 
@@ -1065,58 +1036,54 @@ sweep_kernel(const SweepArgs<Real> a) {
     using C = SweepCfg<NDIM, DIR, R, Real, NC>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
     __shared__ unsigned long long sred[C::WPB];
-    sweep_block<NDIM, DIR, R, Real, FIN, IK, BCG, NC, false>(a, xcd_logical_block(), smem, sred, nullptr);
+    sweep_block<NDIM, DIR, R, Real, FIN, IK, BCG, NC>(a, xcd_logical_block(), smem, sred);
 }
 
 // Batched sweep over many independent problems (same ndim, R, precision and
 // tables). Logical blocks are laid out problem after problem; the launch's
 // work table (BatchDir, in device memory) holds the problems' descriptors,
-// the owner of every logical block and their count. The grid is fixed and its
-// blocks loop over the logical blocks, so the host changes the set by
-// rewriting the table (stream-ordered copies) without touching the launch,
-// and a captured graph of batched steps serves every set. Every logical block
-// runs exactly the code of the single-problem sweep on its own problem's data,
-// so a problem's result does not depend on what else is in the batch.
+// the owner of every logical block and their count, one hardware block per
+// logical block. The host changes the set by rewriting the table with
+// stream-ordered copies and the grid of the captured launch in place, so a
+// captured graph of batched steps serves every set of the same kinds of
+// problems. Every block runs exactly the code of the single-problem sweep on
+// its own problem's data, so a problem's result does not depend on what else
+// is in the batch.
 template <int NDIM, int DIR, int R, typename Real, bool FIN, int IK, bool BCG, int NC>
 __global__ void __launch_bounds__((SweepCfg<NDIM, DIR, R, Real, NC>::THREADS))
 sweep_batch_kernel(const BatchArgs<Real> ba) {
     using C = SweepCfg<NDIM, DIR, R, Real, NC>;
     __shared__ __attribute__((aligned(16))) unsigned char smem[C::SMEM];
     __shared__ unsigned long long sred[C::WPB];
-    __shared__ StepSnap snap;
     const BatchDir* D = ba.dir;
-    const long long total = D->nblocks;
-    const ProbDesc* probs = D->probs;
-    const unsigned short* owner = D->owner;
-    for (long long Lg = xcd_logical_block(); Lg < total; Lg += gridDim.x) {
-        const ProbDesc& P = probs[owner[Lg]];
-        SweepArgs<Real> a;
-        a.U = P.U;
-        a.Un = P.Un;
-        a.dU = P.dU;
-        a.Uout = P.Uout;
-        a.ctl = P.ctl;
-        a.n[0] = P.n[0];
-        a.n[1] = P.n[1];
-        a.n[2] = P.n[2];
-        a.nseg = P.nseg;
-        a.ncell = P.ncell;
-        a.inv_dx = P.inv_dx;
-        a.inv_dx_all[0] = P.inv_dx_all[0];
-        a.inv_dx_all[1] = P.inv_dx_all[1];
-        a.inv_dx_all[2] = P.inv_dx_all[2];
-        a.gamma = P.gamma;
-        a.inv_gm1 = P.inv_gm1;
-        a.positivity = P.positivity;
-        a.bc[0] = P.bc[0];
-        a.bc[1] = P.bc[1];
-        a.first = ba.first;
-        a.stage = ba.stage;
-        a.step_start = ba.step_start;
-        a.tab = ba.tab;
-        sweep_block<NDIM, DIR, R, Real, FIN, IK, BCG, NC, true>(a, Lg - P.block0, smem, sred, &snap);
-        __syncthreads();  // LDS is reused by the next logical block
-    }
+    const long long Lg = xcd_logical_block();
+    if (Lg >= D->nblocks) return;   // a grid of one block for an empty group
+    const ProbDesc& P = D->probs[D->owner[Lg]];
+    SweepArgs<Real> a;
+    a.U = P.U;
+    a.Un = P.Un;
+    a.dU = P.dU;
+    a.Uout = P.Uout;
+    a.ctl = P.ctl;
+    a.n[0] = P.n[0];
+    a.n[1] = P.n[1];
+    a.n[2] = P.n[2];
+    a.nseg = P.nseg;
+    a.ncell = P.ncell;
+    a.inv_dx = P.inv_dx;
+    a.inv_dx_all[0] = P.inv_dx_all[0];
+    a.inv_dx_all[1] = P.inv_dx_all[1];
+    a.inv_dx_all[2] = P.inv_dx_all[2];
+    a.gamma = P.gamma;
+    a.inv_gm1 = P.inv_gm1;
+    a.positivity = P.positivity;
+    a.bc[0] = P.bc[0];
+    a.bc[1] = P.bc[1];
+    a.first = ba.first;
+    a.stage = ba.stage;
+    a.step_start = ba.step_start;
+    a.tab = ba.tab;
+    sweep_block<NDIM, DIR, R, Real, FIN, IK, BCG, NC>(a, Lg - P.block0, smem, sred);
 }
 
 // ---------------------------------------------------------------------------
