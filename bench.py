@@ -461,6 +461,141 @@ def full_length_accuracy(name, W, grid, U0, solvers, run_c3_oracle):
     return out
 
 
+# ---------------------------------------------------------------------------
+# Summaries of rocprofv3 output (profiles/)
+# ---------------------------------------------------------------------------
+PROFILE_TAGS = {(2, 2): "vortex2d_512_R2", (2, 3): "kh2d_2048x1024_R3", (3, 2): "wave3d_256_R2",
+                (1, 2): "sine1d_128_R2"}
+COPY_BYTES = 1 << 30   # the --copy-probe copy
+
+
+def _short_name(name):
+    name = name.strip('"')
+    if name.startswith("void "):
+        name = name[5:]
+    name = name.split("(")[0]
+    return name[name.index("sweep_kernel"):] if "sweep_kernel" in name else name
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _counters(raw):
+    """Mean over dispatches of every counter, per kernel, from run_counter_collection.csv."""
+    sums, counts = {}, {}
+    for row in _read_csv(raw):
+        k = (_short_name(row["Kernel_Name"]), row["Counter_Name"])
+        sums[k] = sums.get(k, 0.0) + float(row["Counter_Value"])
+        counts[k] = counts.get(k, 0) + 1
+    out = {}
+    for (kern, ctr), v in sums.items():
+        out.setdefault(kern, {})[ctr] = v / counts[(kern, ctr)]
+    return out
+
+
+def _copy_calibration(raw, counter):
+    """Value of the counter for the --copy-probe copy (the largest copyBuffer dispatch)."""
+    vals = [float(r["Counter_Value"]) for r in _read_csv(raw)
+            if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    return max(vals) if vals else None
+
+
+def summarize_profiles(raw_dir, out_dir, command):
+    """Writes profiles/ summaries from the rocprofv3 passes in raw_dir
+    (prof_stats: --kernel-trace --stats; prof_fetch / prof_write: --pmc FETCH_SIZE /
+    WRITE_SIZE; prof_busy, prof_mixf, prof_mixo: the SQ counter sets)."""
+    sha = kernel_source_hash()
+    stats = {}
+    for row in _read_csv(os.path.join(raw_dir, "prof_stats", "run_kernel_stats.csv")):
+        n = _short_name(row["Name"])
+        if n.startswith("sweep_kernel"):
+            stats[n] = (int(row["Calls"]), float(row["AverageNs"]) / 1e3, float(row["MinNs"]) / 1e3,
+                        float(row["MaxNs"]) / 1e3, float(row["TotalDurationNs"]) / 1e6)
+    ctr = {}
+    for pas in ("fetch", "write", "busy", "mixf", "mixo"):
+        path = os.path.join(raw_dir, f"prof_{pas}", "run_counter_collection.csv")
+        if os.path.exists(path):
+            for k, v in _counters(path).items():
+                ctr.setdefault(k, {}).update(v)
+    fetch_cal = _copy_calibration(os.path.join(raw_dir, "prof_fetch", "run_counter_collection.csv"), "FETCH_SIZE")
+    write_cal = _copy_calibration(os.path.join(raw_dir, "prof_write", "run_counter_collection.csv"), "WRITE_SIZE")
+    f_scale = COPY_BYTES / (fetch_cal * 1024) if fetch_cal else None
+    w_scale = COPY_BYTES / (write_cal * 1024) if write_cal else None
+
+    def targs(kern):
+        return kern[kern.index("<") + 1:kern.rindex(">")].split(", ")
+
+    by_tag = {}
+    for kern in stats:
+        a = targs(kern)
+        by_tag.setdefault(PROFILE_TAGS.get((int(a[0]), int(a[2])), "other"), []).append(kern)
+    head = (f"# command (one MI355X, repository root, TMPDIR=/tmp):\n"
+            f"#   rocprofv3 <pass> -d <dir> -o run --output-format csv -- python3 bench.py {command}\n"
+            f"#   passes: --kernel-trace --stats | --pmc FETCH_SIZE | --pmc WRITE_SIZE |\n"
+            f"#     --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES "
+            f"SQ_WAVE_CYCLES GRBM_GUI_ACTIVE |\n"
+            f"#     --pmc SQ_INSTS_VALU_{{ADD,MUL,FMA,TRANS}}_{{F32,F64}} |\n"
+            f"#     --pmc SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_INT64 SQ_INSTS_VALU_CVT SQ_INSTS_VALU_FLOPS_FP32 "
+            f"SQ_INSTS_VALU_FLOPS_FP64 SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_LDS_BANK_CONFLICT\n"
+            f"#   summarised by: python3 bench.py --summarize-profiles <dir>\n"
+            f"# device sources sha256[:16] = {sha} (bench.kernel_source_hash)\n")
+    traffic_lines, busy_lines = [], []
+    for tag, kerns in sorted(by_tag.items()):
+        kerns.sort(key=lambda k: -stats[k][4])
+        with open(os.path.join(out_dir, f"kernel_stats_{tag}.txt"), "w") as fh:
+            fh.write(f"# rocprofv3 kernel statistics: GP-WENO sweeps, {tag}\n#\n" + head)
+            fh.write("# The run holds fp32 and fp64 solvers: the timed graph-replayed steps and the back-to-back\n"
+                     "# launches of every kernel of the step sequence (bench's HIP-event timing). sweep_kernel<ndim,\n"
+                     "# dir, R, Real, finishes-an-RK-stage, indicator kind, general boundaries, flux-correction\n"
+                     "# terms>; the sweeps of a stage run z, y, x and the x sweep finishes it.\n#\n")
+            fh.write(f"{'kernel':62s} {'calls':>6s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} "
+                     f"{'total_ms':>9s}\n")
+            for k in kerns:
+                c, av, mn, mx, tot = stats[k]
+                fh.write(f"{k:62s} {c:6d} {av:9.2f} {mn:9.2f} {mx:9.2f} {tot:9.3f}\n")
+        with open(os.path.join(out_dir, f"counters_{tag}.txt"), "w") as fh:
+            fh.write(f"# rocprofv3 --pmc counters per dispatch (mean over dispatches), {tag}\n#\n" + head)
+            fh.write(f"# calibration: a 1 GiB device copy (__amd_rocclr_copyBuffer) reads FETCH_SIZE {fetch_cal} KiB "
+                     f"and WRITE_SIZE {write_cal} KiB per dispatch,\n# so FETCH_SIZE is scaled by "
+                     f"{f_scale:.3f} and WRITE_SIZE by {w_scale:.3f}.\n"
+                     "# derived: hbm_bytes = calibrated fetch + write; valu_busy = SQ_INSTS_VALU x 4 cycles /\n"
+                     "# (1024 SIMDs x avg duration x 2.4 GHz); flops_per_lane_instr = (FLOPS_FP32 + FLOPS_FP64) /\n"
+                     "# (64 SQ_INSTS_VALU); the instruction classes are wave-level counts.\n#\n")
+            for k in kerns:
+                cv = ctr.get(k, {})
+                av_us = stats[k][1]
+                fh.write(f"{k}\n")
+                for name in sorted(cv):
+                    fh.write(f"    {name:32s} {cv[name]:18.1f}\n")
+                fb = cv.get("FETCH_SIZE", 0.0) * 1024 * (f_scale or 0)
+                wb = cv.get("WRITE_SIZE", 0.0) * 1024 * (w_scale or 0)
+                vi = cv.get("SQ_INSTS_VALU")
+                busy = vi * 4 / (1024 * av_us * 1e-6 * 2.4e9) if vi else None
+                flops = cv.get("SQ_INSTS_VALU_FLOPS_FP32", 0.0) + cv.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0)
+                fh.write(f"    {'hbm_bytes':32s} {fb + wb:18.1f}   ({(fb + wb) / (av_us * 1e-6) / 1e9:.0f} GB/s "
+                         f"at {av_us:.2f} us)\n")
+                if busy is not None:
+                    fh.write(f"    {'valu_busy':32s} {busy:18.3f}\n")
+                    fh.write(f"    {'flops_per_lane_instr':32s} {flops / (64 * vi):18.3f}\n")
+                    busy_lines.append(f"{k.replace(' ', '')} {sha} {busy:.4f} {tag}")
+                if fb:
+                    traffic_lines.append(f"{k.replace(' ', '')} {sha} {fb:.0f} {wb:.0f} {tag}")
+    with open(os.path.join(out_dir, "traffic.txt"), "w") as fh:
+        fh.write("# HBM traffic per launch of each sweep kernel, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE\n"
+                 "# (see counters_<workload>.txt for the commands and the copy-kernel calibration).\n"
+                 "# columns: kernel  kernel-source-sha256[:16]  bytes-fetched  bytes-written  workload\n"
+                 "# bench.py reports these only while the kernel source still has the listed hash.\n")
+        fh.write("\n".join(sorted(traffic_lines)) + "\n")
+    with open(os.path.join(out_dir, "valu_busy.txt"), "w") as fh:
+        fh.write("# VALU-busy fraction per launch of each sweep kernel: SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x\n"
+                 "# average duration x 2.4 GHz), from the counters_<workload>.txt passes.\n"
+                 "# columns: kernel  kernel-source-sha256[:16]  valu_busy  workload\n")
+        fh.write("\n".join(sorted(busy_lines)) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -478,7 +613,16 @@ def main():
                     help="skip the full-length oracle comparisons (and the host oracle run of C3)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="write profiles/ summaries from the rocprofv3 passes in DIR (no GPU needed)")
+    ap.add_argument("--profile-command", default="--steps 32 --warmup 0 --no-cpu-baseline --solves 0 --kernel-reps 4 "
+                    "--serving-requests 0 --no-time-to-error --no-full-parity --copy-probe",
+                    help="the bench.py arguments the profiled runs used (recorded in the summaries)")
     args = ap.parse_args()
+
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, os.path.join(ROOT, "profiles"), args.profile_command)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the library has no multi-GPU path; run with --gpus 1.", file=sys.stderr)
