@@ -503,17 +503,48 @@ def _copy_calibration(raw, counter):
     return max(vals) if vals else None
 
 
-def summarize_profiles(raw_dir, out_dir, command):
+def _trace_split(path, min_run):
+    """Per sweep kernel, the mean duration (us) of its back-to-back launches
+    (runs of at least min_run identical consecutive dispatches: the benchmark's
+    HIP-event timing) and of its launches inside the replayed step sequence,
+    with their counts, from a rocprofv3 kernel trace."""
+    rows = sorted(_read_csv(path), key=lambda r: int(r["Start_Timestamp"]))
+    seq = [(_short_name(r["Kernel_Name"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+           for r in rows]
+    out = {}
+    i = 0
+    while i < len(seq):
+        j = i
+        while j < len(seq) and seq[j][0] == seq[i][0]:
+            j += 1
+        name = seq[i][0]
+        if name.startswith("sweep_kernel"):
+            slot = out.setdefault(name, {"b2b": [], "seq": []})
+            slot["b2b" if j - i >= min_run else "seq"].extend(d for _, d in seq[i:j])
+        i = j
+    return {k: {w: (len(v[w]), sum(v[w]) / len(v[w]) if v[w] else None) for w in v} for k, v in out.items()}
+
+
+def summarize_profiles(raw_dir, out_dir, command, stats_command=None, kernel_reps=100):
     """Writes profiles/ summaries from the rocprofv3 passes in raw_dir
-    (prof_stats: --kernel-trace --stats; prof_fetch / prof_write: --pmc FETCH_SIZE /
-    WRITE_SIZE; prof_busy, prof_mixf, prof_mixo: the SQ counter sets)."""
+    (prof_stats: --kernel-trace --stats of stats_command; prof_fetch / prof_write:
+    --pmc FETCH_SIZE / WRITE_SIZE; prof_busy, prof_mixf, prof_mixo: the SQ counter
+    sets, all of command)."""
     sha = kernel_source_hash()
+    stats_command = stats_command or command
     stats = {}
     for row in _read_csv(os.path.join(raw_dir, "prof_stats", "run_kernel_stats.csv")):
         n = _short_name(row["Name"])
         if n.startswith("sweep_kernel"):
             stats[n] = (int(row["Calls"]), float(row["AverageNs"]) / 1e3, float(row["MinNs"]) / 1e3,
                         float(row["MaxNs"]) / 1e3, float(row["TotalDurationNs"]) / 1e6)
+    trace = os.path.join(raw_dir, "prof_stats", "run_kernel_trace.csv")
+    split = _trace_split(trace, min(kernel_reps, 4)) if os.path.exists(trace) else {}
+
+    def launch_us(kern):
+        """The duration the benchmark's roofline uses: the back-to-back mean."""
+        b = split.get(kern, {}).get("b2b", (0, None))
+        return b[1] if b[1] else stats[kern][1]
     ctr = {}
     for pas in ("fetch", "write", "busy", "mixf", "mixo"):
         path = os.path.join(raw_dir, f"prof_{pas}", "run_counter_collection.csv")
@@ -532,9 +563,11 @@ def summarize_profiles(raw_dir, out_dir, command):
     for kern in stats:
         a = targs(kern)
         by_tag.setdefault(PROFILE_TAGS.get((int(a[0]), int(a[2])), "other"), []).append(kern)
-    head = (f"# command (one MI355X, repository root, TMPDIR=/tmp):\n"
+    head = (f"# commands (one MI355X, repository root, TMPDIR=/tmp):\n"
+            f"#   rocprofv3 --kernel-trace --stats -d <dir> -o run --output-format csv -- python3 bench.py "
+            f"{stats_command}\n"
             f"#   rocprofv3 <pass> -d <dir> -o run --output-format csv -- python3 bench.py {command}\n"
-            f"#   passes: --kernel-trace --stats | --pmc FETCH_SIZE | --pmc WRITE_SIZE |\n"
+            f"#   passes: --pmc FETCH_SIZE | --pmc WRITE_SIZE |\n"
             f"#     --pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_ACTIVE_INST_VALU SQ_BUSY_CYCLES "
             f"SQ_WAVE_CYCLES GRBM_GUI_ACTIVE |\n"
             f"#     --pmc SQ_INSTS_VALU_{{ADD,MUL,FMA,TRANS}}_{{F32,F64}} |\n"
@@ -547,26 +580,36 @@ def summarize_profiles(raw_dir, out_dir, command):
         kerns.sort(key=lambda k: -stats[k][4])
         with open(os.path.join(out_dir, f"kernel_stats_{tag}.txt"), "w") as fh:
             fh.write(f"# rocprofv3 kernel statistics: GP-WENO sweeps, {tag}\n#\n" + head)
-            fh.write("# The run holds fp32 and fp64 solvers: the timed graph-replayed steps and the back-to-back\n"
-                     "# launches of every kernel of the step sequence (bench's HIP-event timing). sweep_kernel<ndim,\n"
-                     "# dir, R, Real, finishes-an-RK-stage, indicator kind, general boundaries, flux-correction\n"
-                     "# terms>; the sweeps of a stage run z, y, x and the x sweep finishes it.\n#\n")
+            fh.write("# The stats run is the benchmark's timing with its other legs off (no CPU baseline, latency\n"
+                     "# solves, serving, time-to-error or full-length oracle runs, whose millions of launches\n"
+                     "# are not timed kernels). It holds fp32 and fp64 solvers: the warm-up and timed\n"
+                     "# graph-replayed steps, and the back-to-back launches of every kernel of the step sequence\n"
+                     "# that bench's HIP events time. b2b_us is the mean over those back-to-back launches (what\n"
+                     "# bench's roofline divides by), seq_us the mean inside the replayed steps, where a y sweep\n"
+                     "# follows a finishing sweep. sweep_kernel<ndim, dir, R, Real, finishes-an-RK-stage,\n"
+                     "# indicator kind, general boundaries, flux-correction terms>; the sweeps of a stage run z,\n"
+                     "# y, x and the x sweep finishes it.\n#\n")
             fh.write(f"{'kernel':62s} {'calls':>6s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} "
-                     f"{'total_ms':>9s}\n")
+                     f"{'total_ms':>9s} {'b2b_n':>6s} {'b2b_us':>9s} {'seq_n':>6s} {'seq_us':>9s}\n")
             for k in kerns:
                 c, av, mn, mx, tot = stats[k]
-                fh.write(f"{k:62s} {c:6d} {av:9.2f} {mn:9.2f} {mx:9.2f} {tot:9.3f}\n")
+                sp = split.get(k, {})
+                bn, bu = sp.get("b2b", (0, None))
+                qn, qu = sp.get("seq", (0, None))
+                fh.write(f"{k:62s} {c:6d} {av:9.2f} {mn:9.2f} {mx:9.2f} {tot:9.3f} {bn:6d} "
+                         f"{(bu or float('nan')):9.2f} {qn:6d} {(qu or float('nan')):9.2f}\n")
         with open(os.path.join(out_dir, f"counters_{tag}.txt"), "w") as fh:
             fh.write(f"# rocprofv3 --pmc counters per dispatch (mean over dispatches), {tag}\n#\n" + head)
             fh.write(f"# calibration: a 1 GiB device copy (__amd_rocclr_copyBuffer) reads FETCH_SIZE {fetch_cal} KiB "
                      f"and WRITE_SIZE {write_cal} KiB per dispatch,\n# so FETCH_SIZE is scaled by "
                      f"{f_scale:.3f} and WRITE_SIZE by {w_scale:.3f}.\n"
                      "# derived: hbm_bytes = calibrated fetch + write; valu_busy = SQ_INSTS_VALU x 4 cycles /\n"
-                     "# (1024 SIMDs x avg duration x 2.4 GHz); flops_per_lane_instr = (FLOPS_FP32 + FLOPS_FP64) /\n"
-                     "# (64 SQ_INSTS_VALU); the instruction classes are wave-level counts.\n#\n")
+                     "# (1024 SIMDs x duration x 2.4 GHz), with the back-to-back duration of kernel_stats_<workload>\n"
+                     "# (b2b_us); flops_per_lane_instr = (FLOPS_FP32 + FLOPS_FP64) / (64 SQ_INSTS_VALU); the\n"
+                     "# instruction classes are wave-level counts.\n#\n")
             for k in kerns:
                 cv = ctr.get(k, {})
-                av_us = stats[k][1]
+                av_us = launch_us(k)
                 fh.write(f"{k}\n")
                 for name in sorted(cv):
                     fh.write(f"    {name:32s} {cv[name]:18.1f}\n")
@@ -591,7 +634,7 @@ def summarize_profiles(raw_dir, out_dir, command):
         fh.write("\n".join(sorted(traffic_lines)) + "\n")
     with open(os.path.join(out_dir, "valu_busy.txt"), "w") as fh:
         fh.write("# VALU-busy fraction per launch of each sweep kernel: SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x\n"
-                 "# average duration x 2.4 GHz), from the counters_<workload>.txt passes.\n"
+                 "# back-to-back duration x 2.4 GHz), from the counters_<workload>.txt passes.\n"
                  "# columns: kernel  kernel-source-sha256[:16]  valu_busy  workload\n")
         fh.write("\n".join(sorted(busy_lines)) + "\n")
 
@@ -617,11 +660,15 @@ def main():
                     help="write profiles/ summaries from the rocprofv3 passes in DIR (no GPU needed)")
     ap.add_argument("--profile-command", default="--steps 32 --warmup 0 --no-cpu-baseline --solves 0 --kernel-reps 4 "
                     "--serving-requests 0 --no-time-to-error --no-full-parity --copy-probe",
-                    help="the bench.py arguments the profiled runs used (recorded in the summaries)")
+                    help="the bench.py arguments the counter runs used (recorded in the summaries)")
+    ap.add_argument("--stats-command", default="--no-cpu-baseline --solves 0 --serving-requests 0 "
+                    "--no-time-to-error --no-full-parity",
+                    help="the bench.py arguments the --kernel-trace --stats run used (the default timing)")
     args = ap.parse_args()
 
     if args.summarize_profiles:
-        summarize_profiles(args.summarize_profiles, os.path.join(ROOT, "profiles"), args.profile_command)
+        summarize_profiles(args.summarize_profiles, os.path.join(ROOT, "profiles"), args.profile_command,
+                           args.stats_command, args.kernel_reps)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
