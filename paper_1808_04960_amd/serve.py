@@ -4,7 +4,8 @@ Requests arrive over time and are replayed against a clock. A request is admitte
 when a slot is free and its HBM footprint (state plus stage workspace) fits the
 budget. Admitted problems stay resident on the device. The scheduler advances all
 of them together, a few steps per tick: each step is one batched launch per sweep
-and per group of equal R (``gpweno_batch_run``, replayed from a captured graph).
+and per group of problems of one kind (dimension, R, precision, tables;
+``gpweno_batch_run``, replayed from a captured graph).
 A problem that reaches its step count is copied back and its memory released,
 which lets the next waiting requests in while the others keep running.
 
