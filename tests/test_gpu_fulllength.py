@@ -14,7 +14,11 @@ holds against the oracle's own state). C3's oracle runs here, on the host's
 cores (a few minutes).
 
 Bars: relative L1 1e-12 (float64) and 1e-5 (float32), the same step count and
-end time, and the per-cell state bound of parity_bounds.
+end time, and the per-cell state bound of parity_bounds. Every run also
+conserves mass, momentum and energy (periodic grids) in its float64 sums: the
+flux differences telescope exactly, so the totals change only by the float64
+rounding of the per-cell stage updates, at most a few ulp of the total of |U|
+per step (bound: 8 n eps64 sum|U_k| after n steps).
 """
 import os
 import sys
@@ -54,11 +58,22 @@ def reference(name):
 def gpu_run(g, U, R, prec, t_final, max_steps):
     dx = g.dx[0]
     s = gw.Solver(g, R, 12 * dx, 3 * dx, precision=prec, U0=U)
+    tot0 = s.conserved_sums()
     t0 = time.perf_counter()
     n, t = s.run(t_final, max_steps=max_steps)
     el = time.perf_counter() - t0
+    tot1 = s.conserved_sums()
     Ug = s.get_state()
     s.close()
+    # the float64 totals before and after: conserved up to the rounding of the
+    # per-cell updates (see the module docstring)
+    scale = np.abs(U).reshape(g.nv, -1).sum(axis=1)
+    bound = 8 * n * 2.0**-53 * scale          # a field that is zero everywhere must stay zero
+    change = np.abs(tot1 - tot0)
+    ratio = max((float(c / b) for c, b in zip(change, bound) if b > 0), default=0.0)
+    announce(f"  conserved totals: largest change {ratio:.3f} of the rounding bound")
+    assert np.all(change <= bound), (tot0, tot1)
+    np.testing.assert_allclose(tot0, U.reshape(g.nv, -1).sum(axis=1), rtol=1e-12, atol=1e-12 * scale.max())
     return Ug, n, t, el
 
 
