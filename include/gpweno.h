@@ -137,7 +137,8 @@ typedef struct gpweno_ctx gpweno_ctx;
  * gamma: ratio of specific heats, > 1. Every axis needs n >= 2. On success *out
  * receives a context with default options; the device in use is the current
  * HIP device. Errors: EINVAL for invalid arguments, ENOMEM/EHIP on allocation.
- * Host-side work plus one small device allocation (the control block). */
+ * Host-side work plus a control block from a per-device pool (allocated 64 at
+ * a time, reused after gpweno_destroy). */
 int gpweno_init(const gpweno_grid *grid, int R, double ell, double sigma, double gamma,
                 gpweno_ctx **out);
 
@@ -328,8 +329,9 @@ int gpweno_set_end(gpweno_ctx *ctx, double t_final, long step_limit);
 
 /* ---- Batched execution of many independent problems ------------------------
  * A batch advances a set of bound contexts together: every launch of the step
- * sequence covers all problems of a group (same ndim, R, precision and GP
- * tables) with one kernel whose blocks are dealt problem by problem. Each
+ * sequence covers all problems of a group (one kind: same ndim, R, precision,
+ * scheme and indicator kind, flux-correction terms, boundary kinds per axis and
+ * per-axis tables) with one kernel whose blocks are dealt problem by problem. Each
  * problem keeps its own dt, time, end time and step limit in its own control
  * block; a problem that is done skips its blocks. A block computes exactly
  * what the single-problem sweep computes for its cells, so each problem's
@@ -360,10 +362,11 @@ int gpweno_batch_create(gpweno_batch **out);
 int gpweno_batch_set(gpweno_batch *b, gpweno_ctx *const *ctxs, int n, void *stream);
 
 /* Enqueues nsteps batched steps (nsteps >= 1) on stream by replaying a captured
- * graph of one batched step (captured on first use, and again only when a new
- * kind of problem joins the set). Every launch has a fixed grid, its kernel's
- * resident capacity, whose blocks loop over the set's logical blocks.
- * Errors: EINVAL, EHIP. */
+ * graph of one batched step (captured on first use, and again only when the
+ * kinds of problems in the set change). Every launch has one block per logical
+ * block of its group; after a set change of the same kinds the grids of the
+ * captured launches are updated in place on the instantiated graph before the
+ * next replay. Errors: EINVAL, EHIP. */
 int gpweno_batch_run(gpweno_batch *b, int nsteps, void *stream);
 
 /* Blocking: for every problem of the set, in set order, its time, last dt, step
@@ -373,9 +376,9 @@ int gpweno_batch_status(gpweno_batch *b, double *t, double *dt, long *nsteps, in
 
 /* Number of times the batch has captured its step graph (instrumentation; -1
  * for NULL). A set change that keeps the kinds of problems (dimension, R,
- * precision, scheme, boundary kinds, flux correction, tables) does not add
- * one, whatever the problems' sizes: each launch's grid is its kernel's
- * resident capacity on the device. */
+ * precision, scheme, boundary kinds, flux correction, tables) in the same order
+ * does not add one, whatever the problems' sizes: the captured launches read
+ * the set through the work tables, and their grids are updated in place. */
 long gpweno_batch_captures(const gpweno_batch *b);
 
 /* Waits for the batch's last stream and frees its resources. NULL is ignored. */

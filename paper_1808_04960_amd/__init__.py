@@ -380,8 +380,9 @@ def _bcheck(code, b=None):
 
 class Batch:
     """Advances many independent Solvers together (one batched launch per sweep
-    and group of equal ndim, R and precision). All member solvers and the batch
-    must use the same stream."""
+    and group of problems of one kind: ndim, R, precision, scheme, correction
+    terms, boundary kinds and tables). All member solvers and the batch must use
+    the same stream."""
 
     def __init__(self, stream):
         self._b = ctypes.c_void_p()
