@@ -90,6 +90,49 @@ def test_rhs_matches_oracle(ndim, R, prec):
     assert cell <= 1.0
 
 
+TINY_SHAPES = [(2,), (3,), (5,), (7,), (13,), (3, 5), (2, 64), (64, 2), (3, 2, 4), (2, 5, 3)]
+
+
+def tiny_grid(shape, h=1.0 / 64):
+    """Square cells of size h on an axis of n cells each (n down to 2)."""
+    hi = [n * h for n in shape]
+    if len(shape) == 1:
+        return inputs.grid1d(shape[0], 0.0, hi[0])
+    if len(shape) == 2:
+        return inputs.grid2d(shape[0], shape[1], (0.0, 0.0), tuple(hi))
+    return inputs.grid3d(*shape, (0.0, 0.0, 0.0), tuple(hi))
+
+
+@pytest.mark.parametrize("R", [1, 2, 3])
+@pytest.mark.parametrize("shape", TINY_SHAPES)
+def test_tiny_periodic_axes(shape, R):
+    """Periodic axes shorter than a stencil, down to 2 cells: every stencil and
+    every 64-cell run wraps the axis more than once (the general modulo of the
+    index wrap, runs mostly of unused lanes, x groups with missing columns). One
+    right-hand side in both precisions within the bounds of
+    test_rhs_matches_oracle, and three steps within the usual 1e-12 / 1e-5 and
+    the per-cell state bound."""
+    g = tiny_grid(shape)
+    dx = g.dx[0]
+    U = inputs.random_smooth(g, seed=40 + R)
+    announce(f"tiny periodic axes {shape} R={R}")
+    o = oracle.OracleSolver(g, R, 12 * dx, 3 * dx)
+    ref = o.rhs(U)
+    Uo = U.copy()
+    t_o, n_o = o.run(Uo, 1e9, max_steps=3)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        s = gw.Solver(g, R, 12 * dx, 3 * dx, precision=prec, U0=U)
+        got = s.rhs(U)
+        assert float(np.abs(got - ref).sum()) < 16 * EPS[prec] * flux_bound(g, U)
+        assert rhs_cell_excess(g, U, got, ref, prec, R) <= 1.0
+        n, t = s.run(1e9, max_steps=3)
+        Ug = s.get_state()
+        s.close()
+        assert n == n_o == 3 and abs(t - t_o) <= (1e-13 if prec == "fp64" else 1e-6) * t_o
+        assert rel_l1(Ug, Uo) < tol
+        assert state_cell_excess(g, U, Ug, Uo, prec, t, n) <= 1.0
+
+
 @pytest.mark.parametrize("scale", [1e-20, 1e20])
 @pytest.mark.parametrize("R", [1, 2, 3])
 def test_rhs_over_the_range_of_the_data(R, scale):
