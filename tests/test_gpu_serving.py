@@ -180,3 +180,50 @@ def test_set_changes_reuse_the_captured_step_graph():
         assert s.time()[2] == limit
         assert np.array_equal(s.get_state(), ref.get_state()), (g.n, R)
     b.close()
+
+
+def test_batch_mixing_dimensions_precisions_and_sizes_is_bitwise_single():
+    """One batch holding 1D, 2D and 3D problems in both precisions, including
+    axes of a few cells: each kind is its own group, the captured step graph
+    interleaves groups with 3, 6 and 9 launches per step, and a set change that
+    swaps problems for larger or smaller ones of the same kinds only updates the
+    launch grids. Every problem is bitwise its solo run."""
+    announce("batch mixing dimensions, precisions and sizes")
+    stream = torch.cuda.Stream()
+
+    def grid(shape, h=1.0 / 64):
+        hi = [n * h for n in shape]
+        if len(shape) == 1:
+            return inputs.grid1d(shape[0], 0.0, hi[0])
+        if len(shape) == 2:
+            return inputs.grid2d(shape[0], shape[1], (0.0, 0.0), tuple(hi))
+        return inputs.grid3d(*shape, (0.0, 0.0, 0.0), tuple(hi))
+
+    def mk(shape, prec, R, limit, seed):
+        g = grid(shape)
+        U = inputs.random_smooth(g, seed=seed)
+        dx = g.dx[0]
+        s = gw.Solver(g, R, 12 * dx, 3 * dx, precision=prec, U0=U, stream=stream)
+        s.set_end(1e30, limit)
+        return s, (g, U, prec, R, limit)
+
+    first = [mk((300,), "fp64", 2, 9, 1), mk((5,), "fp32", 3, 7, 2), mk((70, 33), "fp32", 2, 8, 3),
+             mk((3, 90), "fp64", 2, 6, 4), mk((20, 13, 11), "fp32", 2, 5, 5), mk((9, 2, 30), "fp64", 2, 7, 6)]
+    b = gw.Batch(stream)
+    b.set([s for s, _ in first])
+    b.run(4)
+    # same kinds, other sizes: the first three leave, larger and smaller ones join
+    second = [mk((1000,), "fp64", 2, 6, 7), mk((2,), "fp32", 3, 5, 8), mk((130, 21), "fp32", 2, 4, 9)]
+    keep = first[3:]
+    b.set([s for s, _ in keep + second])
+    b.run(10)
+    assert b.captures() == 1
+    _, _, ns, err = b.status()
+    assert list(ns) == [info[4] for _, info in keep + second] and not err.any()
+    for s, (g, U, prec, R, limit) in first[:3]:
+        assert s.time()[2] == 4   # left the batch after four steps
+    for s, (g, U, prec, R, limit) in first + second:
+        ref = gw.Solver(g, R, 12 * g.dx[0], 3 * g.dx[0], precision=prec, U0=U)
+        ref.run(1e30, max_steps=s.time()[2])
+        assert np.array_equal(s.get_state(), ref.get_state()), (g.n, prec, R)
+    b.close()
