@@ -59,6 +59,45 @@ def test_rhs_with_boundaries_matches_oracle(ndim, R, prec):
     assert cell <= 1.0
 
 
+def smallest_grid(ndim, R, h=1.0 / 64):
+    """The shortest axes the library accepts for each boundary kind: reflecting
+    sides need R + 3 cells, outflow and periodic ones 2."""
+    w = R + 3
+    if ndim == 1:
+        return inputs.grid1d(w, 0.0, w * h, [(REFLECT, REFLECT)])
+    if ndim == 2:
+        return inputs.grid2d(w, 2, (0.0, 0.0), (w * h, 2 * h), [(REFLECT, OUTFLOW), (OUTFLOW, OUTFLOW)])
+    return inputs.grid3d(2, w, 3, (0.0, 0.0, 0.0), (2 * h, w * h, 3 * h),
+                         [(OUTFLOW, OUTFLOW), (REFLECT, REFLECT), (PERIODIC, PERIODIC)])
+
+
+@pytest.mark.parametrize("R", [1, 2, 3])
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_smallest_accepted_axes_with_walls_and_outflow(ndim, R):
+    """Reflecting axes of exactly R + 3 cells and outflow axes of 2: every ghost
+    is a mirror or copy of a cell that is itself near the other wall, and most
+    lanes of a run read clamped positions. Right-hand side in both precisions
+    within the rounding bounds, three steps within 1e-12 / 1e-5."""
+    g = smallest_grid(ndim, R)
+    announce(f"smallest axes ndim={ndim} R={R} n={g.n[:ndim]} bc={g.bc[:ndim]}")
+    U = inputs.random_smooth(g, seed=500 + 10 * ndim + R)
+    dx = g.dx[0]
+    o = oracle.OracleSolver(g, R, 12 * dx, 3 * dx)
+    ref = o.rhs(U)
+    Uo = U.copy()
+    t_o, n_o = o.run(Uo, 1e9, max_steps=3)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        s = gw.Solver(g, R, 12 * dx, 3 * dx, precision=prec, U0=U)
+        got = s.rhs(U)
+        assert float(np.abs(got - ref).sum()) < 16 * EPS[prec] * flux_bound(g, U)
+        assert rhs_cell_excess(g, U, got, ref, prec, R) <= 1.0
+        n, t = s.run(1e9, max_steps=3)
+        Ug = s.get_state()
+        s.close()
+        assert n == n_o == 3 and abs(t - t_o) <= (1e-13 if prec == "fp64" else 1e-6) * t_o
+        assert rel_l1(Ug, Uo) < tol
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 @pytest.mark.parametrize("R", [1, 2, 3])
 def test_shock_tube_run_matches_oracle(R, prec, tol):
