@@ -81,3 +81,17 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120, cwd=ROOT)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_committed_profiles_match_the_device_sources():
+    """The counter tables the benchmark reads (profiles/traffic.txt,
+    valu_busy.txt) were taken with the device sources as they are: a kernel
+    change without a new profile fails here instead of silently reporting no
+    traffic."""
+    sha = bench.kernel_source_hash()
+    for name in ("traffic.txt", "valu_busy.txt"):
+        with open(os.path.join(ROOT, "profiles", name)) as fh:
+            rows = [line.split() for line in fh if line.strip() and not line.startswith("#")]
+        assert rows and all(r[1] == sha for r in rows), name
+    with open(os.path.join(ROOT, "profiles", "kernel_stats_vortex2d_512_R2.txt")) as fh:
+        assert f"sha256[:16] = {sha}" in fh.read()
