@@ -212,3 +212,32 @@ def test_residual_grows_with_ell_and_stays_small_for_r_up_to_two():
     for R in (1, 2):
         assert gw.compute_table_residual(R, 192.0, 3.0) < 1e-15
     assert gw.compute_table_residual(2, 80.0, 3.0, scheme="gp-ao") > 1e-13
+
+
+from hypothesis import given, settings, strategies as st  # noqa: E402
+
+
+@settings(max_examples=300, deadline=None)
+@given(scheme=st.integers(-2, 5), R=st.integers(-1, 5),
+       ell=st.one_of(st.floats(allow_nan=True, allow_infinity=True), st.floats(0.5, 300.0)),
+       sigma=st.one_of(st.floats(allow_nan=True, allow_infinity=True), st.floats(0.5, 40.0)))
+def test_host_table_entry_points_never_crash(scheme, R, ell, sigma):
+    """Any arguments to the host-only table builders return OK or EINVAL, never
+    crash; accepted tables are finite and their mirror residual is below the
+    library's acceptance limit (1e-6)."""
+    L = gw.lib()
+    wp = np.zeros((4, 4))
+    wm = np.zeros((4, 4))
+    gp = np.zeros(4)
+    gm = np.zeros(4)
+    P = np.zeros((4, 4, 4))
+    ptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))  # noqa: E731
+    rc = L.gpweno_compute_tables(scheme, R, ell, sigma, ptr(wp), ptr(wm), ptr(gp), ptr(gm), ptr(P))
+    assert rc in (gw.OK, gw.EINVAL)
+    res = ctypes.c_double(-1.0)
+    rc2 = L.gpweno_compute_table_residual(scheme, R, ell, sigma, ctypes.byref(res))
+    assert rc2 == rc
+    if rc == gw.OK:
+        assert 0 <= scheme <= 3 and 1 <= R <= 3
+        assert all(np.isfinite(a).all() for a in (wp, wm, gp, gm, P))
+        assert 0.0 <= res.value <= 1e-6
