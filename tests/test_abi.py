@@ -241,3 +241,25 @@ def test_host_table_entry_points_never_crash(scheme, R, ell, sigma):
         assert 0 <= scheme <= 3 and 1 <= R <= 3
         assert all(np.isfinite(a).all() for a in (wp, wm, gp, gm, P))
         assert 0.0 <= res.value <= 1e-6
+
+
+@settings(max_examples=300, deadline=None)
+@given(ndim=st.integers(-1, 4), n=st.lists(st.integers(-3, 100) | st.just(1 << 25), min_size=3, max_size=3),
+       span=st.lists(st.floats(-2.0, 3.0) | st.just(float("nan")), min_size=3, max_size=3),
+       bc=st.lists(st.integers(-1, 3), min_size=6, max_size=6), R=st.integers(-1, 4),
+       ell=st.floats(-1.0, 5.0) | st.just(float("inf")), sigma=st.floats(-1.0, 2.0) | st.just(float("nan")),
+       gamma=st.floats(0.5, 3.0) | st.just(float("nan")), scheme=st.integers(-1, 4))
+def test_init_never_crashes(L, ndim, n, span, bc, R, ell, sigma, gamma, scheme):
+    """Any grid and parameters: gpweno_init_scheme returns EINVAL, or (valid
+    arguments) OK with a GPU and EHIP without one; never a crash, and no
+    context unless OK."""
+    g = gw.make_grid(_G(ndim, tuple(n), (0.0, 0.0, 0.0), tuple(span),
+                        ((bc[0], bc[1]), (bc[2], bc[3]), (bc[4], bc[5]))))
+    ctx = ctypes.c_void_p()
+    rc = L.gpweno_init_scheme(ctypes.byref(g), scheme, R, ell, sigma, gamma, ctypes.byref(ctx))
+    assert rc in (gw.OK, gw.EINVAL, gw.EHIP)
+    if rc == gw.OK:
+        assert ctx.value
+        L.gpweno_destroy(ctx)
+    else:
+        assert not ctx.value
