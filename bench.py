@@ -11,7 +11,7 @@ Reported (one JSON line):
   fp64         the same for the all-float64 path
   roofline     the dominant sweep kernel of the headline workload, timed with HIP
                events on its stream; achieved flop rate by the algorithmic count
-               of one cell in one direction (the survey's per-cell tally)
+               of one cell in one direction (a per-cell tally of the path's steps)
   workloads    the Kelvin-Helmholtz (2048 x 1024, GP-R3) and 3D density-wave
                (256^3, GP-R2) workloads: the same timing and roofline, plus the
                HBM rate of every sweep from the committed rocprofv3 counters
@@ -77,7 +77,7 @@ def kernel_source_hash() -> str:
 
 def flops_per_cell_dir(ndim: int, R: int) -> int:
     """Algorithmic flops of one cell in one direction (FMA = 2, square root and
-    division = 1), the survey's per-cell tally of the path's steps:
+    division = 1), a per-cell tally of the path's steps in their plain forms:
       eigen quantities 10, projection 10 n (n = 2R+1),
       GP-WENO per characteristic field 4(R+1)^2 (indicators) + 2(R+1)^2(R+2)
         (candidates at both points) + 13(R+1) (weights, combination),
@@ -113,7 +113,7 @@ def flops_per_launch(ndim, R, ncell, fin):
 
 
 def algorithmic_bytes_per_step(ndim, ncell):
-    """The survey's algorithmic bytes: per cell-update (one cell through one RK
+    """Algorithmic bytes: per cell-update (one cell through one RK
     stage, all directions) (8/3) nv s with s = 8 (float64 state): read the stage
     state, write the next, and read U^n in stages 2 and 3. Three per step."""
     return 3 * ncell * (8.0 / 3.0) * (2 + ndim) * 8

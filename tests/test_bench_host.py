@@ -16,7 +16,7 @@ import bench  # noqa: E402
 
 
 def test_algorithmic_flops_per_cell_and_direction():
-    """The survey's tally: eigen quantities 10, projection 10n, per field
+    """The per-cell tally of the path's steps: eigen quantities 10, projection 10n, per field
     4(R+1)^2 + 2(R+1)^2(R+2) + 13(R+1), back-projection 16, HLLC 90, correction
     and difference 9 nv."""
     assert bench.flops_per_cell_dir(2, 2) == 790
