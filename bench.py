@@ -607,9 +607,9 @@ def summarize_profiles(raw_dir, out_dir, command, stats_command=None, kernel_rep
         kerns.sort(key=lambda k: -stats[k][4])
         with open(os.path.join(out_dir, f"kernel_stats_{tag}.txt"), "w") as fh:
             fh.write(f"# rocprofv3 kernel statistics: GP-WENO sweeps, {tag}\n#\n" + head)
-            fh.write("# The stats run is the benchmark's timing with its other legs off (no CPU baseline, latency\n"
-                     "# solves, serving, time-to-error or full-length oracle runs, whose millions of launches\n"
-                     "# are not timed kernels). It holds fp32 and fp64 solvers: the warm-up and timed\n"
+            fh.write("# The stats run is the benchmark's timing (K = 20, W = 5) with its other legs off (no CPU\n"
+                     "# baseline, latency solves, serving, time-to-error or full-length oracle runs, whose many\n"
+                     "# launches are not timed kernels). It holds fp32 and fp64 solvers: the warm-up and timed\n"
                      "# graph-replayed steps, and the back-to-back launches of every kernel of the step sequence\n"
                      "# that bench's HIP events time. b2b_us is the mean over those back-to-back launches (what\n"
                      "# bench's roofline divides by), seq_us the mean inside the replayed steps, where a y sweep\n"
@@ -688,9 +688,9 @@ def main():
     ap.add_argument("--profile-command", default="--steps 32 --warmup 0 --no-cpu-baseline --solves 0 --kernel-reps 4 "
                     "--serving-requests 0 --no-time-to-error --no-full-parity --copy-probe",
                     help="the bench.py arguments the counter runs used (recorded in the summaries)")
-    ap.add_argument("--stats-command", default="--no-cpu-baseline --solves 0 --serving-requests 0 "
-                    "--no-time-to-error --no-full-parity",
-                    help="the bench.py arguments the --kernel-trace --stats run used (the default timing)")
+    ap.add_argument("--stats-command", default="--gpus 1 --steps 20 --warmup 5 --no-cpu-baseline --solves 0 "
+                    "--serving-requests 0 --no-time-to-error --no-full-parity",
+                    help="the bench.py arguments the --kernel-trace --stats run used (the benchmark's timing)")
     args = ap.parse_args()
 
     if args.summarize_profiles:
