@@ -1,8 +1,10 @@
 """Builds libgpweno.so in-tree for gfx950.
 
-  gp_tables.cpp      g++   (binary128 arithmetic, libquadmath)
-  gpweno_kernels_*.hip hipcc --offload-arch=gfx950 (device kernels + launchers)
-  gpweno_api.cpp     hipcc (host C ABI)
+  gp_tables.cpp          g++   (binary128 arithmetic, libquadmath)
+  gpweno_kernels.hip     hipcc --offload-arch=gfx950 (control, CFL-speed and sums kernels, sweep dispatch)
+  gpweno_sweep_*d_*.hip  hipcc --offload-arch=gfx950 (sweep kernels and launchers,
+                         one file per dimension and precision, compiled in parallel)
+  gpweno_api.cpp         hipcc (host C ABI)
 
 Usage: python -m paper_1808_04960_amd.build
 """
