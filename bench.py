@@ -493,6 +493,8 @@ def full_length_accuracy(name, W, grid, U0, solvers, run_c3_oracle):
 # ---------------------------------------------------------------------------
 PROFILE_TAGS = {(2, 2): "vortex2d_512_R2", (2, 3): "kh2d_2048x1024_R3", (3, 2): "wave3d_256_R2",
                 (1, 2): "sine1d_128_R2"}
+PROFILE_CELLS = {"vortex2d_512_R2": 512 * 512, "kh2d_2048x1024_R3": 2048 * 1024, "wave3d_256_R2": 256 ** 3,
+                 "sine1d_128_R2": 128}
 COPY_BYTES = 1 << 30   # the --copy-probe copy
 
 
@@ -632,8 +634,10 @@ def summarize_profiles(raw_dir, out_dir, command, stats_command=None, kernel_rep
                      f"{f_scale:.3f} and WRITE_SIZE by {w_scale:.3f}.\n"
                      "# derived: hbm_bytes = calibrated fetch + write; valu_busy = SQ_INSTS_VALU x 4 cycles /\n"
                      "# (1024 SIMDs x duration x 2.4 GHz), with the back-to-back duration of kernel_stats_<workload>\n"
-                     "# (b2b_us); flops_per_lane_instr = (FLOPS_FP32 + FLOPS_FP64) / (64 SQ_INSTS_VALU); the\n"
-                     "# instruction classes are wave-level counts.\n#\n")
+                     "# (b2b_us). The instruction classes and SQ_INSTS_VALU_FLOPS_* are wave-level counts (one per\n"
+                     "# wave instruction; FLOPS_* count an FMA as 2 per lane), so hw_flops_per_lane_instr =\n"
+                     "# (FLOPS_FP32 + FLOPS_FP64) / SQ_INSTS_VALU, and alg_flops_per_lane_instr = the launch's\n"
+                     "# algorithmic flops (bench.flops_per_launch) / (64 SQ_INSTS_VALU).\n#\n")
             for k in kerns:
                 cv = ctr.get(k, {})
                 av_us = launch_us(k)
@@ -649,7 +653,11 @@ def summarize_profiles(raw_dir, out_dir, command, stats_command=None, kernel_rep
                          f"at {av_us:.2f} us)\n")
                 if busy is not None:
                     fh.write(f"    {'valu_busy':32s} {busy:18.3f}\n")
-                    fh.write(f"    {'flops_per_lane_instr':32s} {flops / (64 * vi):18.3f}\n")
+                    fh.write(f"    {'hw_flops_per_lane_instr':32s} {flops / vi:18.3f}\n")
+                    a = targs(k)
+                    if tag in PROFILE_CELLS:
+                        alg = flops_per_launch(int(a[0]), int(a[2]), PROFILE_CELLS[tag], a[4] == "true")
+                        fh.write(f"    {'alg_flops_per_lane_instr':32s} {alg / (64 * vi):18.3f}\n")
                     busy_lines.append(f"{k.replace(' ', '')} {sha} {busy:.4f} {tag}")
                 if fb:
                     traffic_lines.append(f"{k.replace(' ', '')} {sha} {fb:.0f} {wb:.0f} {tag}")
