@@ -95,3 +95,19 @@ def test_committed_profiles_match_the_device_sources():
         assert rows and all(r[1] == sha for r in rows), name
     with open(os.path.join(ROOT, "profiles", "kernel_stats_vortex2d_512_R2.txt")) as fh:
         assert f"sha256[:16] = {sha}" in fh.read()
+
+
+def test_committed_flop_ratios_are_per_lane():
+    """SQ_INSTS_VALU_FLOPS_* and SQ_INSTS_VALU are both wave-level counts, so
+    their ratio is the hardware flops per lane-instruction: between 0.5 and 2
+    (an FMA counts 2) for every sweep, and so is the algorithmic ratio."""
+    for tag in ("vortex2d_512_R2", "kh2d_2048x1024_R3", "wave3d_256_R2"):
+        with open(os.path.join(ROOT, "profiles", f"counters_{tag}.txt")) as fh:
+            vals = {}
+            for line in fh:
+                parts = line.split()
+                if len(parts) == 2 and parts[0].endswith("flops_per_lane_instr"):
+                    vals.setdefault(parts[0], []).append(float(parts[1]))
+        assert set(vals) == {"hw_flops_per_lane_instr", "alg_flops_per_lane_instr"}, tag
+        for v in vals.values():
+            assert all(0.5 < x < 2.0 for x in v), (tag, v)
