@@ -23,6 +23,11 @@ reach 0 over the initial and final states (the scheme is stable, so earlier
 errors are not amplified), plus the float64 rounding of the stage
 combinations, a few ulp of |U| per step on each side:
     |U_gpu - U_oracle|_{k,i} <= 32 eps t S + 4 n eps64 max|U_k|.
+
+Conserved totals of a periodic run. The flux differences telescope, so the
+exact totals do not change; the float64 totals before and after n steps differ
+by the rounding of the per-cell stage updates (8 n eps64 sum|U_k|) and by the
+rounding of the two reductions that form them (conserved_totals_bound).
 """
 import numpy as np
 
@@ -73,3 +78,21 @@ def state_cell_excess(g, U0, got, ref, prec, t, nsteps, gamma=1.4):
     bound = 32 * EPS[prec] * t * S + 4 * nsteps * EPS["fp64"] * umax
     err = np.abs(got - ref).reshape(g.nv, -1).max(axis=1)
     return float((err / bound).max())
+
+
+def sum_rounding_depth(ncell):
+    """Additions a term passes through in the library's float64 totals: each
+    thread of 1024 x 256 adds its cells at a fixed stride (ceil(ncell / 262144)
+    terms), a tree of 8 levels joins a block's 256 threads, and one thread adds
+    the 1024 block partials in order. The computed sum then differs from the
+    exact one by at most that depth times eps64 sum|x| (to first order)."""
+    m = -(-int(ncell) // (1024 * 256))
+    return (m - 1) + 8 + 1023
+
+
+def conserved_totals_bound(ncell, nsteps, abs_totals):
+    """Largest change of the float64 conserved totals over nsteps steps of a
+    periodic run: 8 eps64 sum|U_k| per step for the stage updates, plus the
+    rounding of the two reductions. A field that is zero everywhere (bound 0)
+    must stay exactly zero."""
+    return (8 * nsteps + 2 * sum_rounding_depth(ncell)) * EPS["fp64"] * np.asarray(abs_totals)

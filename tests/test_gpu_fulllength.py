@@ -18,7 +18,8 @@ end time, and the per-cell state bound of parity_bounds. Every run also
 conserves mass, momentum and energy (periodic grids) in its float64 sums: the
 flux differences telescope exactly, so the totals change only by the float64
 rounding of the per-cell stage updates, at most a few ulp of the total of |U|
-per step (bound: 8 n eps64 sum|U_k| after n steps).
+per step (8 n eps64 sum|U_k| after n steps), and by the rounding of the two
+sums themselves (parity_bounds.conserved_totals_bound).
 """
 import os
 import sys
@@ -29,7 +30,7 @@ import pytest
 
 import inputs
 import oracle
-from parity_bounds import state_cell_excess
+from parity_bounds import conserved_totals_bound, state_cell_excess
 
 pytestmark = pytest.mark.gpu
 
@@ -66,12 +67,14 @@ def gpu_run(g, U, R, prec, t_final, max_steps):
     Ug = s.get_state()
     s.close()
     # the float64 totals before and after: conserved up to the rounding of the
-    # per-cell updates (see the module docstring)
+    # per-cell updates and of the sums (see the module docstring)
     scale = np.abs(U).reshape(g.nv, -1).sum(axis=1)
-    bound = 8 * n * 2.0**-53 * scale          # a field that is zero everywhere must stay zero
+    bound = conserved_totals_bound(U[0].size, n, scale)   # a field that is zero everywhere must stay zero
     change = np.abs(tot1 - tot0)
     ratio = max((float(c / b) for c, b in zip(change, bound) if b > 0), default=0.0)
-    announce(f"  conserved totals: largest change {ratio:.3f} of the rounding bound")
+    upd = max((float(c / (8 * n * 2.0**-53 * a)) for c, a in zip(change, scale) if a > 0), default=0.0)
+    announce(f"  conserved totals: largest change {ratio:.3f} of the rounding bound "
+             f"({upd:.3f} of its stage-update part 8 n eps sum|U|)")
     assert np.all(change <= bound), (tot0, tot1)
     np.testing.assert_allclose(tot0, U.reshape(g.nv, -1).sum(axis=1), rtol=1e-12, atol=1e-12 * scale.max())
     return Ug, n, t, el

@@ -16,7 +16,7 @@ import pytest
 
 import inputs
 import oracle
-from parity_bounds import EPS as _EPS, local_flux_scale
+from parity_bounds import EPS as _EPS, conserved_totals_bound, local_flux_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -155,3 +155,70 @@ def test_fullsize_step_sampled(name, prec, tol):
         umax = np.abs(ref).reshape(g.nv, -1).max(axis=1)[(slice(None),) + (None,) * g.ndim]
         assert np.all(np.abs(got - ref) <= 32 * _EPS[prec] * dt_gpu * S + 8 * _EPS["fp64"] * umax), starts
     assert num / den < tol, num / den
+
+
+# A state of more than 2^31 float64 values: 48 x 48 copies of the 512^2 vortex
+# tile (24576^2 cells, 4 fields: 2.4e9 values, 19.3 GB per array), so every
+# kernel of a step indexes past 2^31 elements. The tiled field is periodic with
+# the tile's period, so the CFL time step is the tile's and the conserved totals
+# are 48^2 times the tile's.
+BIG_TILES = 48
+
+
+def test_state_beyond_2_31_values_step_sampled():
+    gt, Ut = inputs.isentropic_vortex_2d(512)
+    R = 2
+    n = 512 * BIG_TILES
+    dx = gt.dx[0]
+    g = inputs.grid2d(n, n, (gt.lo[0], gt.lo[1]), (gt.lo[0] + n * dx, gt.lo[1] + n * dx))
+    assert g.nv * n * n > 2**31
+    announce(f"{n}^2 tiled vortex ({g.nv * n * n:.3e} values): tiling on the host")
+    U = np.tile(Ut, (1, BIG_TILES, BIG_TILES))
+    s = gw.Solver(g, R, 12 * dx, 3 * dx, precision="fp64")
+    dt_ref = oracle.OracleSolver(gt, R, 12 * dx, 3 * dx).dt(Ut, 0.0, 1e9)
+    tile_totals = Ut.reshape(g.nv, -1).sum(axis=1) * BIG_TILES**2
+    scale = np.abs(Ut).reshape(g.nv, -1).sum(axis=1) * BIG_TILES**2
+    G = 3 * (R + 3)
+    size = 10
+    bg = box_grid(g, size, G)
+    o = oracle.OracleSolver(bg, R, 12 * dx, 3 * dx)
+    # boxes: across the seam at the last cells (the largest indices), inside
+    # the last tile row and column, and two at random
+    rng = np.random.default_rng(5)
+    starts = sample_starts(g, rng, 3) + [[n - 700, n - 40], [n - 40, 9000]]
+    try:
+        for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+            announce(f"  {prec}: upload, one step through gpweno_run, sampled boxes")
+            s.set_options(prec)
+            s.set_state(U)
+            sums0 = s.conserved_sums()
+            np.testing.assert_allclose(sums0, tile_totals, rtol=1e-12, atol=1e-12 * scale.max())
+            nst, _ = s.run(1e9, max_steps=1)
+            assert nst == 1
+            t_gpu, dt_gpu, _ = s.time()
+            assert abs(dt_gpu - dt_ref) <= 1e-14 * dt_ref
+            sums1 = s.conserved_sums()
+            s.synchronize()
+            # periodic: one step changes the float64 totals only by the
+            # rounding of the per-cell updates and of the sums
+            assert np.all(np.abs(sums1 - sums0) <= conserved_totals_bound(n * n, 1, scale)), (sums0, sums1)
+            announce(f"    totals changed by {float((np.abs(sums1 - sums0) / scale).max()):.2e} of sum|U_k|")
+            num = den = 0.0
+            for st in starts:
+                idx = box_indices(g, st, size, G)
+                Ub = extract(U, idx)
+                o.step(Ub, dt_gpu)
+                ref = interior(Ub, g.ndim, G, size)
+                iy = torch.as_tensor(idx[0], device=s.state.device)
+                ix = torch.as_tensor(idx[1], device=s.state.device)
+                got = interior(s.state.index_select(1, iy).index_select(2, ix).cpu().numpy(), g.ndim, G, size)
+                num += float(np.abs(got - ref).sum())
+                den += float(np.abs(ref).sum())
+                S = float(local_flux_scale(bg, Ub, G).max())
+                umax = np.abs(ref).reshape(g.nv, -1).max(axis=1)[:, None, None]
+                assert np.all(np.abs(got - ref) <= 32 * _EPS[prec] * dt_gpu * S + 8 * _EPS["fp64"] * umax), (prec, st)
+            announce(f"    sampled boxes: relative L1 {num / den:.2e}")
+            assert num / den < tol, (prec, num / den)
+    finally:
+        s.close()
+        del U
