@@ -157,35 +157,54 @@ def test_fullsize_step_sampled(name, prec, tol):
     assert num / den < tol, num / den
 
 
-# A state of more than 2^31 float64 values: 48 x 48 copies of the 512^2 vortex
-# tile (24576^2 cells, 4 fields: 2.4e9 values, 19.3 GB per array), so every
-# kernel of a step indexes past 2^31 elements. The tiled field is periodic with
-# the tile's period, so the CFL time step is the tile's and the conserved totals
-# are 48^2 times the tile's.
-BIG_TILES = 48
+# States of more than 2^31 float64 values, tiled from a benchmark-scale state:
+# 48 x 48 copies of the 512^2 vortex (24576^2 cells, 4 fields: 2.4e9 values,
+# 19.3 GB per array) and 3 x 3 x 3 copies of the 256^3 density wave (768^3
+# cells, 5 fields: 2.3e9 values, 18.1 GB per array), so every kernel of a step
+# indexes past 2^31 elements. A tiled field is periodic with the tile's period,
+# so the CFL time step is the tile's and the conserved totals are the number of
+# tiles times the tile's.
+BIG = {
+    "2d-vortex-24576^2": (lambda: inputs.isentropic_vortex_2d(512), 48, 10),
+    "3d-wave-768^3": (lambda: inputs.density_wave_3d(256), 3, 4),
+}
 
 
-def test_state_beyond_2_31_values_step_sampled():
-    gt, Ut = inputs.isentropic_vortex_2d(512)
+def tiled_grid(gt, tiles):
+    n = [gt.n[d] * tiles for d in range(gt.ndim)]
+    lo = [gt.lo[d] for d in range(gt.ndim)]
+    hi = [gt.lo[d] + n[d] * gt.dx[d] for d in range(gt.ndim)]
+    if gt.ndim == 2:
+        return inputs.grid2d(n[0], n[1], lo, hi)
+    return inputs.grid3d(n[0], n[1], n[2], lo, hi)
+
+
+@pytest.mark.parametrize("name", list(BIG))
+def test_state_beyond_2_31_values_step_sampled(name):
+    make, tiles, size = BIG[name]
+    gt, Ut = make()
     R = 2
-    n = 512 * BIG_TILES
+    g = tiled_grid(gt, tiles)
+    ncell = int(np.prod(g.n[:g.ndim]))
+    assert g.nv * ncell > 2**31
     dx = gt.dx[0]
-    g = inputs.grid2d(n, n, (gt.lo[0], gt.lo[1]), (gt.lo[0] + n * dx, gt.lo[1] + n * dx))
-    assert g.nv * n * n > 2**31
-    announce(f"{n}^2 tiled vortex ({g.nv * n * n:.3e} values): tiling on the host")
-    U = np.tile(Ut, (1, BIG_TILES, BIG_TILES))
+    announce(f"{name} ({g.nv * ncell:.3e} values): tiling on the host")
+    U = np.tile(Ut, (1,) + (tiles,) * g.ndim)
     s = gw.Solver(g, R, 12 * dx, 3 * dx, precision="fp64")
     dt_ref = oracle.OracleSolver(gt, R, 12 * dx, 3 * dx).dt(Ut, 0.0, 1e9)
-    tile_totals = Ut.reshape(g.nv, -1).sum(axis=1) * BIG_TILES**2
-    scale = np.abs(Ut).reshape(g.nv, -1).sum(axis=1) * BIG_TILES**2
+    ntile = tiles ** g.ndim
+    tile_totals = Ut.reshape(g.nv, -1).sum(axis=1) * ntile
+    scale = np.abs(Ut).reshape(g.nv, -1).sum(axis=1) * ntile
     G = 3 * (R + 3)
-    size = 10
     bg = box_grid(g, size, G)
     o = oracle.OracleSolver(bg, R, 12 * dx, 3 * dx)
     # boxes: across the seam at the last cells (the largest indices), inside
-    # the last tile row and column, and two at random
+    # the last tile along each axis, and two at random
     rng = np.random.default_rng(5)
-    starts = sample_starts(g, rng, 3) + [[n - 700, n - 40], [n - 40, 9000]]
+    n = g.n
+    far = [[n[0] - 40] + [n[d] - 20 for d in range(1, g.ndim)],
+           [n[0] // 3] + [n[d] - 40 for d in range(1, g.ndim)]]
+    starts = sample_starts(g, rng, 3) + far
     try:
         for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
             announce(f"  {prec}: upload, one step through gpweno_run, sampled boxes")
@@ -201,7 +220,7 @@ def test_state_beyond_2_31_values_step_sampled():
             s.synchronize()
             # periodic: one step changes the float64 totals only by the
             # rounding of the per-cell updates and of the sums
-            assert np.all(np.abs(sums1 - sums0) <= conserved_totals_bound(n * n, 1, scale)), (sums0, sums1)
+            assert np.all(np.abs(sums1 - sums0) <= conserved_totals_bound(ncell, 1, scale)), (sums0, sums1)
             announce(f"    totals changed by {float((np.abs(sums1 - sums0) / scale).max()):.2e} of sum|U_k|")
             num = den = 0.0
             for st in starts:
@@ -209,13 +228,14 @@ def test_state_beyond_2_31_values_step_sampled():
                 Ub = extract(U, idx)
                 o.step(Ub, dt_gpu)
                 ref = interior(Ub, g.ndim, G, size)
-                iy = torch.as_tensor(idx[0], device=s.state.device)
-                ix = torch.as_tensor(idx[1], device=s.state.device)
-                got = interior(s.state.index_select(1, iy).index_select(2, ix).cpu().numpy(), g.ndim, G, size)
+                box = s.state
+                for a, ia in enumerate(idx):
+                    box = box.index_select(1 + a, torch.as_tensor(ia, device=s.state.device))
+                got = interior(box.cpu().numpy(), g.ndim, G, size)
                 num += float(np.abs(got - ref).sum())
                 den += float(np.abs(ref).sum())
                 S = float(local_flux_scale(bg, Ub, G).max())
-                umax = np.abs(ref).reshape(g.nv, -1).max(axis=1)[:, None, None]
+                umax = np.abs(ref).reshape(g.nv, -1).max(axis=1)[(slice(None),) + (None,) * g.ndim]
                 assert np.all(np.abs(got - ref) <= 32 * _EPS[prec] * dt_gpu * S + 8 * _EPS["fp64"] * umax), (prec, st)
             announce(f"    sampled boxes: relative L1 {num / den:.2e}")
             assert num / den < tol, (prec, num / den)
