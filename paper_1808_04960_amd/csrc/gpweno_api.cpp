@@ -1040,6 +1040,9 @@ int batch_update_grids(gpweno_batch* b) {
 }
 
 int batch_capture(gpweno_batch* b) {
+    // the old graph may still be running on the stream it was launched on; an
+    // executable graph is destroyed only once no launch of it is in flight
+    if (b->graph && b->last_stream) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
     batch_drop_graph(b);
     std::vector<std::pair<int, int>> order;   // launch order: step position, then group
     int kmax = 0;

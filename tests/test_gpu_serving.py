@@ -145,7 +145,7 @@ def test_set_changes_reuse_the_captured_step_graph():
     the batch's device work tables by stream-ordered copies, the captured step
     graph keeps serving it (one capture for one kind of problem), and every
     problem's result is bitwise its solo result. A new kind (R = 3) adds one
-    capture."""
+    capture, and set changes within those two kinds again keep the graph."""
     announce("set changes without recapture")
     stream = torch.cuda.Stream()
 
@@ -174,11 +174,50 @@ def test_set_changes_reuse_the_captured_step_graph():
     assert b.captures() == 2
     _, _, ns, err = b.status()
     assert list(ns) == [15, 10, 4] and not err.any()
-    for s, (g, U, R, limit) in ((a0, ia0), (a1, ia1), (a2, ia2), (c0, ic0), (d3, id3)):
+    e3, ie3 = mk(56, 6, R=3)
+    f2, if2 = mk(88, 3)
+    b.set([c0, e3, f2, a1])      # d3 finished and left, e3 and f2 joined
+    b.run(6)
+    assert b.captures() == 2
+    _, _, ns, err = b.status()
+    assert list(ns) == [10, 6, 3, 15] and not err.any()
+    for s, (g, U, R, limit) in ((a0, ia0), (a1, ia1), (a2, ia2), (c0, ic0), (d3, id3), (e3, ie3), (f2, if2)):
         ref = gw.Solver(g, R, 12 * g.dx[0], 3 * g.dx[0], precision="fp32", U0=U)
         ref.run(1e30, max_steps=limit)
         assert s.time()[2] == limit
         assert np.array_equal(s.get_state(), ref.get_state()), (g.n, R)
+    b.close()
+
+
+def test_new_kinds_join_while_the_step_graph_runs():
+    """Kinds join a batch whose step graph was launched and not waited for, so
+    each new kind replaces a graph that may still be running: the old graph
+    must finish first, and every problem's result is bitwise its solo result."""
+    announce("new kinds while the step graph runs")
+    stream = torch.cuda.Stream()
+
+    def mk(n, limit, R, prec="fp32"):
+        g, U = inputs.isentropic_vortex_2d(n)
+        dx = g.dx[0]
+        s = gw.Solver(g, R, 12 * dx, 3 * dx, precision=prec, U0=U, stream=stream)
+        s.set_end(1e30, limit)
+        return s, (g, U, R, limit, prec)
+
+    probs = [mk(64, 30, 1), mk(72, 30, 2)]
+    b = gw.Batch(stream)
+    b.set([p for p, _ in probs])
+    b.run(10)
+    for extra, k in ((mk(56, 20, 3), 10), (mk(64, 12, 2, "fp64"), 10), (mk(48, 9, 1, "fp64"), 12)):
+        probs.append(extra)
+        b.set([p for p, _ in probs])
+        b.run(k)
+    assert b.captures() == 4
+    _, _, ns, err = b.status()
+    assert list(ns) == [30, 30, 20, 12, 9] and not err.any()
+    for s, (g, U, R, limit, prec) in probs:
+        ref = gw.Solver(g, R, 12 * g.dx[0], 3 * g.dx[0], precision=prec, U0=U)
+        ref.run(1e30, max_steps=limit)
+        assert np.array_equal(s.get_state(), ref.get_state()), (g.n, R, prec)
     b.close()
 
 
