@@ -1,0 +1,101 @@
+"""Right-hand-side parity over seeded random configurations (GPU against the
+CPU oracle, per cell): dimension, axis lengths (ragged runs and pencil groups,
+axes down to a few cells), cell aspect ratio, boundary kind per side
+(periodic, outflow, reflecting), stencil radius, scheme with GP indicators of
+zero mean (GP-WENO, WENO-GP, adaptive-order GP), flux-correction terms, GP
+length scales and precision, each on smooth random data of moderate or large
+amplitude. Every configuration must meet the per-cell bound of parity_bounds
+(32 eps of the largest face flux within reach).
+
+GP-AO keeps the normalisation (log-det) constants of its indicators, which are
+negative for sigma above about 1.6 dx (the 7-point one: -1.3 at 1.8 dx, -9.6
+at 3 dx), so eps + beta vanishes where the data's fit term equals minus that
+constant, and the weights 1/(eps + beta)^2 then amplify any rounding of the
+data without bound: the oracle's own result moves by as much under relative
+perturbations of its data of the sweep's eps. There a cell may also differ by
+four times that spread (8 perturbations of every value by eps times a
+uniform number in [-1, 1])."""
+import sys
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from parity_bounds import EPS, local_flux_scale
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU containers
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_1808_04960_amd as gw  # noqa: E402
+
+NCASES = 36
+MAX_N = {1: 150, 2: 70, 3: 24}
+
+
+def announce(msg):
+    print(f"[gpu-random] {msg}", file=sys.stderr, flush=True)
+
+
+def draw(i):
+    rng = np.random.default_rng(7000 + i)
+    ndim = int(rng.integers(1, 4))
+    scheme = ["gp-weno", "weno-gp", "gp-ao"][int(rng.integers(0, 3))]
+    R = int(rng.integers(2, 4)) if scheme == "gp-ao" else int(rng.integers(1, 4))
+    nc = 3 if scheme != "gp-ao" and rng.random() < 0.35 else 2
+    prec = ["fp64", "fp32"][int(rng.integers(0, 2))]
+    n, bc, hi = [], [], []
+    h = 1.0 / 64
+    for d in range(ndim):
+        if rng.random() < 0.5:
+            b = (inputs.PERIODIC, inputs.PERIODIC)
+            lo_n = 2
+        else:
+            b = tuple(int(x) for x in rng.choice([inputs.OUTFLOW, inputs.REFLECT], size=2))
+            lo_n = R + 1 + nc
+        nd = int(rng.integers(lo_n, MAX_N[ndim] + 1))
+        n.append(nd)
+        bc.append(b)
+        hi.append(nd * h * float(rng.uniform(1.0, 1.5)))   # cells up to 1.5 : 1
+    if ndim == 1:
+        g = inputs.grid1d(n[0], 0.0, hi[0], bc)
+    elif ndim == 2:
+        g = inputs.grid2d(n[0], n[1], (0.0, 0.0), tuple(hi), bc)
+    else:
+        g = inputs.grid3d(n[0], n[1], n[2], (0.0, 0.0, 0.0), tuple(hi), bc)
+    dxmax = max(g.dx[:ndim])
+    ell = float(rng.uniform(6.0, 16.0)) * dxmax
+    sigma = float(rng.uniform(2.0, 3.5)) * dxmax
+    amp = float(rng.choice([0.1, 0.25]))
+    U = inputs.random_smooth(g, seed=9000 + i, amp=amp)
+    return dict(g=g, U=U, R=R, scheme=scheme, nc=nc, prec=prec, ell=ell, sigma=sigma, amp=amp)
+
+
+@pytest.mark.parametrize("i", range(NCASES))
+def test_random_configuration_rhs_matches_oracle(i):
+    c = draw(i)
+    g = c["g"]
+    announce(f"case {i}: ndim={g.ndim} n={g.n[:g.ndim]} bc={g.bc[:g.ndim]} R={c['R']} {c['scheme']} "
+             f"nc={c['nc']} {c['prec']} ell/dx={c['ell'] / max(g.dx[:g.ndim]):.1f} amp={c['amp']}")
+    o = oracle.OracleSolver(g, c["R"], c["ell"], c["sigma"], scheme=c["scheme"], flux_corr_terms=c["nc"])
+    ref = o.rhs(c["U"])
+    s = gw.Solver(g, c["R"], c["ell"], c["sigma"], precision=c["prec"], U0=c["U"], scheme=c["scheme"],
+                  flux_corr_terms=c["nc"])
+    try:
+        got = s.rhs(c["U"])
+    finally:
+        s.close()
+    bound = 32 * EPS[c["prec"]] * local_flux_scale(g, c["U"], c["R"] + 1 + c["nc"])[None]
+    if c["scheme"] == "gp-ao":
+        rng = np.random.default_rng(11 + i)
+        spread = np.zeros_like(ref)
+        for _ in range(8):
+            Up = c["U"] * (1.0 + EPS[c["prec"]] * rng.uniform(-1.0, 1.0, c["U"].shape))
+            spread = np.maximum(spread, np.abs(o.rhs(Up) - ref))
+        bound = bound + 4 * spread
+    cell = float((np.abs(got - ref) / bound).max())
+    announce(f"  worst cell {cell:.3f} of the per-cell bound")
+    assert cell <= 1.0
