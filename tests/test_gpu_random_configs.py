@@ -137,3 +137,87 @@ def test_random_configuration_steps_match_oracle(i):
     announce(f"  rel L1 {err:.2e}, worst cell {cell:.3f} of the per-cell bound, t {t:.6e} vs {to:.6e}")
     assert err < tol
     assert cell <= 1.0
+
+
+def draw_problem(rng, stream):
+    """A small random problem for a batch: any dimension, scheme, indicator
+    mean, correction terms, boundaries, precision and positivity option."""
+    ndim = int(rng.integers(1, 4))
+    scheme = ["gp-weno", "weno-js", "weno-gp", "gp-ao"][int(rng.integers(0, 4))]
+    R = {"weno-js": int(rng.integers(1, 3)), "gp-ao": int(rng.integers(2, 4))}.get(scheme, int(rng.integers(1, 4)))
+    gp_ind = scheme in ("gp-weno", "weno-gp")
+    nzm = gp_ind and rng.random() < 0.3
+    nc = 3 if gp_ind and not nzm and rng.random() < 0.3 else 2
+    prec = ["fp64", "fp32"][int(rng.integers(0, 2))]
+    maxn = {1: 90, 2: 36, 3: 14}[ndim]
+    n, bc = [], []
+    for d in range(ndim):
+        if rng.random() < 0.5:
+            bc.append((inputs.PERIODIC, inputs.PERIODIC))
+            n.append(int(rng.integers(2, maxn + 1)))
+        else:
+            bc.append(tuple(int(x) for x in rng.choice([inputs.OUTFLOW, inputs.REFLECT], size=2)))
+            n.append(int(rng.integers(R + 1 + nc, maxn + 1)))
+    h = 1.0 / 64
+    hi = [nd * h for nd in n]                      # square cells: one table set per kind
+    if ndim == 1:
+        g = inputs.grid1d(n[0], 0.0, hi[0], bc)
+    elif ndim == 2:
+        g = inputs.grid2d(n[0], n[1], (0.0, 0.0), tuple(hi), bc)
+    else:
+        g = inputs.grid3d(n[0], n[1], n[2], (0.0, 0.0, 0.0), tuple(hi), bc)
+    U = inputs.random_smooth(g, seed=int(rng.integers(0, 1 << 30)))
+    rho, vel, p = inputs.cons_to_prim(g, U, 1.4)
+    U = inputs.prim_to_cons(g, rho, [v / 3 for v in vel], p, 1.4)
+    opts = dict(precision=prec, scheme=scheme, nonzero_mean=nzm, flux_corr_terms=nc,
+                positivity_fallback=bool(rng.random() < 0.3))
+    sigma = (1.8 if scheme == "gp-ao" else 3.0) * h
+    return g, U, R, 12 * h, sigma, opts
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_random_batch_mixes_are_bitwise_single(seed):
+    """Random sets of small problems of every kind the batch groups (dimension,
+    scheme, indicator mean, correction terms, boundaries, precision) join and
+    leave a batch between runs, some before they reach their step limit; every
+    problem ends bitwise equal to its own single-problem run of the steps it
+    took."""
+    rng = np.random.default_rng(500 + seed)
+    stream = torch.cuda.Stream()
+    b = gw.Batch(stream)
+    probs = []          # (solver, (g, U, R, ell, sigma, opts), limit)
+
+    def admit(k, room):
+        for _ in range(k):
+            g, U, R, ell, sigma, opts = draw_problem(rng, stream)
+            limit = int(rng.integers(2, room + 1))
+            s = gw.Solver(g, R, ell, sigma, U0=U, stream=stream, **opts)
+            s.set_end(1e30, limit)
+            probs.append((s, (g, U, R, ell, sigma, opts), limit))
+
+    runs = [6, 5, 7]
+    admit(7, sum(runs))
+    active = list(range(len(probs)))
+    for r, k in enumerate(runs):
+        if r > 0:
+            # some leave, new ones join with limits that fit the runs left
+            active = [j for j in active if rng.random() < 0.6]
+            before = len(probs)
+            admit(int(rng.integers(2, 5)), sum(runs[r:]))
+            active += list(range(before, len(probs)))
+        announce(f"mix {seed}, run {r}: {len(active)} problems, "
+                 f"{len({(p[1][0].ndim, p[1][2], p[1][5]['precision'], p[1][5]['scheme']) for p in (probs[j] for j in active)})} kinds")
+        b.set([probs[j][0] for j in active])
+        b.run(k)
+    b.status()
+    try:
+        for s, (g, U, R, ell, sigma, opts), limit in probs:
+            done = s.time()[2]
+            assert 1 <= done <= limit and not s.failure()[0]
+            ref = gw.Solver(g, R, ell, sigma, U0=U, **opts)
+            ref.run(1e30, max_steps=done)
+            assert ref.time()[2] == done
+            assert np.array_equal(s.get_state(), ref.get_state()), (g.n, R, opts)
+            ref.close()
+    finally:
+        b.close()
