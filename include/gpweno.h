@@ -361,12 +361,16 @@ int gpweno_batch_create(gpweno_batch **out);
  * kinds), ENOMEM, EHIP. */
 int gpweno_batch_set(gpweno_batch *b, gpweno_ctx *const *ctxs, int n, void *stream);
 
-/* Enqueues nsteps batched steps (nsteps >= 1) on stream by replaying a captured
- * graph of one batched step (captured on first use, and again only when the
- * kinds of problems in the set change). Every launch has one block per logical
- * block of its group; after a set change of the same kinds the grids of the
- * captured launches are updated in place on the instantiated graph before the
- * next replay. Errors: EINVAL, EHIP. */
+/* Enqueues nsteps batched steps (nsteps >= 1) on stream by replaying captured
+ * graphs of one batched step, one graph per kind of problem (captured on first
+ * use, and again only when the kinds of problems in the set change). With
+ * several kinds, each kind's graphs are replayed on a stream of the batch's
+ * own that waits for stream first and that stream then waits for, so kinds
+ * (which share no data) may run side by side while everything stays ordered
+ * on stream. Every launch has one block per logical block of its group; after
+ * a set change of the same kinds the grids of the captured launches are
+ * updated in place on the instantiated graphs before the next replay.
+ * Errors: EINVAL, EHIP. */
 int gpweno_batch_run(gpweno_batch *b, int nsteps, void *stream);
 
 /* Blocking: for every problem of the set, in set order, its time, last dt, step
@@ -374,14 +378,15 @@ int gpweno_batch_run(gpweno_batch *b, int nsteps, void *stream);
  * (each nullable). Errors: EINVAL, EHIP. */
 int gpweno_batch_status(gpweno_batch *b, double *t, double *dt, long *nsteps, int *err, void *stream);
 
-/* Number of times the batch has captured its step graph (instrumentation; -1
- * for NULL). A set change that keeps the kinds of problems (dimension, R,
+/* Number of times the batch has captured its step graphs (all kinds' graphs at
+ * once count as one capture; instrumentation; -1 for NULL). A set change that keeps the kinds of problems (dimension, R,
  * precision, scheme, boundary kinds, flux correction, tables) in the same order
  * does not add one, whatever the problems' sizes: the captured launches read
  * the set through the work tables, and their grids are updated in place. */
 long gpweno_batch_captures(const gpweno_batch *b);
 
-/* Waits for the batch's last stream and frees its resources. NULL is ignored. */
+/* Waits for the batch's last stream (and its per-kind streams) and frees its
+ * resources. NULL is ignored. */
 void gpweno_batch_destroy(gpweno_batch *b);
 
 /* Text of the last failure on this batch (NULL: the thread's last failure of

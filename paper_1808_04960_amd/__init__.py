@@ -409,7 +409,7 @@ class Batch:
         return t[:n], dt[:n], np.array(ns[:n], dtype=np.int64), np.array(er[:n], dtype=np.int32)
 
     def captures(self):
-        """Times the batch has captured its step graph."""
+        """Times the batch has captured its step graphs (one per kind, together)."""
         return lib().gpweno_batch_captures(self._b)
 
     def close(self):

@@ -872,6 +872,14 @@ constexpr int BATCH_MAX_GROUPS = 64;
 constexpr int DIR_PER_GROUP = 9;            // 3 stages x up to 3 directions
 constexpr int STAGING = 4;                  // pinned staging buffers in the ring
 
+// The captured step of one group: its 3 ndim launches as a chain.
+struct GroupGraph {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t src = nullptr;
+    std::vector<hipGraphNode_t> nodes;      // kernel nodes by step position
+    std::vector<hipKernelNodeParams> params;
+};
+
 // Problems sharing one kernel instantiation per launch and one set of tables.
 struct BatchGroup {
     int ndim = 0, R = 0, ik = 0, nc = 2;
@@ -930,14 +938,17 @@ struct gpweno_batch {
     hipEvent_t staging_done[STAGING] = {};
     bool staging_used[STAGING] = {};
     int staging_next = 0;
-    // captured batched step, what it was captured for, and its kernel nodes in
-    // launch order with their parameters (their grids follow the set)
-    hipGraphExec_t graph = nullptr;
-    hipGraph_t graph_src = nullptr;
+    // captured batched step: one graph per group (the group's launches of one
+    // step, a chain), the kinds they were captured for, and each graph's kernel
+    // nodes by step position with their parameters (their grids follow the set)
+    std::vector<GroupGraph> graphs;
     std::vector<BatchGroup> graph_groups;
-    std::vector<hipGraphNode_t> graph_nodes;
-    std::vector<hipKernelNodeParams> graph_params;
-    std::vector<std::pair<int, int>> graph_launch;   // (group, step position) of each node
+    bool nodes_ok = false;                   // every graph's nodes were found
+    // with more than one group, each group's graph runs on a stream of its own,
+    // forked from and joined back to the caller's stream
+    hipStream_t group_stream[BATCH_MAX_GROUPS] = {};
+    hipEvent_t group_join[BATCH_MAX_GROUPS] = {};
+    hipEvent_t group_fork = nullptr;
     long long recaptures = 0;
     bool dirty = true;                       // the set changed since the grids were applied
     std::string err;
@@ -963,18 +974,13 @@ int bfail(gpweno_batch* b, int code, const char* fmt, ...) {
     } while (0)
 
 void batch_drop_graph(gpweno_batch* b) {
-    if (b->graph) {
-        (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
+    for (auto& gg : b->graphs) {
+        if (gg.exec) (void)hipGraphExecDestroy(gg.exec);
+        if (gg.src) (void)hipGraphDestroy(gg.src);
     }
-    if (b->graph_src) {
-        (void)hipGraphDestroy(b->graph_src);
-        b->graph_src = nullptr;
-    }
+    b->graphs.clear();
     b->graph_groups.clear();
-    b->graph_nodes.clear();
-    b->graph_params.clear();
-    b->graph_launch.clear();
+    b->nodes_ok = false;
 }
 
 // One batched launch: step position k for group g (its work table entry
@@ -1018,7 +1024,7 @@ long long launch_grid(const BatchGroup& g, int k) {
 // same order (its launches read the sets through the work tables; their grids
 // are set per set by batch_update_grids).
 bool graph_serves(const gpweno_batch* b) {
-    if (!b->graph || b->graph_groups.size() != b->groups.size()) return false;
+    if (b->graphs.empty() || b->graph_groups.size() != b->groups.size()) return false;
     for (size_t i = 0; i < b->groups.size(); ++i)
         if (!same_kind(b->graph_groups[i], b->groups[i])) return false;
     return true;
@@ -1027,78 +1033,122 @@ bool graph_serves(const gpweno_batch* b) {
 // Sets the grid of every launch of the instantiated graph to the current set's
 // blocks (host-side; launches already enqueued keep the grids they had).
 int batch_update_grids(gpweno_batch* b) {
-    for (size_t i = 0; i < b->graph_nodes.size(); ++i) {
-        hipKernelNodeParams& p = b->graph_params[i];
-        const long long gr = launch_grid(b->groups[b->graph_launch[i].first], b->graph_launch[i].second);
-        if (gr > INT_MAX) return bfail(b, GPWENO_EINVAL, "batch too large");
-        if ((long long)p.gridDim.x == gr) continue;
-        p.gridDim.x = (unsigned)gr;
-        hipError_t e = hipGraphExecKernelNodeSetParams(b->graph, b->graph_nodes[i], &p);
-        if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "hipGraphExecKernelNodeSetParams: %s", hipGetErrorString(e));
+    for (size_t gi = 0; gi < b->graphs.size(); ++gi) {
+        GroupGraph& gg = b->graphs[gi];
+        for (size_t k = 0; k < gg.nodes.size(); ++k) {
+            hipKernelNodeParams& p = gg.params[k];
+            const long long gr = launch_grid(b->groups[gi], (int)k);
+            if (gr > INT_MAX) return bfail(b, GPWENO_EINVAL, "batch too large");
+            if ((long long)p.gridDim.x == gr) continue;
+            p.gridDim.x = (unsigned)gr;
+            hipError_t e = hipGraphExecKernelNodeSetParams(gg.exec, gg.nodes[k], &p);
+            if (e != hipSuccess)
+                return bfail(b, GPWENO_EHIP, "hipGraphExecKernelNodeSetParams: %s", hipGetErrorString(e));
+        }
     }
     return GPWENO_OK;
 }
 
+// Captures the batched step: for each group, its 3 ndim launches of one step
+// on the batch's own stream (a chain), instantiated, with its kernel nodes
+// found along the chain for the in-place grid updates.
 int batch_capture(gpweno_batch* b) {
-    // the old graph may still be running on the stream it was launched on; an
-    // executable graph is destroyed only once no launch of it is in flight
-    if (b->graph && b->last_stream) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
+    // the old graphs may still be running (on the stream they were last
+    // launched on, which waited for the group streams); an executable graph is
+    // destroyed only once no launch of it is in flight
+    if (!b->graphs.empty() && b->last_stream) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
     batch_drop_graph(b);
-    std::vector<std::pair<int, int>> order;   // launch order: step position, then group
-    int kmax = 0;
-    for (const auto& g : b->groups) kmax = std::max(kmax, 3 * g.ndim);
-    for (int k = 0; k < kmax; ++k)
-        for (size_t gi = 0; gi < b->groups.size(); ++gi)
-            if (k < 3 * b->groups[gi].ndim) order.emplace_back((int)gi, k);
-    BHIP_TRY(b, hipStreamBeginCapture(b->own_stream, hipStreamCaptureModeThreadLocal));
-    int st = GPWENO_OK;
-    for (const auto& [gi, k] : order) {
+    const size_t ng = b->groups.size();
+    if (ng > 1) {
+        if (!b->group_fork) BHIP_TRY(b, hipEventCreateWithFlags(&b->group_fork, hipEventDisableTiming));
+        for (size_t gi = 0; gi < ng; ++gi) {
+            if (!b->group_stream[gi])
+                BHIP_TRY(b, hipStreamCreateWithFlags(&b->group_stream[gi], hipStreamNonBlocking));
+            if (!b->group_join[gi]) BHIP_TRY(b, hipEventCreateWithFlags(&b->group_join[gi], hipEventDisableTiming));
+        }
+    }
+    bool nodes_ok = true;
+    for (size_t gi = 0; gi < ng; ++gi) {
         const BatchGroup& g = b->groups[gi];
-        if ((st = batch_launch(b, gi, g, k, launch_grid(g, k), b->own_stream))) break;
+        const int nk = 3 * g.ndim;
+        BHIP_TRY(b, hipStreamBeginCapture(b->own_stream, hipStreamCaptureModeThreadLocal));
+        int st = GPWENO_OK;
+        for (int k = 0; k < nk && !st; ++k) st = batch_launch(b, (int)gi, g, k, launch_grid(g, k), b->own_stream);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(b->own_stream, &gr);
+        if (st) {
+            if (gr) (void)hipGraphDestroy(gr);
+            batch_drop_graph(b);
+            return st;
+        }
+        if (e != hipSuccess) {
+            batch_drop_graph(b);
+            return bfail(b, GPWENO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        }
+        GroupGraph gg;
+        gg.src = gr;
+        e = hipGraphInstantiate(&gg.exec, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(gr);
+            batch_drop_graph(b);
+            return bfail(b, GPWENO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+        // the kernel nodes in launch order: the capture of one stream is a chain
+        // from its root; if the runtime does not expose it, set changes recapture
+        std::vector<hipGraphNode_t> chain;
+        size_t n = 1;
+        hipGraphNode_t node = nullptr;
+        bool ok = hipGraphGetRootNodes(gr, &node, &n) == hipSuccess && n == 1;
+        while (ok && node) {
+            chain.push_back(node);
+            hipGraphNode_t next = nullptr;
+            size_t m = 0;
+            ok = hipGraphNodeGetDependentNodes(node, nullptr, &m) == hipSuccess && m <= 1;
+            if (ok && m == 1) ok = hipGraphNodeGetDependentNodes(node, &next, &m) == hipSuccess;
+            node = m == 1 ? next : nullptr;
+        }
+        ok = ok && (int)chain.size() == nk;
+        std::vector<hipKernelNodeParams> params(chain.size());
+        for (size_t i = 0; ok && i < chain.size(); ++i) {
+            hipGraphNodeType t;
+            ok = hipGraphNodeGetType(chain[i], &t) == hipSuccess && t == hipGraphNodeTypeKernel &&
+                 hipGraphKernelNodeGetParams(chain[i], &params[i]) == hipSuccess &&
+                 (long long)params[i].gridDim.x == launch_grid(g, (int)i);
+        }
+        if (ok) {
+            gg.nodes = std::move(chain);
+            gg.params = std::move(params);
+        }
+        nodes_ok = nodes_ok && ok;
+        b->graphs.push_back(std::move(gg));
     }
-    hipGraph_t gr = nullptr;
-    hipError_t e = hipStreamEndCapture(b->own_stream, &gr);
-    if (st) {
-        if (gr) (void)hipGraphDestroy(gr);
-        return st;
-    }
-    if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&b->graph, gr, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        (void)hipGraphDestroy(gr);
-        b->graph = nullptr;
-        return bfail(b, GPWENO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    }
-    b->graph_src = gr;
     b->graph_groups = b->groups;
+    b->nodes_ok = nodes_ok;
     ++b->recaptures;
-    // the kernel nodes in launch order: the capture of one stream is a chain
-    // from its root; if the runtime does not expose it, set changes recapture
-    std::vector<hipGraphNode_t> chain;
-    size_t n = 1;
-    hipGraphNode_t node = nullptr;
-    bool ok = hipGraphGetRootNodes(gr, &node, &n) == hipSuccess && n == 1;
-    while (ok && node) {
-        chain.push_back(node);
-        hipGraphNode_t next = nullptr;
-        size_t m = 0;
-        ok = hipGraphNodeGetDependentNodes(node, nullptr, &m) == hipSuccess && m <= 1;
-        if (ok && m == 1) ok = hipGraphNodeGetDependentNodes(node, &next, &m) == hipSuccess;
-        node = m == 1 ? next : nullptr;
+    return GPWENO_OK;
+}
+
+// Enqueues nsteps batched steps on s: one group's graph directly on s; several
+// groups each on a stream of its own (forked from s, all joined back into s),
+// so that the groups' sweeps, which share no data, can run side by side.
+int batch_launch_steps(gpweno_batch* b, int nsteps, hipStream_t s) {
+    const size_t ng = b->graphs.size();
+    if (ng == 1) {
+        for (int i = 0; i < nsteps; ++i) BHIP_TRY(b, hipGraphLaunch(b->graphs[0].exec, s));
+        return GPWENO_OK;
     }
-    ok = ok && chain.size() == order.size();
-    std::vector<hipKernelNodeParams> params(chain.size());
-    for (size_t i = 0; ok && i < chain.size(); ++i) {
-        hipGraphNodeType t;
-        ok = hipGraphNodeGetType(chain[i], &t) == hipSuccess && t == hipGraphNodeTypeKernel &&
-             hipGraphKernelNodeGetParams(chain[i], &params[i]) == hipSuccess &&
-             (long long)params[i].gridDim.x == launch_grid(b->groups[order[i].first], order[i].second);
+    BHIP_TRY(b, hipEventRecord(b->group_fork, s));
+    hipError_t first = hipSuccess;
+    for (size_t gi = 0; gi < ng; ++gi) {
+        hipStream_t gs = b->group_stream[gi];
+        hipError_t e = hipStreamWaitEvent(gs, b->group_fork, 0);
+        for (int i = 0; e == hipSuccess && i < nsteps; ++i) e = hipGraphLaunch(b->graphs[gi].exec, gs);
+        // joined back even after a failure, so that s orders everything after it
+        hipError_t e1 = hipEventRecord(b->group_join[gi], gs);
+        if (e1 == hipSuccess) e1 = hipStreamWaitEvent(s, b->group_join[gi], 0);
+        if (first == hipSuccess) first = e != hipSuccess ? e : e1;
     }
-    if (ok) {
-        b->graph_nodes = chain;
-        b->graph_params = params;
-        b->graph_launch = order;
-    }
+    if (first != hipSuccess) return bfail(b, GPWENO_EHIP, "batched step launch: %s", hipGetErrorString(first));
     return GPWENO_OK;
 }
 
@@ -1320,7 +1370,7 @@ int gpweno_batch_run(gpweno_batch* b, int nsteps, void* stream) {
     if (b->set.empty()) return GPWENO_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (b->last_stream && b->last_stream != s) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
-    if (graph_serves(b) && (!b->dirty || !b->graph_nodes.empty())) {
+    if (graph_serves(b) && (!b->dirty || b->nodes_ok)) {
         if (b->dirty) {
             int st = batch_update_grids(b);
             if (st) return st;
@@ -1343,8 +1393,9 @@ int gpweno_batch_run(gpweno_batch* b, int nsteps, void* stream) {
         if (st) return st;
     }
     b->dirty = false;
-    for (int i = 0; i < nsteps; ++i) BHIP_TRY(b, hipGraphLaunch(b->graph, s));
+    int st = batch_launch_steps(b, nsteps, s);
     b->last_stream = s;
+    if (st) return st;
     return GPWENO_OK;
 }
 
@@ -1372,6 +1423,8 @@ void gpweno_batch_destroy(gpweno_batch* b) {
     if (!b) return;
     if (b->last_stream) (void)hipStreamSynchronize(b->last_stream);
     if (b->own_stream) (void)hipStreamSynchronize(b->own_stream);
+    for (int i = 0; i < BATCH_MAX_GROUPS; ++i)
+        if (b->group_stream[i]) (void)hipStreamSynchronize(b->group_stream[i]);
     batch_drop_graph(b);
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_owner) (void)hipFree(b->d_owner);
@@ -1383,6 +1436,11 @@ void gpweno_batch_destroy(gpweno_batch* b) {
         if (b->staging[i]) (void)hipHostFree(b->staging[i]);
         if (b->staging_done[i]) (void)hipEventDestroy(b->staging_done[i]);
     }
+    for (int i = 0; i < BATCH_MAX_GROUPS; ++i) {
+        if (b->group_stream[i]) (void)hipStreamDestroy(b->group_stream[i]);
+        if (b->group_join[i]) (void)hipEventDestroy(b->group_join[i]);
+    }
+    if (b->group_fork) (void)hipEventDestroy(b->group_fork);
     if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
     delete b;
 }

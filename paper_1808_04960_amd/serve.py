@@ -5,11 +5,12 @@ when a slot is free and its HBM footprint (state plus stage workspace) fits the
 budget. Admitted problems stay resident on the device. The scheduler advances all
 of them together, a few steps per tick: each step is one batched launch per sweep
 and per group of problems of one kind (dimension, R, precision, tables;
-``gpweno_batch_run``, replayed from a captured graph).
+``gpweno_batch_run``, replayed from captured graphs, one per kind, the kinds
+on streams of their own so that they run side by side).
 A problem that reaches its step count is copied back and its memory released,
 which lets the next waiting requests in while the others keep running.
 
-The batch's step graph is captured once per set of problem kinds: admitting or
+The batch's step graphs are captured once per set of problem kinds: admitting or
 retiring a problem rewrites the batch's device work tables with stream-ordered
 copies, and a new problem's initial state is uploaded on a stream of its own,
 so neither waits for the batches in flight. The host waits once per tick, for

@@ -223,8 +223,8 @@ def test_new_kinds_join_while_the_step_graph_runs():
 
 def test_batch_mixing_dimensions_precisions_and_sizes_is_bitwise_single():
     """One batch holding 1D, 2D and 3D problems in both precisions, including
-    axes of a few cells: each kind is its own group, the captured step graph
-    interleaves groups with 3, 6 and 9 launches per step, and a set change that
+    axes of a few cells: each kind is its own group with its own step graph
+    (3, 6 and 9 launches per step) on its own stream, and a set change that
     swaps problems for larger or smaller ones of the same kinds only updates the
     launch grids. Every problem is bitwise its solo run."""
     announce("batch mixing dimensions, precisions and sizes")
