@@ -13,8 +13,10 @@ which lets the next waiting requests in while the others keep running.
 The batch's step graphs are captured once per set of problem kinds: admitting or
 retiring a problem rewrites the batch's device work tables with stream-ordered
 copies, and a new problem's initial state is uploaded on a stream of its own,
-so neither waits for the batches in flight. The host waits once per tick, for
-the progress poll.
+so neither waits for the batches in flight. A finished problem's result is
+copied back on a stream of its own too, while the next steps run; the request
+completes (and its memory is released) once the copy has landed. The host waits
+once per tick, for the progress poll.
 
 Admission is first-in first-out: a request that does not fit blocks the ones
 behind it (no starvation of large problems). A request larger than the whole
@@ -64,6 +66,20 @@ class Job:
     @property
     def latency(self) -> float:
         return self.finished - self.req.arrival
+
+
+class PendingResult:
+    """A result still being copied to the host: ``done()`` polls, ``value()``
+    waits for it and returns it, ``release()`` frees what it holds."""
+
+    def done(self) -> bool:  # pragma: no cover - interface
+        raise NotImplementedError
+
+    def value(self):  # pragma: no cover - interface
+        raise NotImplementedError
+
+    def release(self):  # pragma: no cover - interface
+        pass
 
 
 @dataclasses.dataclass
@@ -116,7 +132,26 @@ class Server:
         cell_updates = 0.0
         t0 = ex.now()
         first_arrival = jobs[0].req.arrival if jobs else 0.0
-        while pending or waiting or active:
+        finishing = []   # (job, PendingResult): done on the device, result on its way
+
+        def land(block):
+            """Completes the jobs whose results have arrived (all of them if
+            block); returns the footprint released."""
+            nonlocal finishing
+            freed, rest = 0, []
+            for j, r in finishing:
+                if block or r.done():
+                    j.result = r.value()
+                    r.release()
+                    j.finished = ex.now() - t0
+                    freed += j.footprint
+                else:
+                    rest.append((j, r))
+            finishing = rest
+            return freed
+
+        while pending or waiting or active or finishing:
+            used -= land(False)
             now = ex.now() - t0
             while pending and pending[0].req.arrival <= now:
                 j = pending.pop(0)
@@ -147,7 +182,9 @@ class Server:
                 for j in refused:
                     used -= self._fail(j, ex.now() - t0)
             if not active:
-                if pending:
+                if finishing:
+                    used -= land(True)
+                elif pending:
                     ex.idle_until(t0 + pending[0].req.arrival)
                 continue
             ex.advance(self.k)
@@ -158,12 +195,16 @@ class Server:
                 cell_updates += (int(n) - j.steps_done) * 3.0 * j.req.cells
                 j.steps_done = int(n)
                 if e or n >= j.req.steps:
-                    j.result = ex.retire(j.handle, keep_results and not e)
+                    res = ex.retire(j.handle, keep_results and not e)
                     j.handle = None
                     j.status = "failed" if e else "done"
-                    j.finished = ex.now() - t0
-                    used -= j.footprint
                     retired.append(j)
+                    if isinstance(res, PendingResult):
+                        finishing.append((j, res))
+                    else:
+                        j.result = res
+                        j.finished = ex.now() - t0
+                        used -= j.footprint
             if retired:
                 active = [j for j in active if j.handle is not None]
                 active, refused = self._set_active(active)
@@ -218,6 +259,7 @@ class GpuExecutor:
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self.stream = torch.cuda.Stream(self.device)
         self.upload = torch.cuda.Stream(self.device)
+        self.copy = torch.cuda.Stream(self.device)
         self.batch = Batch(self.stream)
 
     def now(self):
@@ -254,14 +296,45 @@ class GpuExecutor:
         return ns, err
 
     def retire(self, handle, keep):
-        out = handle.get_state() if keep else None
+        """Called while the stream is idle (right after the progress poll). The
+        context goes at once; with keep, the state is copied into pinned host
+        memory on the copy stream, behind everything enqueued so far, and the
+        returned PendingResult holds the device state until the copy is done."""
+        torch = self.torch
         handle.close()
-        handle.state = None
         handle.workspace = None
-        return out
+        if not keep:
+            handle.state = None
+            return None
+        state = handle.state
+        handle.state = None
+        host = torch.empty(state.shape, dtype=state.dtype, pin_memory=True)
+        self.copy.wait_stream(self.stream)
+        with torch.cuda.stream(self.copy):
+            host.copy_(state, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(self.copy)
+        return _CopyBack(state, host, ev)
 
     def close(self):
         self.batch.close()
+
+
+class _CopyBack(PendingResult):
+    """A finished problem's state on its way to pinned host memory."""
+
+    def __init__(self, state, host, event):
+        self.state, self.host, self.event = state, host, event
+
+    def done(self):
+        return self.event.query()
+
+    def value(self):
+        self.event.synchronize()
+        return self.host.numpy()
+
+    def release(self):
+        self.state = None
 
 
 class SimExecutor:

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import inputs
-from paper_1808_04960_amd.serve import Server, SimExecutor, footprint_bytes
+from paper_1808_04960_amd.serve import PendingResult, Server, SimExecutor, footprint_bytes
 
 
 @dataclasses.dataclass
@@ -158,3 +158,58 @@ def test_a_request_the_batch_refuses_fails_alone():
     assert st == {0: "done", 1: "done", 2: "done", 3: "failed", 4: "done"}
     assert rep.jobs[3].steps_done == 0 and "refused" in rep.jobs[3].error
     assert 3 not in ex.ever_active and {0, 1, 2, 4} <= ex.ever_active
+
+
+class _SlowCopy(PendingResult):
+    """A result that arrives after a fixed number of polls, with its bytes
+    still held until then."""
+
+    def __init__(self, ex, rid, polls):
+        self.ex, self.rid, self.left = ex, rid, polls
+        ex.held.add(rid)
+
+    def done(self):
+        self.left -= 1
+        return self.left <= 0
+
+    def value(self):
+        return ("result", self.rid)
+
+    def release(self):
+        self.ex.held.discard(self.rid)
+
+
+class _CopyingExecutor(_Recorder):
+    """Retires with results still on their way (copied back while the next
+    steps run), as the GPU executor does."""
+
+    def __init__(self, *a, **k):
+        super().__init__(*a, **k)
+        self.held = set()
+        self.max_bytes = 0
+
+    def retire(self, handle, keep):
+        return _SlowCopy(self, handle.req.rid, 3) if keep else None
+
+    def advance(self, k):
+        held = sum(footprint_bytes(_Req(r, 0.0, self.sizes[r], 1).grid) for r in self.held)
+        used = sum(footprint_bytes(h.req.grid) for h in self.active)
+        self.max_bytes = max(self.max_bytes, used + held)
+        super().advance(k)
+
+
+def test_results_still_on_their_way_hold_their_memory_until_they_land():
+    """A job completes when its result has landed: its latency includes the
+    copy, its footprint stays counted until then (resident plus still-held
+    bytes never exceed the budget), and every result lands before run ends."""
+    reqs = [_Req(i, 0.0005 * i, n, steps) for i, (n, steps) in
+            enumerate([(128, 12), (96, 20), (128, 8), (64, 30), (96, 16), (128, 10)])]
+    budget = 2 * footprint_bytes(inputs.grid2d(128, 128)) + 1
+    ex = _CopyingExecutor(rate=2e9)
+    ex.sizes = {r.rid: r.n for r in reqs}
+    rep = Server(ex, hbm_budget=budget, max_slots=8, steps_per_tick=4).run(reqs, keep_results=True)
+    assert all(j.status == "done" and j.result == ("result", j.req.rid) for j in rep.jobs)
+    assert not ex.held
+    assert ex.max_bytes <= budget
+    for j in rep.jobs:
+        assert j.finished > j.admitted
