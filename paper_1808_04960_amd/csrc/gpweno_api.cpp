@@ -872,12 +872,20 @@ constexpr int BATCH_MAX_GROUPS = 64;
 constexpr int DIR_PER_GROUP = 9;            // 3 stages x up to 3 directions
 constexpr int STAGING = 4;                  // pinned staging buffers in the ring
 
-// The captured step of one group: its 3 ndim launches as a chain.
-struct GroupGraph {
+// Captured batched steps of one group: its 3 ndim launches per step as a
+// chain, for BATCH_GRAPH_STEPS[i] steps; a run of n steps replays them largest
+// first (8 steps per graph launch instead of one: fewer host calls and gaps).
+constexpr int BATCH_GRAPH_STEPS[2] = {8, 1};
+
+struct StepGraph {
     hipGraphExec_t exec = nullptr;
     hipGraph_t src = nullptr;
-    std::vector<hipGraphNode_t> nodes;      // kernel nodes by step position
+    std::vector<hipGraphNode_t> nodes;      // kernel nodes in launch order
     std::vector<hipKernelNodeParams> params;
+};
+
+struct GroupGraph {
+    StepGraph by_steps[2];                  // BATCH_GRAPH_STEPS[i] steps each
 };
 
 // Problems sharing one kernel instantiation per launch and one set of tables.
@@ -974,10 +982,11 @@ int bfail(gpweno_batch* b, int code, const char* fmt, ...) {
     } while (0)
 
 void batch_drop_graph(gpweno_batch* b) {
-    for (auto& gg : b->graphs) {
-        if (gg.exec) (void)hipGraphExecDestroy(gg.exec);
-        if (gg.src) (void)hipGraphDestroy(gg.src);
-    }
+    for (auto& gg : b->graphs)
+        for (auto& sg : gg.by_steps) {
+            if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
+            if (sg.src) (void)hipGraphDestroy(sg.src);
+        }
     b->graphs.clear();
     b->graph_groups.clear();
     b->nodes_ok = false;
@@ -1034,24 +1043,74 @@ bool graph_serves(const gpweno_batch* b) {
 // blocks (host-side; launches already enqueued keep the grids they had).
 int batch_update_grids(gpweno_batch* b) {
     for (size_t gi = 0; gi < b->graphs.size(); ++gi) {
-        GroupGraph& gg = b->graphs[gi];
-        for (size_t k = 0; k < gg.nodes.size(); ++k) {
-            hipKernelNodeParams& p = gg.params[k];
-            const long long gr = launch_grid(b->groups[gi], (int)k);
-            if (gr > INT_MAX) return bfail(b, GPWENO_EINVAL, "batch too large");
-            if ((long long)p.gridDim.x == gr) continue;
-            p.gridDim.x = (unsigned)gr;
-            hipError_t e = hipGraphExecKernelNodeSetParams(gg.exec, gg.nodes[k], &p);
-            if (e != hipSuccess)
-                return bfail(b, GPWENO_EHIP, "hipGraphExecKernelNodeSetParams: %s", hipGetErrorString(e));
-        }
+        const int nk = 3 * b->groups[gi].ndim;
+        for (StepGraph& sg : b->graphs[gi].by_steps)
+            for (size_t i = 0; i < sg.nodes.size(); ++i) {
+                hipKernelNodeParams& p = sg.params[i];
+                const long long gr = launch_grid(b->groups[gi], (int)(i % nk));
+                if (gr > INT_MAX) return bfail(b, GPWENO_EINVAL, "batch too large");
+                if ((long long)p.gridDim.x == gr) continue;
+                p.gridDim.x = (unsigned)gr;
+                hipError_t e = hipGraphExecKernelNodeSetParams(sg.exec, sg.nodes[i], &p);
+                if (e != hipSuccess)
+                    return bfail(b, GPWENO_EHIP, "hipGraphExecKernelNodeSetParams: %s", hipGetErrorString(e));
+            }
     }
     return GPWENO_OK;
 }
 
-// Captures the batched step: for each group, its 3 ndim launches of one step
-// on the batch's own stream (a chain), instantiated, with its kernel nodes
-// found along the chain for the in-place grid updates.
+// Captures one group's launches of `steps` batched steps on the batch's own
+// stream (a chain), instantiates it and finds its kernel nodes along the chain
+// for the in-place grid updates (nodes_ok false if the runtime does not expose
+// them; set changes then recapture).
+int capture_steps(gpweno_batch* b, int gi, int steps, StepGraph& sg, bool& nodes_ok) {
+    const BatchGroup& g = b->groups[gi];
+    const int nk = 3 * g.ndim;
+    BHIP_TRY(b, hipStreamBeginCapture(b->own_stream, hipStreamCaptureModeThreadLocal));
+    int st = GPWENO_OK;
+    for (int i = 0; i < steps * nk && !st; ++i) st = batch_launch(b, gi, g, i % nk, launch_grid(g, i % nk), b->own_stream);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(b->own_stream, &gr);
+    if (st) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return st;
+    }
+    if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    sg.src = gr;
+    e = hipGraphInstantiate(&sg.exec, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        sg.exec = nullptr;
+        return bfail(b, GPWENO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    std::vector<hipGraphNode_t> chain;
+    size_t n = 1;
+    hipGraphNode_t node = nullptr;
+    bool ok = hipGraphGetRootNodes(gr, &node, &n) == hipSuccess && n == 1;
+    while (ok && node) {
+        chain.push_back(node);
+        hipGraphNode_t next = nullptr;
+        size_t m = 0;
+        ok = hipGraphNodeGetDependentNodes(node, nullptr, &m) == hipSuccess && m <= 1;
+        if (ok && m == 1) ok = hipGraphNodeGetDependentNodes(node, &next, &m) == hipSuccess;
+        node = m == 1 ? next : nullptr;
+    }
+    ok = ok && (int)chain.size() == steps * nk;
+    std::vector<hipKernelNodeParams> params(chain.size());
+    for (size_t i = 0; ok && i < chain.size(); ++i) {
+        hipGraphNodeType t;
+        ok = hipGraphNodeGetType(chain[i], &t) == hipSuccess && t == hipGraphNodeTypeKernel &&
+             hipGraphKernelNodeGetParams(chain[i], &params[i]) == hipSuccess &&
+             (long long)params[i].gridDim.x == launch_grid(g, (int)(i % nk));
+    }
+    if (ok) {
+        sg.nodes = std::move(chain);
+        sg.params = std::move(params);
+    }
+    nodes_ok = nodes_ok && ok;
+    return GPWENO_OK;
+}
+
+// Captures the batched step graphs of every group (BATCH_GRAPH_STEPS steps each).
 int batch_capture(gpweno_batch* b) {
     // the old graphs may still be running (on the stream they were last
     // launched on, which waited for the group streams); an executable graph is
@@ -1068,64 +1127,29 @@ int batch_capture(gpweno_batch* b) {
         }
     }
     bool nodes_ok = true;
-    for (size_t gi = 0; gi < ng; ++gi) {
-        const BatchGroup& g = b->groups[gi];
-        const int nk = 3 * g.ndim;
-        BHIP_TRY(b, hipStreamBeginCapture(b->own_stream, hipStreamCaptureModeThreadLocal));
-        int st = GPWENO_OK;
-        for (int k = 0; k < nk && !st; ++k) st = batch_launch(b, (int)gi, g, k, launch_grid(g, k), b->own_stream);
-        hipGraph_t gr = nullptr;
-        hipError_t e = hipStreamEndCapture(b->own_stream, &gr);
-        if (st) {
-            if (gr) (void)hipGraphDestroy(gr);
-            batch_drop_graph(b);
-            return st;
+    b->graphs.resize(ng);
+    for (size_t gi = 0; gi < ng; ++gi)
+        for (int i = 0; i < 2; ++i) {
+            int st = capture_steps(b, (int)gi, BATCH_GRAPH_STEPS[i], b->graphs[gi].by_steps[i], nodes_ok);
+            if (st) {
+                batch_drop_graph(b);
+                return st;
+            }
         }
-        if (e != hipSuccess) {
-            batch_drop_graph(b);
-            return bfail(b, GPWENO_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-        }
-        GroupGraph gg;
-        gg.src = gr;
-        e = hipGraphInstantiate(&gg.exec, gr, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            (void)hipGraphDestroy(gr);
-            batch_drop_graph(b);
-            return bfail(b, GPWENO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-        }
-        // the kernel nodes in launch order: the capture of one stream is a chain
-        // from its root; if the runtime does not expose it, set changes recapture
-        std::vector<hipGraphNode_t> chain;
-        size_t n = 1;
-        hipGraphNode_t node = nullptr;
-        bool ok = hipGraphGetRootNodes(gr, &node, &n) == hipSuccess && n == 1;
-        while (ok && node) {
-            chain.push_back(node);
-            hipGraphNode_t next = nullptr;
-            size_t m = 0;
-            ok = hipGraphNodeGetDependentNodes(node, nullptr, &m) == hipSuccess && m <= 1;
-            if (ok && m == 1) ok = hipGraphNodeGetDependentNodes(node, &next, &m) == hipSuccess;
-            node = m == 1 ? next : nullptr;
-        }
-        ok = ok && (int)chain.size() == nk;
-        std::vector<hipKernelNodeParams> params(chain.size());
-        for (size_t i = 0; ok && i < chain.size(); ++i) {
-            hipGraphNodeType t;
-            ok = hipGraphNodeGetType(chain[i], &t) == hipSuccess && t == hipGraphNodeTypeKernel &&
-                 hipGraphKernelNodeGetParams(chain[i], &params[i]) == hipSuccess &&
-                 (long long)params[i].gridDim.x == launch_grid(g, (int)i);
-        }
-        if (ok) {
-            gg.nodes = std::move(chain);
-            gg.params = std::move(params);
-        }
-        nodes_ok = nodes_ok && ok;
-        b->graphs.push_back(std::move(gg));
-    }
     b->graph_groups = b->groups;
     b->nodes_ok = nodes_ok;
     ++b->recaptures;
     return GPWENO_OK;
+}
+
+// Replays nsteps batched steps of one group on stream gs, largest graphs first.
+hipError_t replay_steps(const GroupGraph& gg, int nsteps, hipStream_t gs) {
+    hipError_t e = hipSuccess;
+    int left = nsteps;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+        for (; left >= BATCH_GRAPH_STEPS[i] && e == hipSuccess; left -= BATCH_GRAPH_STEPS[i])
+            e = hipGraphLaunch(gg.by_steps[i].exec, gs);
+    return e;
 }
 
 // Enqueues nsteps batched steps on s: one group's graph directly on s; several
@@ -1134,7 +1158,7 @@ int batch_capture(gpweno_batch* b) {
 int batch_launch_steps(gpweno_batch* b, int nsteps, hipStream_t s) {
     const size_t ng = b->graphs.size();
     if (ng == 1) {
-        for (int i = 0; i < nsteps; ++i) BHIP_TRY(b, hipGraphLaunch(b->graphs[0].exec, s));
+        BHIP_TRY(b, replay_steps(b->graphs[0], nsteps, s));
         return GPWENO_OK;
     }
     BHIP_TRY(b, hipEventRecord(b->group_fork, s));
@@ -1142,7 +1166,7 @@ int batch_launch_steps(gpweno_batch* b, int nsteps, hipStream_t s) {
     for (size_t gi = 0; gi < ng; ++gi) {
         hipStream_t gs = b->group_stream[gi];
         hipError_t e = hipStreamWaitEvent(gs, b->group_fork, 0);
-        for (int i = 0; e == hipSuccess && i < nsteps; ++i) e = hipGraphLaunch(b->graphs[gi].exec, gs);
+        if (e == hipSuccess) e = replay_steps(b->graphs[gi], nsteps, gs);
         // joined back even after a failure, so that s orders everything after it
         hipError_t e1 = hipEventRecord(b->group_join[gi], gs);
         if (e1 == hipSuccess) e1 = hipStreamWaitEvent(s, b->group_join[gi], 0);
