@@ -362,8 +362,9 @@ int gpweno_batch_create(gpweno_batch **out);
 int gpweno_batch_set(gpweno_batch *b, gpweno_ctx *const *ctxs, int n, void *stream);
 
 /* Enqueues nsteps batched steps (nsteps >= 1) on stream by replaying captured
- * graphs of one batched step, one graph per kind of problem (captured on first
- * use, and again only when the kinds of problems in the set change). With
+ * graphs of eight batched steps and of one (nsteps / 8 and nsteps % 8 times),
+ * per kind of problem (captured on first use, and again only when the kinds of
+ * problems in the set change). With
  * several kinds, each kind's graphs are replayed on a stream of the batch's
  * own that waits for stream first and that stream then waits for, so kinds
  * (which share no data) may run side by side while everything stays ordered
