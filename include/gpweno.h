@@ -364,11 +364,10 @@ int gpweno_batch_set(gpweno_batch *b, gpweno_ctx *const *ctxs, int n, void *stre
 /* Enqueues nsteps batched steps (nsteps >= 1) on stream by replaying captured
  * graphs of eight batched steps and of one (nsteps / 8 and nsteps % 8 times),
  * per kind of problem (captured on first use, and again only when the kinds of
- * problems in the set change). With
- * several kinds, each kind's graphs are replayed on a stream of the batch's
- * own that waits for stream first and that stream then waits for, so kinds
- * (which share no data) may run side by side while everything stays ordered
- * on stream. Every launch has one block per logical block of its group; after
+ * problems in the set change). With several kinds, each kind's graphs are
+ * replayed on a stream of the batch's own that waits for stream first and that
+ * stream then waits for, so kinds (which share no data) may run side by side
+ * while everything stays ordered on stream. Every launch has one block per logical block of its group; after
  * a set change of the same kinds the grids of the captured launches are
  * updated in place on the instantiated graphs before the next replay.
  * Errors: EINVAL, EHIP. */
