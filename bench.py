@@ -402,6 +402,21 @@ def time_workload(name, W, grid, U0, steps, warmup, kernel_reps):
     return solvers, timing, kern
 
 
+def limiter(valu_busy, hbm_frac):
+    """What the counters say bounds a sweep: VALU issue when the VALUs issue at
+    least 3/4 of the kernel's time, HBM when the counted traffic runs at 60 %
+    of the peak or more, else latency (the kernel's start, waiting for the
+    first tiles, and its end, the last stores, are not covered by computation:
+    on a small grid every wave of a launch is resident at once)."""
+    if valu_busy is None:
+        return None
+    if valu_busy >= 0.75:
+        return f"VALU issue (busy {valu_busy:.2f})"
+    if hbm_frac is not None and hbm_frac >= 0.6:
+        return f"HBM ({hbm_frac:.2f} of peak)"
+    return f"latency: launch ramp and drain (VALU busy {valu_busy:.2f}, HBM {hbm_frac or 0:.2f} of peak)"
+
+
 def roofline_of(W, grid, timing, kern, steps, prec, entries, sha):
     """Roofline of the dominant kernel (largest time per step) of one precision,
     and every sweep's rates."""
@@ -424,6 +439,7 @@ def roofline_of(W, grid, timing, kern, steps, prec, entries, sha):
                     "hbm_gbs": traffic / t / 1e9 if traffic else None,
                     "hbm_frac": traffic / t / 1e9 / PEAK_HBM_GBS if traffic else None,
                     "valu_busy": c.get("valu_busy")}
+        per[sym]["limited_by"] = limiter(per[sym]["valu_busy"], per[sym]["hbm_frac"])
     p = per[dom]
     step_s = timing[prec] / steps
     alg_bytes = algorithmic_bytes_per_step(ndim, ncell)
@@ -434,6 +450,7 @@ def roofline_of(W, grid, timing, kern, steps, prec, entries, sha):
             "flops_per_cell_dir_evaluated_form": flops_per_cell_dir_evaluated(ndim, R, prec == "fp64"),
             "frac_of_unpacked_peak": p["frac_of_unpacked_peak"], "peak_unpacked": PEAK_TFLOPS_UNPACKED,
             "valu_busy": p["valu_busy"], "hbm_gbs": p["hbm_gbs"], "hbm_frac": p["hbm_frac"],
+            "limited_by": p["limited_by"],
             "algorithmic_bytes_per_step": alg_bytes,
             "algorithmic_hbm_gbs": alg_bytes / step_s / 1e9,
             "algorithmic_hbm_frac": alg_bytes / step_s / 1e9 / PEAK_HBM_GBS,

@@ -111,3 +111,12 @@ def test_committed_flop_ratios_are_per_lane():
         assert set(vals) == {"hw_flops_per_lane_instr", "alg_flops_per_lane_instr"}, tag
         for v in vals.values():
             assert all(0.5 < x < 2.0 for x in v), (tag, v)
+
+
+def test_limiter_reads_the_counters():
+    """The 512^2 y sweep (VALU busy 0.50, 25 % of HBM) is latency-bound; the
+    large-grid sweeps (0.78-0.93) are VALU-issue bound."""
+    assert bench.limiter(0.50, 0.25).startswith("latency")
+    assert bench.limiter(0.93, 0.51).startswith("VALU")
+    assert bench.limiter(0.40, 0.70).startswith("HBM")
+    assert bench.limiter(None, None) is None
