@@ -405,16 +405,16 @@ def time_workload(name, W, grid, U0, steps, warmup, kernel_reps):
 def limiter(valu_busy, hbm_frac):
     """What the counters say bounds a sweep: VALU issue when the VALUs issue at
     least 3/4 of the kernel's time, HBM when the counted traffic runs at 60 %
-    of the peak or more, else latency (the kernel's start, waiting for the
-    first tiles, and its end, the last stores, are not covered by computation:
-    on a small grid every wave of a launch is resident at once)."""
+    of the peak or more, else latency (waits that computation does not cover:
+    on a small grid, where every wave of a launch is resident at once, the
+    launch's start and end)."""
     if valu_busy is None:
         return None
     if valu_busy >= 0.75:
         return f"VALU issue (busy {valu_busy:.2f})"
     if hbm_frac is not None and hbm_frac >= 0.6:
         return f"HBM ({hbm_frac:.2f} of peak)"
-    return f"latency: launch ramp and drain (VALU busy {valu_busy:.2f}, HBM {hbm_frac or 0:.2f} of peak)"
+    return f"latency (VALU busy {valu_busy:.2f}, HBM {hbm_frac or 0:.2f} of peak)"
 
 
 def roofline_of(W, grid, timing, kern, steps, prec, entries, sha):
