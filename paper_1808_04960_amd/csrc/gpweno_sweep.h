@@ -729,14 +729,17 @@ __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long 
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         const double L = a.first ? d[k] : pd[k] + d[k];
-        const double adv = pu[k] + dt * L;
-        double out;
-        if (a.stage == 1) out = adv;
-        else if (a.stage == 2) out = 0.75 * pn[k] + 0.25 * adv;
-        else out = (1.0 / 3.0) * pn[k] + (2.0 / 3.0) * adv;
-        put<NT>(&a.Uout[k * nc + cell], out);
-        o[k] = out;
+        o[k] = fma(dt, L, pu[k]);  // the stage input advanced by dt L
     }
+    // Shu-Osher weights of stages 2 and 3 (3/4 U^n + 1/4 adv, 1/3 U^n + 2/3 adv),
+    // one uniform branch for all components
+    if (a.stage != 1) {
+        const double cn = a.stage == 2 ? 0.75 : 1.0 / 3.0, cu = a.stage == 2 ? 0.25 : 2.0 / 3.0;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) o[k] = fma(cn, pn[k], cu * o[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) put<NT>(&a.Uout[k * nc + cell], o[k]);
     bool ok;
     const double s = cell_speed<NDIM>(o, a.gamma, a.inv_dx_all, ok, a.stage == 3);
     if (!ok) {
@@ -930,11 +933,15 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     }
 
     // ---- epilogue operands: requested now, they arrive while the sweep computes
+    // (each uniform condition tested once, outside the loops over components)
     if (!LATE && ecell >= 0) {
+        if (!a.first) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            if (!a.first) pd[k] = a.dU[k * nc + ecell];
-            if (FIN && a.stage >= 2) pn[k] = a.Un[k * nc + ecell];
+            for (int k = 0; k < NV; ++k) pd[k] = a.dU[k * nc + ecell];
+        }
+        if (FIN && a.stage >= 2) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) pn[k] = a.Un[k * nc + ecell];
         }
     }
 
@@ -948,11 +955,17 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
         Real qp[NV], qm[NV];
         reconstruct<NDIM, R, Real, IK>(sV + w * PITCH, FS, lane, a.tab, g, a.positivity, qp, qm);
         if (LATE && ecell >= 0) {
+            if (!a.first) {
 #pragma unroll
-            for (int k = 0; k < NV; ++k) {
-                if (!a.first) pd[k] = a.dU[k * nc + ecell];
-                if (FIN && a.stage >= 2) pn[k] = a.Un[k * nc + ecell];
-                if (FIN) pu[k] = a.U[k * nc + ecell];
+                for (int k = 0; k < NV; ++k) pd[k] = a.dU[k * nc + ecell];
+            }
+            if (FIN && a.stage >= 2) {
+#pragma unroll
+                for (int k = 0; k < NV; ++k) pn[k] = a.Un[k * nc + ecell];
+            }
+            if (FIN) {
+#pragma unroll
+                for (int k = 0; k < NV; ++k) pu[k] = a.U[k * nc + ecell];
             }
         }
         Real qR[NV], F[NV];
