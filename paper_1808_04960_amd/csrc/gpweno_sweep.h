@@ -75,8 +75,8 @@ __host__ __device__ constexpr int cons_slot(int k) {
 // than the IEEE division and square-root sequences. Arguments are positive and
 // normal wherever these are used on a selected value.
 template <typename Real> __device__ __forceinline__ Real frcp(Real x);
-template <> inline __device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> inline __device__ __forceinline__ double frcp<double>(double x) {
+template <> __device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ __forceinline__ double frcp<double>(double x) {
     double r = __builtin_amdgcn_rcp(x);
     double e = fma(-x, r, 1.0);
     r = fma(r, e, r);
@@ -84,8 +84,8 @@ template <> inline __device__ __forceinline__ double frcp<double>(double x) {
     return fma(r, e, r);
 }
 template <typename Real> __device__ __forceinline__ Real frsq(Real x);
-template <> inline __device__ __forceinline__ float frsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
-template <> inline __device__ __forceinline__ double frsq<double>(double x) {
+template <> __device__ __forceinline__ float frsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ __forceinline__ double frsq<double>(double x) {
     double y = __builtin_amdgcn_rsq(x);
     double e = fma(-x * y, y, 1.0);
     y = fma(0.5 * y, e, y);
@@ -99,19 +99,19 @@ template <> inline __device__ __forceinline__ double frsq<double>(double x) {
 // result is never used: a run's outputs come from lanes NC+1 .. 62-NC). One VALU move,
 // which the compiler can fold into the consuming instruction, instead of a
 // permute through the LDS crossbar.
-inline __device__ __forceinline__ float lane_prev(float x) {
+__device__ __forceinline__ float lane_prev(float x) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xF, 0xF, true));
 }
-inline __device__ __forceinline__ float lane_next(float x) {
+__device__ __forceinline__ float lane_next(float x) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xF, 0xF, true));
 }
-inline __device__ __forceinline__ double lane_prev(double x) {
+__device__ __forceinline__ double lane_prev(double x) {
     const long long b = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x138, 0xF, 0xF, true);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xF, 0xF, true);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
-inline __device__ __forceinline__ double lane_next(double x) {
+__device__ __forceinline__ double lane_next(double x) {
     const long long b = __double_as_longlong(x);
     const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), 0x130, 0xF, 0xF, true);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xF, 0xF, true);
@@ -120,7 +120,7 @@ inline __device__ __forceinline__ double lane_next(double x) {
 
 // Periodic index. For n >= 64 every index a sweep forms lies in [-n, 2n), so a
 // compare-and-add suffices; shorter axes (tests) take the general modulo.
-inline __device__ __forceinline__ int wrap(int x, int n) {
+__device__ __forceinline__ int wrap(int x, int n) {
     if (n >= WAVE) {
         x += (x < 0) ? n : 0;
         return x - ((x >= n) ? n : 0);
@@ -134,7 +134,7 @@ inline __device__ __forceinline__ int wrap(int x, int n) {
 // whether the normal momentum changes sign (mirror image at a wall). Positions
 // beyond the ghost depth (unused lanes of a pencil's last run) are clamped into
 // the axis so every load stays in bounds.
-inline __device__ __forceinline__ int ghost_src(int x, int n, int lo, int hi, bool& flip) {
+__device__ __forceinline__ int ghost_src(int x, int n, int lo, int hi, bool& flip) {
     flip = false;
     if (x >= 0 && x < n) return x;
     const int kind = x < 0 ? lo : hi;
@@ -635,7 +635,7 @@ struct SweepCfg {
     static constexpr size_t SMEM = IN_BYTES > OUT_BYTES ? IN_BYTES : OUT_BYTES;
 };
 
-inline __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         unsigned long long w = __shfl_xor(v, o);
@@ -659,7 +659,7 @@ __device__ __forceinline__ double dpp_f64(double x, double old) {
 // by 1, 2, 4, 8 (out-of-row sources read 0, the identity here) leave each row's
 // max in its lane 15; row_bcast:15 and row_bcast:31 carry those across rows into
 // lane 63. Registers only, no LDS round trips.
-inline __device__ __forceinline__ double wave_max_nonneg(double v) {
+__device__ __forceinline__ double wave_max_nonneg(double v) {
     v = fmax(v, dpp_f64<0x111, 0xF, true>(v, v));  // row_shr:1
     v = fmax(v, dpp_f64<0x112, 0xF, true>(v, v));  // row_shr:2
     v = fmax(v, dpp_f64<0x114, 0xF, true>(v, v));  // row_shr:4
@@ -670,16 +670,6 @@ inline __device__ __forceinline__ double wave_max_nonneg(double v) {
     const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
     const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-
-// Store of a sweep output. x sweeps write whole rows with non-temporal
-// stores: the rows bypass L2, so the writeback of dirty lines at the end of
-// the kernel has nothing left to do (on a 512^2 grid that writeback held each
-// launch up by about 2 us). y/z sweeps write partial lines and keep L2.
-template <bool NT>
-__device__ __forceinline__ void put(double* p, double v) {
-    if constexpr (NT) __builtin_nontemporal_store(v, p);
-    else *p = v;
 }
 
 // Physical check and CFL speed sum_d (|u_d| + c)/dx_d of one cell's conserved
@@ -714,7 +704,7 @@ __device__ __forceinline__ double cell_speed(const double (&o)[2 + NDIM], double
 // dU. FIN = true (last direction of an RK stage): form the stage output
 // (SSP-RK3, Shu-Osher form), check it is physical and, in stage 3, track the
 // CFL speed of the new state.
-template <int NDIM, bool FIN, typename Real, bool NT>
+template <int NDIM, bool FIN, typename Real>
 __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long cell, const double (&d)[2 + NDIM],
                                             const double (&pd)[2 + NDIM], const double (&pu)[2 + NDIM],
                                             const double (&pn)[2 + NDIM], double dt, double& spd) {
@@ -722,7 +712,7 @@ __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long 
     const long long nc = a.ncell;
     if (!FIN) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) put<NT>(&a.dU[k * nc + cell], a.first ? d[k] : pd[k] + d[k]);
+        for (int k = 0; k < NV; ++k) a.dU[k * nc + cell] = a.first ? d[k] : pd[k] + d[k];
         return;
     }
     double o[NV];
@@ -739,7 +729,7 @@ __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long 
         for (int k = 0; k < NV; ++k) o[k] = fma(cn, pn[k], cu * o[k]);
     }
 #pragma unroll
-    for (int k = 0; k < NV; ++k) put<NT>(&a.Uout[k * nc + cell], o[k]);
+    for (int k = 0; k < NV; ++k) a.Uout[k * nc + cell] = o[k];
     bool ok;
     const double s = cell_speed<NDIM>(o, a.gamma, a.inv_dx_all, ok, a.stage == 3);
     if (!ok) {
@@ -755,7 +745,7 @@ __device__ __forceinline__ void finish_cell(const SweepArgs<Real>& a, long long 
 // runs along y / z for y / z sweeps), so an XCD keeps working on roughly the
 // same slab of the grid in every sweep, and the slab's stage states and
 // accumulator stay in that XCD's L2 between kernels.
-inline __device__ __forceinline__ long long xcd_logical_block() {
+__device__ __forceinline__ long long xcd_logical_block() {
     const unsigned nb = gridDim.x, b = blockIdx.x;
     const unsigned q8 = nb >> 3, r8 = nb & 7u, xcd = b & 7u;
     return (long long)(xcd * q8 + (xcd < r8 ? xcd : r8) + (b >> 3));
@@ -1003,7 +993,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
     double spd = 0.0;  // this lane's CFL speed (stage 3 of a finishing sweep)
     const bool lane_out = lane >= LEFT && lane < LEFT + tseg;
     if (DIR == 0) {
-        if (ecell >= 0) finish_cell<NDIM, FIN, Real, true>(a, ecell, dcons, pd, pu, pn, dt, spd);
+        if (ecell >= 0) finish_cell<NDIM, FIN, Real>(a, ecell, dcons, pd, pu, pn, dt, spd);
     } else {
         __syncthreads();  // every wave is done reading the stencil tile
         if (lane_out) {
@@ -1016,7 +1006,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<Real>& a, const long
             double d[NV];
 #pragma unroll
             for (int k = 0; k < NV; ++k) d[k] = sO[(k * TOUT + row) * C::OPITCH + c];
-            finish_cell<NDIM, FIN, Real, false>(a, ecell, d, pd, pu, pn, dt, spd);
+            finish_cell<NDIM, FIN, Real>(a, ecell, d, pd, pu, pn, dt, spd);
         }
     }
     if (FIN && a.stage == 3) {
