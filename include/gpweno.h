@@ -149,8 +149,11 @@ int gpweno_init(const gpweno_grid *grid, int R, double ell, double sigma, double
 int gpweno_init_scheme(const gpweno_grid *grid, int scheme, int R, double ell, double sigma,
                        double gamma, gpweno_ctx **out);
 
-/* Options (host pointer, copied). Changing the precision or positivity flag
- * drops any captured graph. Errors: EINVAL. */
+/* Options (host pointer, copied). Changing the precision, the positivity
+ * flag, the non-zero-mean flag, the correction terms or the stream drops any
+ * captured graph, after waiting for the context's current stream (blocking:
+ * graph launches may still be in flight there, and work on a new stream comes
+ * after them). Errors: EINVAL, EHIP. */
 int gpweno_set_options(gpweno_ctx *ctx, const gpweno_options *opt);
 int gpweno_get_options(const gpweno_ctx *ctx, gpweno_options *opt);
 
@@ -385,7 +388,8 @@ int gpweno_batch_status(gpweno_batch *b, double *t, double *dt, long *nsteps, in
  * the set through the work tables, and their grids are updated in place. */
 long gpweno_batch_captures(const gpweno_batch *b);
 
-/* Waits for the batch's last stream (and its per-kind streams) and frees its
+/* Waits for the stream of the batch's last set or run (the default stream
+ * too, when that was the one) and for its per-kind streams, and frees its
  * resources. NULL is ignored. */
 void gpweno_batch_destroy(gpweno_batch *b);
 
@@ -398,7 +402,7 @@ const char *gpweno_batch_last_error(const gpweno_batch *b);
 const char *gpweno_last_error(const gpweno_ctx *ctx);
 
 /* Releases the context's own resources (not the caller's buffers). Synchronises
- * the context's stream first. NULL is ignored. */
+ * the context's stream first (NULL: the default stream). NULL is ignored. */
 void gpweno_destroy(gpweno_ctx *ctx);
 
 #ifdef __cplusplus

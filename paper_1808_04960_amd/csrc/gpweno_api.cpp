@@ -566,8 +566,13 @@ int gpweno_set_options(gpweno_ctx* c, const gpweno_options* o) {
                                (o->nonzero_mean != 0) != (c->opt.nonzero_mean != 0) ||
                                o->flux_corr_terms != c->opt.flux_corr_terms;
     const bool changes_rule = o->cfl != c->opt.cfl || o->fixed_dt != c->opt.fixed_dt;
+    if (changes_graph) {
+        // launches of the graphs may still be in flight on the current stream,
+        // and work on a new stream must come after them
+        HIP_TRY(c, hipStreamSynchronize(user_stream(c)));
+        drop_graph(c);
+    }
     c->opt = *o;
-    if (changes_graph) drop_graph(c);
     if (changes_rule && c->state) {
         // the CFL number and fixed dt live in the control block
         if (read_ctl(c, user_stream(c))) return GPWENO_EHIP;
@@ -852,7 +857,7 @@ const char* gpweno_last_error(const gpweno_ctx* c) { return c ? c->err.c_str() :
 
 void gpweno_destroy(gpweno_ctx* c) {
     if (!c) return;
-    if (c->opt.stream) (void)hipStreamSynchronize(user_stream(c));
+    (void)hipStreamSynchronize(user_stream(c));  // NULL: the default stream
     if (c->own_stream) (void)hipStreamSynchronize(c->own_stream);
     drop_graph(c);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -926,7 +931,10 @@ size_t align_up(size_t b) { return (b + 255) & ~size_t(255); }
 struct gpweno_batch {
     int device = 0;
     hipStream_t own_stream = nullptr;
+    // the stream of the last set or run; a flag of its own, since the default
+    // stream's handle is NULL
     hipStream_t last_stream = nullptr;
+    bool last_used = false;
     std::vector<gpweno_ctx*> set;
     std::vector<BatchGroup> groups;
     // device work tables: per group and step position a BatchDir (fixed
@@ -1115,7 +1123,7 @@ int batch_capture(gpweno_batch* b) {
     // the old graphs may still be running (on the stream they were last
     // launched on, which waited for the group streams); an executable graph is
     // destroyed only once no launch of it is in flight
-    if (!b->graphs.empty() && b->last_stream) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
+    if (!b->graphs.empty() && b->last_used) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
     batch_drop_graph(b);
     const size_t ng = b->groups.size();
     if (ng > 1) {
@@ -1244,7 +1252,7 @@ int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stre
     hipStream_t s = static_cast<hipStream_t>(stream);
     // work already enqueued on another stream must finish before this one
     // rewrites the tables it reads
-    if (b->last_stream && b->last_stream != s) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
+    if (b->last_used && b->last_stream != s) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
     // groups, in the order their kinds first appear; kinds the captured graph
     // already has keep their place so that the graph keeps serving the set
     std::vector<BatchGroup> groups;
@@ -1384,6 +1392,7 @@ int gpweno_batch_set(gpweno_batch* b, gpweno_ctx* const* ctxs, int n, void* stre
     b->set.assign(ctxs, ctxs + n);
     b->groups = std::move(groups);
     b->last_stream = s;
+    b->last_used = true;
     b->dirty = true;
     return GPWENO_OK;
 }
@@ -1393,7 +1402,7 @@ int gpweno_batch_run(gpweno_batch* b, int nsteps, void* stream) {
     if (nsteps < 1) return bfail(b, GPWENO_EINVAL, "nsteps must be >= 1");
     if (b->set.empty()) return GPWENO_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (b->last_stream && b->last_stream != s) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
+    if (b->last_used && b->last_stream != s) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
     if (graph_serves(b) && (!b->dirty || b->nodes_ok)) {
         if (b->dirty) {
             int st = batch_update_grids(b);
@@ -1419,6 +1428,7 @@ int gpweno_batch_run(gpweno_batch* b, int nsteps, void* stream) {
     b->dirty = false;
     int st = batch_launch_steps(b, nsteps, s);
     b->last_stream = s;
+    b->last_used = true;
     if (st) return st;
     return GPWENO_OK;
 }
@@ -1445,7 +1455,7 @@ long gpweno_batch_captures(const gpweno_batch* b) { return b ? (long)b->recaptur
 
 void gpweno_batch_destroy(gpweno_batch* b) {
     if (!b) return;
-    if (b->last_stream) (void)hipStreamSynchronize(b->last_stream);
+    if (b->last_used) (void)hipStreamSynchronize(b->last_stream);
     if (b->own_stream) (void)hipStreamSynchronize(b->own_stream);
     for (int i = 0; i < BATCH_MAX_GROUPS; ++i)
         if (b->group_stream[i]) (void)hipStreamSynchronize(b->group_stream[i]);

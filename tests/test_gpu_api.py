@@ -2,7 +2,8 @@
 context reports, the time step a blocking step returns, runs of any step count
 composed from graph replays, resuming from a saved state, the non-physical-state
 test hook (alone and inside a batch), batches of problems with non-square
-cells, and the three-term flux correction against the oracle.
+cells, the three-term flux correction against the oracle, and runs on the
+default stream.
 
 Parity bars as in test_gpu_parity: 1e-12 (float64) and 1e-5 (float32) relative
 L1 for states, 16 eps times the flux scale for one right-hand side.
@@ -385,3 +386,71 @@ def test_three_term_batch_is_bitwise_single():
     ref2.run(1e30, max_steps=7)
     assert np.array_equal(s2.get_state(), ref2.get_state())
     b.close()
+
+
+# ---------------------------------------------------------------------------
+# The default stream, whose handle is NULL
+# ---------------------------------------------------------------------------
+def test_default_stream_runs_are_bitwise_the_own_stream_runs():
+    """A solver, and a batch of two kinds (so the per-kind streams are used),
+    run on the default stream, then move to another stream (new options for
+    the solver, a set on the new stream for the batch) and run on; a second
+    batch is destroyed right after enqueueing on the default stream. Every
+    result is bitwise the same problem's run on a stream of its own."""
+    announce("default stream")
+    dflt = torch.cuda.default_stream()
+    other = torch.cuda.Stream()
+    assert dflt.cuda_stream == 0
+
+    def ref_state(g, U, prec, n):
+        dx = g.dx[0]
+        r = gw.Solver(g, 2, 12 * dx, 3 * dx, precision=prec, U0=U)
+        r.run(1e30, max_steps=n)
+        out = r.get_state()
+        r.close()
+        return out
+
+    (g, U) = inputs.isentropic_vortex_2d(48)
+    dx = g.dx[0]
+    s = gw.Solver(g, 2, 12 * dx, 3 * dx, precision="fp32", U0=U, stream=dflt)
+    assert s.run(1e30, max_steps=5)[0] == 5
+    s.stream = other
+    s.set_options("fp32")
+    assert s.run(1e30, max_steps=4)[0] == 4
+    assert np.array_equal(s.get_state(), ref_state(g, U, "fp32", 9))
+    s.close()
+
+    probs = [(inputs.isentropic_vortex_2d(48), "fp32"), (inputs.isentropic_vortex_2d(64), "fp64"),
+             (inputs.isentropic_vortex_2d(40), "fp32")]
+    solvers = []
+    for (g, U), prec in probs:
+        dx = g.dx[0]
+        sv = gw.Solver(g, 2, 12 * dx, 3 * dx, precision=prec, U0=U, stream=dflt)
+        sv.set_end(1e30, 10)
+        solvers.append(sv)
+    b = gw.Batch(dflt)
+    b.set(solvers)
+    b.run(3)
+    b.stream = other
+    for sv, (_, prec) in zip(solvers, probs):
+        sv.stream = other
+        sv.set_options(prec)
+    b.set(solvers)
+    b.run(7)
+    _, _, ns, err = b.status()
+    assert list(ns) == [10] * 3 and not err.any()
+    for sv, ((g, U), prec) in zip(solvers, probs):
+        assert np.array_equal(sv.get_state(), ref_state(g, U, prec, 10))
+    b.close()
+
+    (g, U), prec = probs[1]
+    dx = g.dx[0]
+    sv = gw.Solver(g, 2, 12 * dx, 3 * dx, precision=prec, U0=U, stream=dflt)
+    sv.set_end(1e30, 6)
+    b2 = gw.Batch(dflt)
+    b2.set([sv])
+    b2.run(6)
+    b2.close()
+    assert np.array_equal(sv.get_state(), ref_state(g, U, prec, 6))
+    for x in solvers + [sv]:
+        x.close()
