@@ -151,9 +151,9 @@ int gpweno_init_scheme(const gpweno_grid *grid, int scheme, int R, double ell, d
 
 /* Options (host pointer, copied). Changing the precision, the positivity
  * flag, the non-zero-mean flag, the correction terms or the stream drops any
- * captured graph, after waiting for the context's current stream (blocking:
- * graph launches may still be in flight there, and work on a new stream comes
- * after them). Errors: EINVAL, EHIP. */
+ * captured graph; a context with a bound state or captured graphs first waits
+ * for its current stream (blocking: graph launches may still be in flight
+ * there, and work on a new stream comes after them). Errors: EINVAL, EHIP. */
 int gpweno_set_options(gpweno_ctx *ctx, const gpweno_options *opt);
 int gpweno_get_options(const gpweno_ctx *ctx, gpweno_options *opt);
 
@@ -169,7 +169,9 @@ size_t gpweno_workspace_bytes(const gpweno_ctx *ctx);
  * stay owned by the caller and must outlive the binding. Resets t and the step
  * count to 0, and enqueues the CFL speed reduction of the current state (so the
  * state must hold valid data before the first step; call gpweno_set_time after
- * changing it). Errors: EINVAL for NULL or misaligned pointers. */
+ * changing it). Rebinding a context whose captured graphs may still run waits
+ * for its stream first and drops them. Errors: EINVAL for NULL or misaligned
+ * pointers, EHIP. */
 int gpweno_bind(gpweno_ctx *ctx, double *d_state, void *d_workspace);
 
 /* Sets the simulation time and step count, and recomputes the CFL speed of the

@@ -182,6 +182,12 @@ void drop_graph(gpweno_ctx* c) {
     }
 }
 
+bool has_graph(const gpweno_ctx* c) {
+    for (auto g : c->graph)
+        if (g) return true;
+    return false;
+}
+
 // Terms of the flux correction, and the cells a 64-lane run produces with them.
 int corr_terms(const gpweno_ctx* c) { return c->opt.flux_corr_terms; }
 int run_cells(const gpweno_ctx* c) { return gpw::run_out(corr_terms(c)); }
@@ -567,9 +573,10 @@ int gpweno_set_options(gpweno_ctx* c, const gpweno_options* o) {
                                o->flux_corr_terms != c->opt.flux_corr_terms;
     const bool changes_rule = o->cfl != c->opt.cfl || o->fixed_dt != c->opt.fixed_dt;
     if (changes_graph) {
-        // launches of the graphs may still be in flight on the current stream,
-        // and work on a new stream must come after them
-        HIP_TRY(c, hipStreamSynchronize(user_stream(c)));
+        // launches of the graphs, or other work on the bound state, may still be
+        // in flight on the current stream, and work on a new stream must come
+        // after them (a context with neither has nothing to wait for)
+        if (c->state || has_graph(c)) HIP_TRY(c, hipStreamSynchronize(user_stream(c)));
         drop_graph(c);
     }
     c->opt = *o;
@@ -623,6 +630,8 @@ int gpweno_bind(gpweno_ctx* c, double* d_state, void* d_workspace) {
     if (!d_state || !d_workspace) return fail(c, GPWENO_EINVAL, "NULL state or workspace");
     if (((uintptr_t)d_state & 7) || ((uintptr_t)d_workspace & 255))
         return fail(c, GPWENO_EINVAL, "state must be 8-byte and workspace 256-byte aligned");
+    // the graphs (which hold the old buffers' addresses) may still be running
+    if (has_graph(c)) HIP_TRY(c, hipStreamSynchronize(user_stream(c)));
     drop_graph(c);
     const size_t st = align256(sizeof(double) * (size_t)c->nv * (size_t)c->ncell);
     char* w = static_cast<char*>(d_workspace);
