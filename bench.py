@@ -319,16 +319,17 @@ def kernel_symbol(ndim, d, R, real, fin, bcg=False):
 KERNEL_TIMING_HOLD_S = 0.05   # stream hold while the host enqueues the kernel-timing phase
 
 
-def time_workload(name, W, grid, U0, steps, warmup, kernel_reps):
+def time_workload(name, W, grid, U0, steps, warmup, kernel_reps, kernel_phase_s=0.0):
     """Per precision: every launch of the step sequence timed back to back with
     HIP events on the solver's stream, then the warm-up and the timed
     graph-replayed steps. The kernel timing comes first (after one step that
-    captures the step graphs): it keeps the GPU busy for some tens of
-    milliseconds right before the timed window, so that the window runs at the
-    clocks of a continuous run. Started after the GPU idled (or ran only light
-    work), a window of 20 steps of the 512^2 vortex runs 6-20 % slower per step
-    than in a long run (59.5-65 against 56 us). The timed window is exactly
-    `steps` steps either way.
+    captures the step graphs): a pass of kernel_reps repeats per launch, then,
+    if that pass took less than kernel_phase_s, a second pass with the repeats
+    scaled up to fill it, whose times are the ones reported. The GPU's clocks
+    follow its load: a pass of a few milliseconds times the 512^2 sweeps about
+    5 % slow (9.03 against 8.6 us), and a 20-step window right after it runs
+    56.7-57.2 us per step against 55.0 after a 0.2 s phase (53 us in a long
+    run). The timed window is exactly `steps` steps either way.
     Returns (solvers, wall seconds per precision, per-kernel (mean us, launches per step))."""
     import torch
 
@@ -356,32 +357,45 @@ def time_workload(name, W, grid, U0, steps, warmup, kernel_reps):
         # launches of small grids are no longer back to back: compare profiled
         # kernel durations, not profiled event times.)
         real = "float" if prec == "fp32" else "double"
-        with torch.cuda.stream(s.stream):
-            torch.cuda._sleep(int(2.4e9 * KERNEL_TIMING_HOLD_S))
-        t_enq = time.perf_counter()
-        marks = []
-        for k in range(nk):
-            s.set_state(U0_dev)
-            s.step(t_run)  # sets the end time and lifts the step limit
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(s.stream)
-            for _ in range(kernel_reps):
-                s.step_kernel(k)
-            e1.record(s.stream)
-            marks.append((k, e0, e1))
-        t_enq = time.perf_counter() - t_enq
-        s.synchronize()
-        if t_enq > KERNEL_TIMING_HOLD_S:
-            # either the host waited for queue space (the queue stayed full: no
-            # gaps) or it enqueued slower than the GPU ran (gaps, then timed too)
-            log(f"note: enqueueing the kernel timing took {t_enq * 1e3:.0f} ms, more than the "
-                f"{KERNEL_TIMING_HOLD_S * 1e3:.0f} ms hold")
+
+        def kernel_pass(reps):
+            with torch.cuda.stream(s.stream):
+                torch.cuda._sleep(int(2.4e9 * KERNEL_TIMING_HOLD_S))
+            t_enq = time.perf_counter()
+            marks = []
+            for k in range(nk):
+                s.set_state(U0_dev)
+                s.step(t_run)  # sets the end time and lifts the step limit
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(s.stream)
+                for _ in range(reps):
+                    s.step_kernel(k)
+                e1.record(s.stream)
+                marks.append((k, e0, e1))
+            t_enq = time.perf_counter() - t_enq
+            s.synchronize()
+            if t_enq > KERNEL_TIMING_HOLD_S:
+                # either the host waited for queue space (the queue stayed full:
+                # no gaps) or it enqueued slower than the GPU ran (gaps, then
+                # timed too)
+                log(f"note: enqueueing the kernel timing took {t_enq * 1e3:.0f} ms, more than the "
+                    f"{KERNEL_TIMING_HOLD_S * 1e3:.0f} ms hold")
+            return marks
+
+        reps = kernel_reps
+        marks = kernel_pass(reps)
+        span = sum(e0.elapsed_time(e1) for _, e0, e1 in marks) * 1e-3
+        if span < kernel_phase_s:
+            reps = int(math.ceil(reps * kernel_phase_s / max(span, 1e-6)))
+            marks = kernel_pass(reps)
+            log(f"  kernel timing: {reps} repeats per launch (the {kernel_reps}-repeat pass took "
+                f"{span * 1e3:.1f} ms)")
         per_sym = {}
         for k, e0, e1 in marks:
             d = grid.ndim - 1 - k % grid.ndim   # sweeps of a stage run z, y, x; x finishes it
             sym = kernel_symbol(grid.ndim, d, R, real, d == 0, W.get("bcg", False))
-            per_sym.setdefault(sym, []).append(e0.elapsed_time(e1) / kernel_reps * 1e-3)
+            per_sym.setdefault(sym, []).append(e0.elapsed_time(e1) / reps * 1e-3)
         for sym, ts in per_sym.items():
             kern[(prec, sym)] = (float(np.mean(ts)), len(ts))
             log(f"  {sym}: {np.mean(ts) * 1e6:.2f} us per launch, {len(ts)} per step")
@@ -701,6 +715,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="oracle sample budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=100, help="back-to-back launches per timed kernel")
+    ap.add_argument("--kernel-phase-ms", type=float, default=200.0,
+                    help="minimum length of the kernel-timing phase: a pass of --kernel-reps repeats that takes "
+                         "less is followed by one with the repeats scaled up to this length (0: one pass)")
     ap.add_argument("--serving-requests", type=int, default=200, help="requests of the serving stream (0: skip)")
     ap.add_argument("--no-time-to-error", action="store_true", help="skip the time-to-error study")
     ap.add_argument("--no-extra-workloads", action="store_true", help="only the selected workload")
@@ -711,7 +728,7 @@ def main():
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="write profiles/ summaries from the rocprofv3 passes in DIR (no GPU needed)")
     ap.add_argument("--profile-command", default="--steps 32 --warmup 0 --no-cpu-baseline --solves 0 --kernel-reps 4 "
-                    "--serving-requests 0 --no-time-to-error --no-full-parity --copy-probe",
+                    "--kernel-phase-ms 0 --serving-requests 0 --no-time-to-error --no-full-parity --copy-probe",
                     help="the bench.py arguments the counter runs used (recorded in the summaries)")
     ap.add_argument("--stats-command", default="--gpus 1 --steps 20 --warmup 5 --no-cpu-baseline --solves 0 "
                     "--serving-requests 0 --no-time-to-error --no-full-parity",
@@ -753,7 +770,8 @@ def main():
         args.steps = W["max_steps"] - args.warmup
         log(f"timed run held to {args.warmup} + {args.steps} steps, inside the workload's span")
 
-    solvers, timing, kern = time_workload(args.workload, W, grid, U0, args.steps, args.warmup, args.kernel_reps)
+    solvers, timing, kern = time_workload(args.workload, W, grid, U0, args.steps, args.warmup, args.kernel_reps,
+                                          args.kernel_phase_ms * 1e-3)
 
     if args.copy_probe:
         nbytes = 1 << 30
@@ -794,7 +812,8 @@ def main():
         for name in ("kh2d", "wave3d"):
             Wx = WORKLOADS[name]
             gx, Ux = Wx["make"]()
-            sx, tx, kx = time_workload(name, Wx, gx, Ux, args.steps, args.warmup, args.kernel_reps)
+            sx, tx, kx = time_workload(name, Wx, gx, Ux, args.steps, args.warmup, args.kernel_reps,
+                                       args.kernel_phase_ms * 1e-3)
             rx = roofline_of(Wx, gx, tx, kx, args.steps, "fp32", entries, sha)
             rx["fp64"] = roofline_of(Wx, gx, tx, kx, args.steps, "fp64", entries, sha)
             rx["fp64"].pop("fp64", None)
