@@ -319,6 +319,16 @@ def kernel_symbol(ndim, d, R, real, fin, bcg=False):
 KERNEL_TIMING_HOLD_S = 0.05   # stream hold while the host enqueues the kernel-timing phase
 
 
+def phase_reps(reps, span_s, phase_s):
+    """Repeats per launch of the second kernel-timing pass: the first pass of
+    `reps` repeats took span_s seconds; a pass shorter than phase_s is scaled
+    up to fill it, by at most 1000 times (None: the first pass is long
+    enough)."""
+    if span_s >= phase_s:
+        return None
+    return int(math.ceil(reps * min(1000.0, phase_s / max(span_s, 1e-9))))
+
+
 def time_workload(name, W, grid, U0, steps, warmup, kernel_reps, kernel_phase_s=0.0):
     """Per precision: every launch of the step sequence timed back to back with
     HIP events on the solver's stream, then the warm-up and the timed
@@ -386,8 +396,9 @@ def time_workload(name, W, grid, U0, steps, warmup, kernel_reps, kernel_phase_s=
         reps = kernel_reps
         marks = kernel_pass(reps)
         span = sum(e0.elapsed_time(e1) for _, e0, e1 in marks) * 1e-3
-        if span < kernel_phase_s:
-            reps = int(math.ceil(reps * kernel_phase_s / max(span, 1e-6)))
+        more = phase_reps(reps, span, kernel_phase_s)
+        if more is not None:
+            reps = more
             marks = kernel_pass(reps)
             log(f"  kernel timing: {reps} repeats per launch (the {kernel_reps}-repeat pass took "
                 f"{span * 1e3:.1f} ms)")

@@ -120,3 +120,12 @@ def test_limiter_reads_the_counters():
     assert bench.limiter(0.93, 0.51).startswith("VALU")
     assert bench.limiter(0.40, 0.70).startswith("HBM")
     assert bench.limiter(None, None) is None
+
+
+def test_kernel_timing_phase_scales_short_passes_only():
+    """A first pass shorter than the phase is followed by one scaled to fill
+    it; a long enough pass (or a phase of 0) is used as it is."""
+    assert bench.phase_reps(100, 0.0055, 0.2) == 3637   # 512^2 sweeps: 5.5 ms -> 0.2 s
+    assert bench.phase_reps(100, 0.3, 0.2) is None
+    assert bench.phase_reps(4, 0.001, 0.0) is None
+    assert bench.phase_reps(100, 0.0, 0.2) == 100_000  # scaled by at most 1000
