@@ -6,6 +6,8 @@
 * Through the server, a request's result is bitwise the same alone and in a mix
   of other requests arriving while it runs.
 * Batched results agree with the CPU oracle (1e-12 fp64, 1e-5 fp32).
+* The batch's limits (64 kinds, 4096 problems) hold, and larger sets are
+  refused.
 """
 import sys
 
@@ -266,3 +268,67 @@ def test_batch_mixing_dimensions_precisions_and_sizes_is_bitwise_single():
         ref.run(1e30, max_steps=s.time()[2])
         assert np.array_equal(s.get_state(), ref.get_state()), (g.n, prec, R)
     b.close()
+
+
+def test_batch_limits_64_kinds_and_4096_problems():
+    """The batch's limits. 64 kinds of problems (1D, tables differing in ell,
+    so each kind has its own graphs and stream) and then 4096 problems of one
+    kind run together, each sampled problem bitwise its single-problem result;
+    a 65th kind and a 4097th problem are refused (EINVAL), and the batch keeps
+    serving the set it had."""
+    announce("batch limits: 64 kinds, 4096 problems")
+    stream = torch.cuda.Stream()
+    g, U = inputs.sine_wave_1d(64)
+    _, U2 = inputs.sine_wave_1d(64, amp=0.1)
+    dx = g.dx[0]
+
+    def solo(ell, prec, U0, n):
+        r = gw.Solver(g, 2, ell, 3 * dx, precision=prec, U0=U0)
+        r.run(1e30, max_steps=n)
+        out = r.get_state()
+        r.close()
+        return out
+
+    ells = [(6 + 0.25 * i) * dx for i in range(64)]
+    kinds = []
+    for ell in ells:
+        s = gw.Solver(g, 2, ell, 3 * dx, precision="fp32", U0=U, stream=stream)
+        s.set_end(1e30, 9)
+        kinds.append(s)
+    b = gw.Batch(stream)
+    b.set(kinds)
+    b.run(9)
+    _, _, ns, err = b.status()
+    assert list(ns) == [9] * 64 and not err.any()
+    extra = gw.Solver(g, 2, 40 * dx, 3 * dx, precision="fp32", U0=U, stream=stream)
+    with pytest.raises(gw.GpwenoError) as e:
+        b.set(kinds + [extra])
+    assert e.value.code == gw.EINVAL
+    b.run(2)   # the old set, all at their step limit: nothing moves
+    _, _, ns, err = b.status()
+    assert list(ns) == [9] * 64 and not err.any()
+    for i in (0, 21, 42, 63):
+        assert np.array_equal(kinds[i].get_state(), solo(ells[i], "fp32", U, 9)), i
+    b.close()
+    for s in kinds:
+        s.close()
+
+    many = []
+    for i in range(4096):
+        s = gw.Solver(g, 2, 12 * dx, 3 * dx, precision="fp64", U0=U if i % 2 == 0 else U2, stream=stream)
+        s.set_end(1e30, 5)
+        many.append(s)
+    b = gw.Batch(stream)
+    b.set(many)
+    b.run(5)
+    _, _, ns, err = b.status()
+    assert len(ns) == 4096 and (ns == 5).all() and not err.any()
+    with pytest.raises(gw.GpwenoError) as e:
+        b.set(many + [extra])
+    assert e.value.code == gw.EINVAL
+    ref = {0: solo(12 * dx, "fp64", U, 5), 1: solo(12 * dx, "fp64", U2, 5)}
+    for i in (0, 1, 2047, 2048, 4094, 4095):
+        assert np.array_equal(many[i].get_state(), ref[i % 2]), i
+    b.close()
+    for s in many + [extra]:
+        s.close()
