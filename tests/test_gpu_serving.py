@@ -7,7 +7,7 @@
   of other requests arriving while it runs.
 * Batched results agree with the CPU oracle (1e-12 fp64, 1e-5 fp32).
 * The batch's limits (64 kinds, 4096 problems) hold, and larger sets are
-  refused.
+  refused; an empty batch runs nothing.
 """
 import sys
 
@@ -332,3 +332,33 @@ def test_batch_limits_64_kinds_and_4096_problems():
     b.close()
     for s in many + [extra]:
         s.close()
+
+
+def test_empty_batch_runs_nothing():
+    """A batch with no problems (never set, set empty, or emptied after its
+    graphs were captured) runs nothing and reports nothing; a problem that
+    left it keeps the state it had."""
+    announce("empty batch")
+    stream = torch.cuda.Stream()
+    b = gw.Batch(stream)
+    b.run(3)
+    b.set([])
+    b.run(2)
+    t, dt, ns, err = b.status()
+    assert len(t) == len(dt) == len(ns) == len(err) == 0
+    g, U = inputs.isentropic_vortex_2d(40)
+    dx = g.dx[0]
+    s = gw.Solver(g, 2, 12 * dx, 3 * dx, precision="fp32", U0=U, stream=stream)
+    s.set_end(1e30, 100)
+    b.set([s])
+    b.run(3)
+    b.set([])
+    b.run(4)
+    assert len(b.status()[2]) == 0
+    ref = gw.Solver(g, 2, 12 * dx, 3 * dx, precision="fp32", U0=U)
+    ref.run(1e30, max_steps=3)
+    assert s.time()[2] == 3
+    assert np.array_equal(s.get_state(), ref.get_state())
+    b.close()
+    s.close()
+    ref.close()
