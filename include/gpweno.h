@@ -380,7 +380,9 @@ int gpweno_batch_run(gpweno_batch *b, int nsteps, void *stream);
 
 /* Blocking: for every problem of the set, in set order, its time, last dt, step
  * count and error flag (1: non-physical state) into host arrays of length n
- * (each nullable). Errors: EINVAL, EHIP. */
+ * (each nullable), read on stream after the steps enqueued so far (on another
+ * stream than the last set or run, that stream is waited for first).
+ * Errors: EINVAL, EHIP. */
 int gpweno_batch_status(gpweno_batch *b, double *t, double *dt, long *nsteps, int *err, void *stream);
 
 /* Number of times the batch has captured its step graphs (all kinds' graphs at

@@ -1447,6 +1447,8 @@ int gpweno_batch_status(gpweno_batch* b, double* t, double* dt, long* nsteps, in
     const int n = (int)b->set.size();
     if (n == 0) return GPWENO_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // steps enqueued on another stream must have run before their status is read
+    if (b->last_used && b->last_stream != s) BHIP_TRY(b, hipStreamSynchronize(b->last_stream));
     hipError_t e = gpw::launch_gather_status(b->d_ctls, n, b->d_status, s);
     if (e != hipSuccess) return bfail(b, GPWENO_EHIP, "status launch: %s", hipGetErrorString(e));
     BHIP_TRY(b, hipMemcpyAsync(b->h_status, b->d_status, sizeof(gpw::BatchStatus) * n, hipMemcpyDeviceToHost, s));
