@@ -655,11 +655,12 @@ def summarize_profiles(raw_dir, out_dir, command, stats_command=None, kernel_rep
                      "# baseline, latency solves, serving, time-to-error or full-length oracle runs, whose many\n"
                      "# launches are not timed kernels). It holds fp32 and fp64 solvers: the warm-up and timed\n"
                      "# graph-replayed steps, and the back-to-back launches of every kernel of the step sequence\n"
-                     "# that bench's HIP events time. b2b_us is the mean over those back-to-back launches (what\n"
-                     "# bench's roofline divides by), seq_us the mean inside the replayed steps, where a y sweep\n"
-                     "# follows a finishing sweep. sweep_kernel<ndim, dir, R, Real, finishes-an-RK-stage,\n"
-                     "# indicator kind, general boundaries, flux-correction terms>; the sweeps of a stage run z,\n"
-                     "# y, x and the x sweep finishes it.\n#\n")
+                     "# that bench's HIP events time (its kernel-timing phase: a 100-repeat pass, then one\n"
+                     "# scaled to about 0.2 s, whose times bench reports). b2b_us is the mean over all those\n"
+                     "# back-to-back launches (what bench's roofline divides by), seq_us the mean inside the\n"
+                     "# replayed steps, where a y sweep follows a finishing sweep. sweep_kernel<ndim, dir, R,\n"
+                     "# Real, finishes-an-RK-stage, indicator kind, general boundaries, flux-correction terms>;\n"
+                     "# the sweeps of a stage run z, y, x and the x sweep finishes it.\n#\n")
             fh.write(f"{'kernel':62s} {'calls':>6s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} "
                      f"{'total_ms':>9s} {'b2b_n':>6s} {'b2b_us':>9s} {'seq_n':>6s} {'seq_us':>9s}\n")
             for k in kerns:
